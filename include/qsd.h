@@ -1,0 +1,272 @@
+/*
+ * qsd.h - C-ABI of the MI355X (gfx950) subspace-Hamiltonian library.
+ *
+ * The library evaluates a Hamiltonian written over an extended operator alphabet on a subspace
+ * of computational-basis bit-strings (Nation, Saki, Kang, "A generalized framework for quantum
+ * subspace diagonalization", arXiv 2603.18731):
+ *
+ *   - bit-set subspaces of any width, hashed for lookup        (Methods, Subspace data structure)
+ *   - operators over {Z, 0, 1, X, Y, -, +} and fermionic terms  (Methods, Hamiltonian representations)
+ *   - grouping by off-diagonal structure and ladder integers    (Methods, Qubit / Fermionic Hamiltonians)
+ *   - cached diagonal, matrix-free SpMV and two-pass CSR        (Methods, Matrix evaluation)
+ *   - a ground-state Lanczos eigensolver built on the SpMV      (not in the paper, which hands the
+ *                                                                operator to external eigensolvers)
+ *
+ * Conventions for every call:
+ *   - The return value is a status code (QSD_OK = 0, negative on error).  On error a message
+ *     is available from qsd_last_error() (per calling thread) and no output is valid.
+ *   - Pointers documented "device" are HIP device (HBM) addresses on the current device;
+ *     "host" pointers are ordinary CPU memory.  The library never frees caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is enqueued
+ *     asynchronously on it unless a call is documented to synchronize.
+ *   - Handles are created by *_build / *_compile / *_create and released by *_destroy.  A
+ *     handle is immutable after creation; concurrent read-only use on several streams is
+ *     safe.  Destroying a handle that is still referenced (a subspace or operator bound in a
+ *     live qsd_ham) is the caller's error.
+ *   - Bit-strings: qubit q is bit (q % 64) of 64-bit word (q / 64); W = ceil(n_qubits / 64)
+ *     words per string (Supplemental Material, MSOB section: bit indexing starts from the
+ *     right).  Bits at positions >= n_qubits must be zero.
+ *   - Subspace index: strings are sorted ascending as unsigned integers (word W-1 most
+ *     significant) and deduplicated; the index of a string is its rank (Methods, Lower /
+ *     upper triangle evaluation).
+ *   - Matrix convention: H_ij = <b_i|H|b_j>, y = H x.
+ */
+#ifndef QSD_H
+#define QSD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status codes */
+#define QSD_OK 0
+#define QSD_ERR_INVALID_ARG (-1)   /* malformed input; nothing was enqueued */
+#define QSD_ERR_OUT_OF_MEMORY (-2) /* a device or host allocation failed */
+#define QSD_ERR_HIP (-3)           /* a HIP runtime call failed */
+#define QSD_ERR_CAPACITY (-4)      /* a size exceeds what the requested index type can hold */
+#define QSD_ERR_NOT_HERMITIAN (-5) /* QSD_OP_CHECK_HERMITIAN failed */
+#define QSD_ERR_NOT_CONVERGED (-6) /* Lanczos stopped at max_iter; outputs hold the best estimate */
+#define QSD_ERR_DTYPE (-7)         /* dtype does not match the operator (real vs complex) */
+#define QSD_ERR_UNSUPPORTED (-8)   /* a valid request outside what this build implements */
+
+/* ----------------------------------------------------------------- value types */
+#define QSD_F64 0  /* double */
+#define QSD_F32 1  /* float elements and vectors, double accumulation */
+#define QSD_C128 2 /* double complex, interleaved (re, im) */
+#define QSD_C64 3  /* float complex, double accumulation */
+
+#define QSD_INDEX_I32 0
+#define QSD_INDEX_I64 1
+
+/* -------------------------------------------------- extended alphabet (Methods, Qubit Hamiltonians) */
+#define QSD_Z 0     /* Pauli Z */
+#define QSD_P0 1    /* projector |0><0| */
+#define QSD_P1 2    /* projector |1><1| */
+#define QSD_X 3     /* Pauli X */
+#define QSD_Y 4     /* Pauli Y */
+#define QSD_LOWER 5 /* |0><1|; with QSD_OP_FERMIONIC: annihilator f */
+#define QSD_RAISE 6 /* |1><0|; with QSD_OP_FERMIONIC: creator f^dagger */
+
+/* --------------------------------------------------------------------- flags */
+#define QSD_SUB_ASSUME_SORTED_UNIQUE 1u /* input is already ascending and duplicate-free */
+
+#define QSD_OP_FERMIONIC 1u       /* terms are products of f / f^dagger (codes 5 / 6) */
+#define QSD_OP_CHECK_HERMITIAN 2u /* fail with QSD_ERR_NOT_HERMITIAN unless H = H^dagger */
+#define QSD_OP_FORCE_COMPLEX 4u   /* treat the matrix as complex even if every element is real */
+#define QSD_OP_NO_LADDER_INT 8u   /* evaluate every group without ladder-integer ranges (ablation) */
+
+typedef struct qsd_subspace qsd_subspace;
+typedef struct qsd_op qsd_op;
+typedef struct qsd_ham qsd_ham;
+
+/* Message of the last failing call on this thread ("" if none).  Valid until the next call. */
+const char *qsd_last_error(void);
+
+/* Library version as an integer (major * 10000 + minor * 100 + patch). */
+int qsd_version(void);
+
+/* ============================================================ subspace (bit-set hash map)
+ *
+ * qsd_subspace_build - Methods, Subspace data structure.
+ *   Copies, sorts and deduplicates n_in bit-strings and builds the lookup table: open
+ *   addressing with linear probing over 2^k slots holding {32-bit tag, 32-bit index}, plus
+ *   one occupancy bit per slot tested before any slot is read (the paper's bucket-occupancy
+ *   bit-set).  k is the smallest power of two with N / 2^k <= max_load.
+ *   d_bits    device, [n_in][W] uint64 row-major; read only during the call's stream work.
+ *   n_in      number of input strings (>= 1).
+ *   n_qubits  >= 1.  W = ceil(n_qubits / 64).
+ *   flags     QSD_SUB_* bits.
+ *   max_load  hash load factor in (0, 0.5]; 0 selects 0.5.
+ *   out       receives the new handle.
+ *   Synchronizes `stream` (the unique count N is read back).  Errors: INVALID_ARG if n_in < 1,
+ *   n_qubits < 1, a bit >= n_qubits is set, or max_load is out of range; CAPACITY if
+ *   N >= 2^32 - 1; UNSUPPORTED if W exceeds the widest compiled key (see qsd_max_qubits).
+ */
+int qsd_subspace_build(const uint64_t *d_bits, int64_t n_in, int32_t n_qubits, uint32_t flags, double max_load,
+                       void *stream, qsd_subspace **out);
+
+/* Largest n_qubits this build supports. */
+int32_t qsd_max_qubits(void);
+
+/* Sizes of a built subspace: N unique strings, n_qubits, W words per string, hash capacity
+ * (slots).  Any output pointer may be NULL. */
+int qsd_subspace_info(const qsd_subspace *s, int64_t *N, int32_t *n_qubits, int32_t *W, int64_t *capacity);
+
+/* Copies the canonical (sorted, unique) strings to device memory d_out, [N][W] row-major. */
+int qsd_subspace_keys(const qsd_subspace *s, uint64_t *d_out, void *stream);
+
+/* Index lookup through the hash table: d_idx[i] = index of d_q[i] ([n][W] device) or -1.
+ * Strings with bits >= n_qubits set are reported absent. */
+int qsd_subspace_lookup(const qsd_subspace *s, const uint64_t *d_q, int64_t n, int64_t *d_idx, void *stream);
+
+/* Probe-length statistics of the hash table (host outputs, synchronizes): mean and maximum
+ * number of occupied slots inspected by a successful lookup of every stored string. */
+int qsd_subspace_probe_stats(const qsd_subspace *s, double *mean_probe, int64_t *max_probe, void *stream);
+
+int qsd_subspace_destroy(qsd_subspace *s);
+
+/* ==================================================================== operator compile
+ *
+ * qsd_op_compile - Methods, Hamiltonian representations.  Host-only (no device work).
+ *   Input is a flat list of terms c_t * word_t, word_t = product of single-qubit letters:
+ *   term t has letters op_code[term_ptr[t] .. term_ptr[t+1]) acting on qubits op_idx[...],
+ *   coefficient (coef_reim[2t], coef_reim[2t+1]).  An empty word is the identity.  Terms with
+ *   a zero coefficient are ignored.
+ *   Qubit mode: letters are QSD_Z..QSD_RAISE on distinct qubits (any order).
+ *   QSD_OP_FERMIONIC: letters are QSD_LOWER (f) / QSD_RAISE (f^dagger) in product order; indices
+ *   may repeat.  Each term is brought to ascending index order with the sign of every exchange
+ *   of operators on different modes, repeated modes are merged with the 16 rules of
+ *   Supplemental Table S1, and the extended Jordan-Wigner map (f_j -> |0><1|_j with Z on
+ *   every lower qubit) produces a word over {Z, 0, 1, -, +}.
+ *   Both modes then combine equal words (sum of coefficients; a word whose coefficients cancel
+ *   is kept), split off the diagonal group (no off-diagonal letter), group off-diagonal words
+ *   by their off-diagonal qubit set (ordered by set size, then by the set as an integer) and,
+ *   inside a group whose off-diagonal letters are all ladders on at most 4 qubits, sort terms
+ *   by ladder integer ('-' -> 0, '+' -> 1, k-th lowest qubit -> bit k) with 2^k + 1 range
+ *   pointers.
+ *   trim_tol  must be 0 (group trimming is not implemented in this build: UNSUPPORTED).
+ *   All arrays are host memory and are not retained.
+ *   Errors: INVALID_ARG (index out of range, bad code, repeated qubit in qubit mode, NaN);
+ *   NOT_HERMITIAN with QSD_OP_CHECK_HERMITIAN when some word's adjoint does not carry the
+ *   conjugate coefficient (relative tolerance 1e-12).
+ */
+int qsd_op_compile(int32_t n_qubits, int64_t n_terms, const int64_t *term_ptr, const int32_t *op_idx,
+                   const uint8_t *op_code, const double *coef_reim, uint32_t flags, double trim_tol, qsd_op **out);
+
+/* Sizes of a compiled operator: T compiled terms, total letters, G groups (the diagonal
+ * group counts as one), whether the matrix is complex, n_qubits.  Any pointer may be NULL. */
+int qsd_op_info(const qsd_op *op, int64_t *T, int64_t *n_letters, int64_t *G, int32_t *is_complex,
+                int32_t *n_qubits);
+
+/* Exports the compiled terms (host buffers sized from qsd_op_info): term_ptr[T+1],
+ * op_idx / op_code [n_letters] (ascending qubit per term, qubit-alphabet codes),
+ * coef_reim[2T], group_ptr[G+1] (group 0 = diagonal terms, possibly empty), and
+ * group_ladder[G] (1 if the group uses ladder-integer ranges).  Terms appear in group order,
+ * each group sorted by ladder integer where applicable.  Any output pointer may be NULL. */
+int qsd_op_export(const qsd_op *op, int64_t *term_ptr, int32_t *op_idx, uint8_t *op_code, double *coef_reim,
+                  int64_t *group_ptr, int32_t *group_ladder);
+
+int qsd_op_destroy(qsd_op *op);
+
+/* ============================================================ subspace Hamiltonian
+ *
+ * qsd_ham_create - Methods, Matrix evaluation ("SubspaceHamiltonian").  Binds a subspace and
+ *   an operator with the same n_qubits, uploads the group and term tables and computes the
+ *   diagonal d_i = H_ii once (projector letters tested before any sign is formed).  The
+ *   handle references `s` and `op`; they must outlive it.  flags: reserved, pass 0.
+ *   Enqueued on `stream`.
+ */
+int qsd_ham_create(const qsd_subspace *s, const qsd_op *op, uint32_t flags, void *stream, qsd_ham **out);
+
+/* Copies the cached diagonal (FP64 real part; imaginary parts of a Hermitian H are zero) to
+ * device d_out[N]. */
+int qsd_ham_diagonal(const qsd_ham *h, double *d_out, void *stream);
+
+int qsd_ham_destroy(qsd_ham *h);
+
+/* Sizes: N rows, G groups. */
+int qsd_ham_info(const qsd_ham *h, int64_t *N, int64_t *G, int32_t *is_complex);
+
+/* Work of one SpMV, counted by a separate pass (synchronizes): `probes` = (row, group) pairs
+ * that reach the hash table (a live ladder-integer range with at least one term whose
+ * projector bits match), `hits` = those whose column is in the subspace (the off-diagonal
+ * stored entries).  Host outputs; either may be NULL. */
+int qsd_ham_work_counts(const qsd_ham *h, int64_t *probes, int64_t *hits, void *stream);
+
+/* ==================================================================== matrix-free SpMV
+ *
+ * qsd_matvec - Methods, Matrix evaluation (matrix-free).  Y = H X for `nvec` vectors at once:
+ *   every row evaluates each group once (ladder-integer range, column by XOR with the group
+ *   mask, one hash probe, projector refinement, popcount-parity signs) and applies the element
+ *   to all nvec vectors.
+ *   Layout: interleaved, element (row j, vector v) at X[j * ldx + v] (ldx >= nvec), likewise Y.
+ *   dtype: QSD_F64 / QSD_F32 for a real matrix, QSD_C128 / QSD_C64 for a complex one
+ *   (ld counts complex elements).  F32/C64 store elements and vectors in single precision and
+ *   accumulate each row in double.
+ *   1 <= nvec <= 16.  X and Y must not overlap.  Y is overwritten.
+ */
+int qsd_matvec(const qsd_ham *h, int32_t nvec, const void *d_x, int64_t ldx, void *d_y, int64_t ldy, int32_t dtype,
+               void *stream);
+
+/* ============================================================================= CSR
+ *
+ * qsd_csr_build - Methods, Matrix evaluation (two-pass CSR).
+ *   Call 1 with d_indices == d_data == NULL: writes d_indptr[N+1] (int64, device), returns
+ *   nnz in *nnz_out (synchronizes).  The caller allocates indices[nnz] and data[nnz].
+ *   Call 2 with all pointers: fills column indices (ascending within each row; type
+ *   QSD_INDEX_I32 or QSD_INDEX_I64) and values (dtype as for qsd_matvec).
+ *   An entry (i, j) is stored iff j == i, or b_j is in the subspace and at least one term's
+ *   element between b_i and b_j is nonzero (the stored value may cancel to 0.0).
+ *   Errors: CAPACITY for QSD_INDEX_I32 with N >= 2^31.
+ */
+int qsd_csr_build(const qsd_ham *h, int64_t *d_indptr, void *d_indices, void *d_data, int32_t index_type,
+                  int32_t dtype, int64_t *nnz_out, void *stream);
+
+/* ========================================================================== Lanczos */
+#define QSD_V0_UNIFORM 0  /* all ones, normalized */
+#define QSD_V0_MIN_DIAG 1 /* unit spike at the smallest diagonal entry (lowest index on ties) */
+#define QSD_V0_RANDOM 2   /* uniform [-1, 1) entries from a counter-based generator (seed) */
+#define QSD_V0_USER 3     /* read from d_evec on entry */
+
+typedef struct {
+    int32_t max_iter;    /* Krylov dimension limit (default 300) */
+    double tol;          /* stop when beta_k |s_k| <= tol |theta| (default 1e-10) */
+    int32_t v0_mode;     /* QSD_V0_* */
+    uint64_t seed;       /* QSD_V0_RANDOM */
+    int32_t spmv_dtype;  /* QSD_F64 or QSD_F32 (real) / QSD_C128 or QSD_C64 (complex) */
+    int32_t check_every; /* iterations between convergence checks (default 5) */
+    int32_t want_vector; /* write the normalized Ritz vector to d_evec */
+    int32_t use_graph;   /* capture one iteration in a HIP graph and replay it */
+} qsd_lanczos_opts;
+
+typedef struct {
+    int32_t iterations;
+    int32_t converged;
+    double ritz_residual;     /* beta_k |s_k| at exit */
+    double explicit_residual; /* ||H x - theta x|| / |theta| in FP64 (if want_vector) */
+    double matvec_ms;         /* GPU time in SpMV (HIP events) */
+    double total_ms;          /* wall time of the call */
+} qsd_lanczos_info;
+
+/* Fills opts with the defaults above. */
+void qsd_lanczos_default_opts(qsd_lanczos_opts *opts);
+
+/* Lowest eigenvalue of H (Hermitian) by Lanczos with full reorthogonalization (classical
+ * Gram-Schmidt applied twice), FP64 basis and recurrence, tridiagonal eigenproblem by Sturm
+ * bisection plus inverse iteration on the device.
+ *   eval_out  host, receives theta.
+ *   d_evec    device [N] (FP64, or complex FP64 for a complex H): Ritz vector if want_vector,
+ *             start vector if v0_mode == QSD_V0_USER; may be NULL otherwise.
+ *   info      host, may be NULL.
+ * Synchronizes.  Returns NOT_CONVERGED (with outputs filled) if max_iter is reached.
+ * The basis needs (max_iter + 1) * N * 8 bytes (x2 for complex) of device memory.
+ */
+int qsd_lanczos(const qsd_ham *h, const qsd_lanczos_opts *opts, double *eval_out, void *d_evec,
+                qsd_lanczos_info *info, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QSD_H */

@@ -1,0 +1,364 @@
+"""MI355X-native subspace-Hamiltonian SpMV (arXiv 2603.18731, "Fulqrum" method).
+
+Python binding of the C-ABI in ``include/qsd.h`` (``libqsd.so``, built for gfx950 by
+``paper_2603_18731_amd.build``).  This module only marshals arguments: every step of the
+path runs in the library's HIP kernels.  PyTorch supplies device memory and streams.
+
+Classes mirror the paper's API names (Methods; workflow figure):
+
+* ``Subspace``            - bit-strings -> canonical index + device hash table
+* ``QubitOperator``       - terms over {Z, 0, 1, X, Y, -, +}
+* ``FermionicOperator``   - products of f / f^dagger, compiled by the extended JW transform
+* ``SubspaceHamiltonian`` - cached diagonal, ``matvec``, ``to_csr``, ``lanczos``
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqsd.so")
+
+QSD_OK = 0
+F64, F32, C128, C64 = 0, 1, 2, 3
+INDEX_I32, INDEX_I64 = 0, 1
+OP_FERMIONIC, OP_CHECK_HERMITIAN, OP_FORCE_COMPLEX, OP_NO_LADDER_INT = 1, 2, 4, 8
+SUB_ASSUME_SORTED_UNIQUE = 1
+V0_UNIFORM, V0_MIN_DIAG, V0_RANDOM, V0_USER = 0, 1, 2, 3
+ERR_NAMES = {-1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "HIP", -4: "CAPACITY", -5: "NOT_HERMITIAN",
+             -6: "NOT_CONVERGED", -7: "DTYPE", -8: "UNSUPPORTED"}
+
+EXPORTED = [
+    "qsd_last_error", "qsd_version", "qsd_max_qubits", "qsd_subspace_build", "qsd_subspace_info",
+    "qsd_subspace_keys", "qsd_subspace_lookup", "qsd_subspace_probe_stats", "qsd_subspace_destroy",
+    "qsd_op_compile", "qsd_op_info", "qsd_op_export", "qsd_op_destroy", "qsd_ham_create", "qsd_ham_diagonal",
+    "qsd_ham_destroy", "qsd_ham_info", "qsd_ham_work_counts", "qsd_matvec", "qsd_csr_build", "qsd_lanczos_default_opts", "qsd_lanczos",
+]
+
+
+class QsdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (ERR_NAMES.get(code, "ERROR"), code, msg))
+        self.code = code
+
+
+class LanczosOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("v0_mode", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("spmv_dtype", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("want_vector", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class LanczosInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("ritz_residual", ctypes.c_double),
+                ("explicit_residual", ctypes.c_double), ("matvec_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded ``libqsd.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libqsd.so is missing: build it with `python -m paper_2603_18731_amd.build` "
+                           "(no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "qsd_last_error": ([], ctypes.c_char_p),
+        "qsd_version": ([], ctypes.c_int),
+        "qsd_max_qubits": ([], I32),
+        "qsd_subspace_build": ([P, I64, I32, U32, D, P, PP], ctypes.c_int),
+        "qsd_subspace_info": ([P, P, P, P, P], ctypes.c_int),
+        "qsd_subspace_keys": ([P, P, P], ctypes.c_int),
+        "qsd_subspace_lookup": ([P, P, I64, P, P], ctypes.c_int),
+        "qsd_subspace_probe_stats": ([P, P, P, P], ctypes.c_int),
+        "qsd_subspace_destroy": ([P], ctypes.c_int),
+        "qsd_op_compile": ([I32, I64, P, P, P, P, U32, D, PP], ctypes.c_int),
+        "qsd_op_info": ([P, P, P, P, P, P], ctypes.c_int),
+        "qsd_op_export": ([P, P, P, P, P, P, P], ctypes.c_int),
+        "qsd_op_destroy": ([P], ctypes.c_int),
+        "qsd_ham_create": ([P, P, U32, P, PP], ctypes.c_int),
+        "qsd_ham_diagonal": ([P, P, P], ctypes.c_int),
+        "qsd_ham_destroy": ([P], ctypes.c_int),
+        "qsd_ham_info": ([P, P, P, P], ctypes.c_int),
+        "qsd_ham_work_counts": ([P, P, P, P], ctypes.c_int),
+        "qsd_matvec": ([P, I32, P, I64, P, I64, I32, P], ctypes.c_int),
+        "qsd_csr_build": ([P, P, P, P, I32, I32, P, P], ctypes.c_int),
+        "qsd_lanczos_default_opts": ([ctypes.POINTER(LanczosOpts)], None),
+        "qsd_lanczos": ([P, ctypes.POINTER(LanczosOpts), P, P, ctypes.POINTER(LanczosInfo), P], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != QSD_OK:
+        raise QsdError(rc, lib().qsd_last_error().decode())
+
+
+def _ptr(a) -> ctypes.c_void_p:
+    if a is None:
+        return ctypes.c_void_p(0)
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(ctypes.c_void_p)
+    return ctypes.c_void_p(a.data_ptr())
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _device_tensor(a, dtype=None):
+    import torch
+
+    if isinstance(a, torch.Tensor):
+        t = a
+    else:
+        arr = np.ascontiguousarray(a)
+        if arr.dtype == np.uint64:
+            arr = arr.view(np.int64)
+        t = torch.from_numpy(arr)
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda().contiguous()
+
+
+# ----------------------------------------------------------------------------- classes
+
+class Subspace:
+    """Canonical bit-string subspace on the device (Methods, Subspace data structure)."""
+
+    def __init__(self, bits, n_qubits: int, max_load: float = 0.5, assume_sorted_unique: bool = False, stream=None):
+        import torch
+
+        b = _device_tensor(bits)
+        if b.dtype not in (torch.int64, torch.uint64):
+            raise TypeError("bits must be 64-bit words")
+        W = (n_qubits + 63) // 64
+        b = b.reshape(-1, W) if b.numel() else b.reshape(0, W)
+        self.n_qubits = int(n_qubits)
+        h = ctypes.c_void_p()
+        _check(lib().qsd_subspace_build(_ptr(b), b.shape[0], self.n_qubits,
+                                        SUB_ASSUME_SORTED_UNIQUE if assume_sorted_unique else 0, max_load,
+                                        _stream(stream), ctypes.byref(h)))
+        self._h = h
+        N, nq, Wo, C = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().qsd_subspace_info(h, ctypes.byref(N), ctypes.byref(nq), ctypes.byref(Wo), ctypes.byref(C)))
+        self.N, self.W, self.capacity = N.value, Wo.value, C.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __len__(self):
+        return self.N
+
+    def keys(self, stream=None):
+        """Canonical strings, ``[N][W]`` int64 device tensor (uint64 bit patterns)."""
+        import torch
+
+        out = torch.empty((self.N, self.W), dtype=torch.int64, device="cuda")
+        _check(lib().qsd_subspace_keys(self._h, _ptr(out), _stream(stream)))
+        return out
+
+    def lookup(self, q, stream=None):
+        import torch
+
+        qt = _device_tensor(q).reshape(-1, self.W)
+        out = torch.empty(qt.shape[0], dtype=torch.int64, device="cuda")
+        _check(lib().qsd_subspace_lookup(self._h, _ptr(qt), qt.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def probe_stats(self, stream=None):
+        m, x = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().qsd_subspace_probe_stats(self._h, ctypes.byref(m), ctypes.byref(x), _stream(stream)))
+        return m.value, x.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.qsd_subspace_destroy(h)
+            self._h = None
+
+
+class _Operator:
+    fermionic = False
+
+    def __init__(self, n_qubits: int, term_ptr, op_idx, op_code, coef, check_hermitian: bool = False,
+                 force_complex: bool = False, ladder_ints: bool = True):
+        tp = np.ascontiguousarray(term_ptr, dtype=np.int64)
+        oi = np.ascontiguousarray(op_idx, dtype=np.int32)
+        oc = np.ascontiguousarray(op_code, dtype=np.uint8)
+        c = np.asarray(coef, dtype=np.complex128)
+        cr = np.ascontiguousarray(np.stack([c.real, c.imag], axis=1)).astype(np.float64)
+        flags = (OP_FERMIONIC if self.fermionic else 0) | (OP_CHECK_HERMITIAN if check_hermitian else 0) | \
+                (OP_FORCE_COMPLEX if force_complex else 0) | (0 if ladder_ints else OP_NO_LADDER_INT)
+        h = ctypes.c_void_p()
+        _check(lib().qsd_op_compile(int(n_qubits), tp.shape[0] - 1, _ptr(tp), _ptr(oi), _ptr(oc), _ptr(cr), flags, 0.0,
+                                    ctypes.byref(h)))
+        self._h = h
+        self.n_qubits = int(n_qubits)
+        T, nl, G, cx, nq = (ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32())
+        _check(lib().qsd_op_info(h, ctypes.byref(T), ctypes.byref(nl), ctypes.byref(G), ctypes.byref(cx),
+                                 ctypes.byref(nq)))
+        self.n_terms, self.n_letters, self.n_groups, self.is_complex = T.value, nl.value, G.value, bool(cx.value)
+
+    @classmethod
+    def from_termlist(cls, tl, **kw):
+        return cls(tl.n_qubits, tl.term_ptr, tl.op_idx, tl.op_code, tl.coef, **kw)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self):
+        """Compiled terms: ``(term_ptr, op_idx, op_code, coef, group_ptr, group_ladder)``."""
+        tp = np.zeros(self.n_terms + 1, dtype=np.int64)
+        oi = np.zeros(max(1, self.n_letters), dtype=np.int32)
+        oc = np.zeros(max(1, self.n_letters), dtype=np.uint8)
+        cr = np.zeros((max(1, self.n_terms), 2), dtype=np.float64)
+        gp = np.zeros(self.n_groups + 1, dtype=np.int64)
+        gl = np.zeros(self.n_groups, dtype=np.int32)
+        _check(lib().qsd_op_export(self._h, _ptr(tp), _ptr(oi), _ptr(oc), _ptr(cr), _ptr(gp), _ptr(gl)))
+        return tp, oi[: self.n_letters], oc[: self.n_letters], (cr[:, 0] + 1j * cr[:, 1])[: self.n_terms], gp, gl
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.qsd_op_destroy(h)
+            self._h = None
+
+
+class QubitOperator(_Operator):
+    """Sum of words over the extended alphabet (Methods, Qubit Hamiltonians)."""
+
+    fermionic = False
+
+
+class FermionicOperator(_Operator):
+    """Sum of products of f / f^dagger, compiled through the extended JW transform."""
+
+    fermionic = True
+
+
+def operator_from_termlist(tl, **kw):
+    return (FermionicOperator if tl.fermionic else QubitOperator).from_termlist(tl, **kw)
+
+
+class SubspaceHamiltonian:
+    """Operator restricted to a subspace (Methods, Matrix evaluation)."""
+
+    def __init__(self, subspace: Subspace, op: _Operator, stream=None):
+        self.subspace, self.op = subspace, op  # kept alive: the handle references both
+        h = ctypes.c_void_p()
+        _check(lib().qsd_ham_create(subspace.handle, op.handle, 0, _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.N = subspace.N
+        self.is_complex = op.is_complex
+        self.shape = (self.N, self.N)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def diagonal(self, stream=None):
+        import torch
+
+        d = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        _check(lib().qsd_ham_diagonal(self._h, _ptr(d), _stream(stream)))
+        return d
+
+    @staticmethod
+    def _dtype_code(t):
+        import torch
+
+        return {torch.float64: F64, torch.float32: F32, torch.complex128: C128, torch.complex64: C64}[t.dtype]
+
+    def work_counts(self, stream=None):
+        """``(probes, hits)`` of one SpMV."""
+        p, h = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().qsd_ham_work_counts(self._h, ctypes.byref(p), ctypes.byref(h), _stream(stream)))
+        return p.value, h.value
+
+    def matvec(self, x, out=None, stream=None):
+        """``H @ x`` for ``x`` of shape ``[N]`` or ``[N][nvec]`` (row-major, interleaved vectors)."""
+        import torch
+
+        vec = x.dim() == 1
+        X = x.reshape(self.N, -1)
+        if X.stride(1) != 1:
+            X = X.contiguous()
+        nvec = X.shape[1]
+        Y = torch.empty_like(X) if out is None else out.reshape(self.N, -1)
+        _check(lib().qsd_matvec(self._h, nvec, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0), self._dtype_code(X),
+                                _stream(stream)))
+        return Y.reshape(-1) if vec else Y
+
+    def matvec_raw(self, nvec, x_ptr, ldx, y_ptr, ldy, dtype, stream=None):
+        _check(lib().qsd_matvec(self._h, nvec, ctypes.c_void_p(x_ptr), ldx, ctypes.c_void_p(y_ptr), ldy, dtype,
+                                _stream(stream)))
+
+    def to_csr(self, index_type: int = INDEX_I64, dtype=None, stream=None):
+        """Two-pass CSR: ``(indptr int64, indices, data)`` device tensors."""
+        import torch
+
+        if dtype is None:
+            dtype = torch.complex128 if self.is_complex else torch.float64
+        code = {torch.float64: F64, torch.float32: F32, torch.complex128: C128, torch.complex64: C64}[dtype]
+        indptr = torch.empty(self.N + 1, dtype=torch.int64, device="cuda")
+        nnz = ctypes.c_int64()
+        st = _stream(stream)
+        _check(lib().qsd_csr_build(self._h, _ptr(indptr), None, None, index_type, code, ctypes.byref(nnz), st))
+        idx = torch.empty(max(1, nnz.value), dtype=torch.int32 if index_type == INDEX_I32 else torch.int64,
+                          device="cuda")
+        data = torch.empty(max(1, nnz.value), dtype=dtype, device="cuda")
+        _check(lib().qsd_csr_build(self._h, _ptr(indptr), _ptr(idx), _ptr(data), index_type, code, ctypes.byref(nnz),
+                                   st))
+        return indptr, idx[: nnz.value], data[: nnz.value]
+
+    def lanczos(self, max_iter=300, tol=1e-10, v0="uniform", seed=0, spmv_dtype="f64", check_every=5,
+                want_vector=False, use_graph=False, v0_vector=None, stream=None, raise_on_nonconv=True):
+        """Lowest eigenvalue by GPU Lanczos: ``(energy, vector or None, info dict)``."""
+        import torch
+
+        o = LanczosOpts()
+        lib().qsd_lanczos_default_opts(ctypes.byref(o))
+        o.max_iter, o.tol, o.seed, o.check_every = max_iter, tol, seed, check_every
+        o.v0_mode = {"uniform": V0_UNIFORM, "min_diag": V0_MIN_DIAG, "random": V0_RANDOM, "user": V0_USER}[v0]
+        o.spmv_dtype = {"f64": F64, "f32": F32}[spmv_dtype]
+        o.want_vector, o.use_graph = int(want_vector), int(use_graph)
+        vec = None
+        if want_vector or v0 == "user":
+            vec = torch.empty(self.N, dtype=torch.float64, device="cuda")
+            if v0 == "user":
+                vec.copy_(v0_vector)
+        e = ctypes.c_double()
+        info = LanczosInfo()
+        rc = lib().qsd_lanczos(self._h, ctypes.byref(o), ctypes.byref(e), _ptr(vec), ctypes.byref(info),
+                               _stream(stream))
+        if rc != QSD_OK and not (rc == -6 and not raise_on_nonconv):
+            _check(rc)
+        return e.value, (vec if want_vector else None), info.as_dict()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.qsd_ham_destroy(h)
+            self._h = None

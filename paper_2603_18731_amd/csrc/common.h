@@ -1,0 +1,154 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "qsd.h"
+
+namespace qsd {
+
+// Error state (thread-local message) -------------------------------------------------
+int fail(int code, const char *fmt, ...);
+void clear_error();
+
+#define QSD_CHECK_HIP(call)                                                                            \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return ::qsd::fail(QSD_ERR_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),    \
+                               __FILE__, __LINE__);                                                    \
+    } while (0)
+
+#define QSD_TRY(expr)                                                                                  \
+    do {                                                                                               \
+        int rc_ = (expr);                                                                              \
+        if (rc_ != QSD_OK) return rc_;                                                                 \
+    } while (0)
+
+constexpr int kMaxLadder = 4;   // ladder-integer ranges for groups of up to 4 ladder letters
+constexpr int kMaxWords = 16;   // widest compiled key: 16 x 64 = 1024 qubits
+constexpr int kBlock = 256;     // threads per workgroup for row kernels
+
+// Padded word count used by the kernels: 1, 2, 4, 8 or 16.
+inline int padded_words(int n_qubits) {
+    int W = (n_qubits + 63) / 64;
+    int Wp = 1;
+    while (Wp < W) Wp <<= 1;
+    return Wp;
+}
+
+// GF(2)-linear hash of a bit-string: XOR of one fixed pseudo-random 64-bit value per set
+// bit.  Linearity gives hash(row ^ mask) = hash(row) ^ hash(mask), so a probe for the
+// column of any group costs one XOR once the row's hash is known.
+uint64_t qubit_hash_value(int q);  // value for qubit q
+void hash_byte_tables(int Wp, std::vector<uint64_t> &tab);  // [Wp*8][256] byte tabulation
+
+// Device memory helpers --------------------------------------------------------------
+template <class T>
+int dev_alloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(QSD_ERR_OUT_OF_MEMORY, "hipMalloc(%zu bytes) failed: %s", count * sizeof(T),
+                    hipGetErrorString(e));
+    }
+    return QSD_OK;
+}
+template <class T>
+void dev_free(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+// Device-wide exclusive scan of int64 counts (in place allowed); n elements.
+int exclusive_scan_i64(const int64_t *d_in, int64_t *d_out, int64_t n, hipStream_t stream);
+
+}  // namespace qsd
+
+// ------------------------------------------------------------------- handle contents
+
+struct qsd_subspace {
+    int32_t n_qubits = 0;
+    int32_t W = 0;   // words per string
+    int32_t Wp = 0;  // padded words used by kernels
+    int64_t N = 0;   // unique strings
+    int64_t C = 0;   // hash slots (power of two)
+    uint64_t *keys = nullptr;    // [Wp][N] word planes, ascending order
+    uint64_t *hkey = nullptr;    // [N] linear hash of each key
+    uint64_t *slots = nullptr;   // [C] (tag << 32) | index, empty = ~0
+    uint32_t *bitmap = nullptr;  // [C / 32] slot occupancy
+    uint64_t *ztab = nullptr;    // [Wp * 8][256] byte tabulation of the hash
+};
+
+struct Letter {
+    int32_t q;
+    uint8_t code;
+};
+
+struct CompiledTerm {
+    std::vector<Letter> word;  // ascending qubit
+    std::complex<double> c;    // coefficient of the word
+};
+
+struct qsd_op {
+    int32_t n_qubits = 0;
+    int32_t Wp = 0;
+    bool is_complex = false;
+    std::vector<CompiledTerm> terms;      // group order; group 0 = diagonal
+    std::vector<int64_t> group_ptr;       // G + 1
+    std::vector<int32_t> group_ladder;    // G
+    // Device-table images (host), built by the compiler -------------------------------
+    // diagonal terms: care/want/sign words and c' = c * (-i)^{#Y}
+    std::vector<uint64_t> diag_cws;       // [Td][3][Wp]
+    std::vector<double> diag_coef;        // [Td][2]
+    // off-diagonal groups
+    std::vector<uint64_t> g_mask;         // [G-1][Wp]
+    std::vector<uint64_t> g_hash;         // [G-1]
+    std::vector<uint64_t> g_pos;          // [G-1] four 16-bit ladder positions
+    std::vector<uint32_t> g_info;         // [G-1] k | ladder<<3 | care<<4 | live16<<16
+    std::vector<uint32_t> g_term0;        // [G-1] first off-diagonal term
+    std::vector<uint32_t> g_nterm;        // [G-1]
+    std::vector<uint16_t> g_iptr;         // [G-1][kIptr] ladder ranges relative to g_term0
+    std::vector<uint64_t> t_cws;          // [To][3][Wp]
+    std::vector<double> t_coef;           // [To][2]
+    int64_t max_group_terms = 0;
+};
+
+constexpr int kIptr = 18;  // 2^4 + 1 pointers, padded to an even count
+
+// Packed group descriptor bits.
+constexpr uint32_t kInfoKMask = 7u;
+constexpr uint32_t kInfoLadder = 1u << 3;
+constexpr uint32_t kInfoCare = 1u << 4;
+
+struct qsd_ham {
+    const qsd_subspace *s = nullptr;
+    const qsd_op *op = nullptr;
+    int64_t N = 0;
+    int64_t G = 0;   // off-diagonal groups
+    int32_t Wp = 0;
+    bool is_complex = false;
+    double *diag = nullptr;       // [N] real part (FP64)
+    double *diag_im = nullptr;    // [N] imaginary part (complex operators only)
+    uint64_t *g_mask = nullptr;
+    uint64_t *g_hash = nullptr;
+    uint64_t *g_pos = nullptr;
+    uint32_t *g_info = nullptr;
+    uint32_t *g_term0 = nullptr;
+    uint32_t *g_nterm = nullptr;
+    uint16_t *g_iptr = nullptr;
+    uint64_t *t_cws = nullptr;
+    double *t_coef = nullptr;     // [To][2]
+    float *t_coef32 = nullptr;    // [To][2]
+    float *diag32 = nullptr;      // [N]
+    float *diag32_im = nullptr;
+};

@@ -1,0 +1,699 @@
+// Subspace Hamiltonian on the device: cached diagonal, matrix-free SpMV / SpMM and the
+// two-pass CSR builder (Methods, Matrix evaluation).
+//
+// Row engine.  One lane owns one row bit-string; the 64 lanes of a wavefront walk the group
+// list in lockstep, so every group descriptor is a wave-uniform (scalar) load.  For each
+// group a lane
+//   1. forms its ladder integer from the row bits at the group's ladder qubits and takes the
+//      term range int_ptrs[L] .. int_ptrs[L+1]; an empty range skips the group with no probe
+//      (Methods, Fermionic Hamiltonians);
+//   2. if some term in range also constrains other qubits (projectors), tests those bits
+//      first and skips the group when every term fails;
+//   3. probes the hash table for col = row ^ mask: the row's hash XOR the group's hash (the
+//      hash is linear over GF(2)), occupancy bit first, then {tag, index} slots, then a key
+//      compare (Methods, Subspace data structure);
+//   4. on a hit sums c'_t (-1)^popcount(row & S_t) over the terms in range whose projector
+//      bits match (Methods, Matrix evaluation).
+// Groups where no lane of the wave is live are skipped by a wave vote.
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "device.h"
+
+namespace qsd {
+namespace {
+
+struct HamView {
+    const uint64_t *__restrict__ g_mask;
+    const uint64_t *__restrict__ g_hash;
+    const uint64_t *__restrict__ g_pos;
+    const uint32_t *__restrict__ g_info;
+    const uint32_t *__restrict__ g_term0;
+    const uint32_t *__restrict__ g_nterm;
+    const uint16_t *__restrict__ g_iptr;
+    const uint64_t *__restrict__ t_cws;
+    const void *__restrict__ t_coef;  // double2 or float2 per term
+    int64_t G;
+};
+
+template <int Wp>
+__device__ __forceinline__ uint32_t row_bit(const uint64_t (&k)[Wp], uint32_t p) {
+    uint64_t w = k[0];
+#pragma unroll
+    for (int i = 1; i < Wp; ++i)
+        if ((p >> 6) == (uint32_t)i) w = k[i];
+    const uint32_t half = (p & 32u) ? (uint32_t)(w >> 32) : (uint32_t)w;
+    return (half >> (p & 31u)) & 1u;
+}
+
+template <int Wp>
+__device__ __forceinline__ bool term_pass(const uint64_t (&k)[Wp], const uint64_t *__restrict__ cws) {
+    bool ok = true;
+#pragma unroll
+    for (int w = 0; w < Wp; ++w) ok &= (k[w] & cws[w]) == cws[Wp + w];
+    return ok;
+}
+
+template <int Wp>
+__device__ __forceinline__ uint32_t term_parity(const uint64_t (&k)[Wp], const uint64_t *__restrict__ cws) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < Wp; ++w) c += (uint32_t)__popcll(k[w] & cws[2 * Wp + w]);
+    return c & 1u;
+}
+
+template <class ET>
+struct C2;
+template <>
+struct C2<double> {
+    using T = double2;
+};
+template <>
+struct C2<float> {
+    using T = float2;
+};
+
+// Walks the groups of one row and calls on_hit(j, re, im) for every present off-diagonal
+// entry (j = column index).  NEED_VALUE = false skips the value arithmetic (CSR count).
+template <int Wp, class ET, bool NEED_VALUE, class OnHit>
+__device__ __forceinline__ void row_groups(const SubView &s, const HamView &h, const uint64_t (&key)[Wp], uint64_t hrow,
+                                           bool valid, OnHit &&on_hit) {
+    using CT = typename C2<ET>::T;
+    const CT *__restrict__ coef = (const CT *)h.t_coef;
+    for (int64_t g = 0; g < h.G; ++g) {
+        const uint32_t info = h.g_info[g];
+        uint32_t lo, hi;
+        bool live;
+        if (info & kInfoLadder) {
+            const uint64_t pos = h.g_pos[g];
+            const uint32_t kk = info & kInfoKMask;
+            uint32_t L = 0;
+            for (uint32_t j = 0; j < kk; ++j) L |= row_bit<Wp>(key, (uint32_t)(pos >> (16 * j)) & 0xFFFFu) << j;
+            live = (info >> (16 + L)) & 1u;
+            lo = h.g_iptr[g * kIptr + L];
+            hi = h.g_iptr[g * kIptr + L + 1];
+        } else {
+            lo = 0;
+            hi = h.g_nterm[g];
+            live = true;
+        }
+        live = live && valid;
+        if (!__any(live)) continue;
+        if (!live) continue;
+        const uint32_t t0 = h.g_term0[g];
+        if (info & kInfoCare) {
+            bool anyp = false;
+            for (uint32_t t = lo; t < hi; ++t)
+                if (term_pass<Wp>(key, h.t_cws + (int64_t)(t0 + t) * 3 * Wp)) {
+                    anyp = true;
+                    break;
+                }
+            if (!anyp) continue;
+        }
+        uint64_t col[Wp];
+#pragma unroll
+        for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ h.g_mask[g * Wp + w];
+        const int64_t j = probe<Wp>(s, hrow ^ h.g_hash[g], col);
+        if (j < 0) continue;
+        ET vre = 0, vim = 0;
+        if (NEED_VALUE) {
+            for (uint32_t t = lo; t < hi; ++t) {
+                const uint64_t *cws = h.t_cws + (int64_t)(t0 + t) * 3 * Wp;
+                if (!term_pass<Wp>(key, cws)) continue;
+                const CT c = coef[t0 + t];
+                if (term_parity<Wp>(key, cws)) {
+                    vre -= c.x;
+                    vim -= c.y;
+                } else {
+                    vre += c.x;
+                    vim += c.y;
+                }
+            }
+        }
+        on_hit(j, vre, vim);
+    }
+}
+
+// ----------------------------------------------------------------------------- diagonal
+
+template <int Wp>
+__global__ __launch_bounds__(kBlock) void k_diag(SubView s, const uint64_t *__restrict__ cws,
+                                                 const double *__restrict__ coef, int64_t Td, double *__restrict__ d_re,
+                                                 double *__restrict__ d_im) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= s.N) return;
+    uint64_t key[Wp];
+#pragma unroll
+    for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + i];
+    double re = 0.0, im = 0.0;
+    for (int64_t t = 0; t < Td; ++t) {
+        const uint64_t *c = cws + t * 3 * Wp;
+        if (!term_pass<Wp>(key, c)) continue;  // projector pass-over before the sign
+        const double cr = coef[2 * t], ci = coef[2 * t + 1];
+        if (term_parity<Wp>(key, c)) {
+            re -= cr;
+            im -= ci;
+        } else {
+            re += cr;
+            im += ci;
+        }
+    }
+    d_re[i] = re;
+    if (d_im) d_im[i] = im;
+}
+
+__global__ void k_to_f32(const double *__restrict__ in, float *__restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
+}
+
+// ------------------------------------------------------------------------------- matvec
+
+template <int Wp, int NV, class ET, bool CPLX>
+__global__ __launch_bounds__(kBlock) void k_matvec(SubView s, HamView h, const ET *__restrict__ dre,
+                                                   const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
+                                                   ET *__restrict__ y, int64_t ldy, int nvec) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = i < s.N;
+    const int64_t r = valid ? i : s.N - 1;
+    uint64_t key[Wp];
+#pragma unroll
+    for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + r];
+    const uint64_t hrow = s.hkey[r];
+    double acc_re[NV], acc_im[NV];
+    {
+        const double dr = (double)dre[r];
+        const double di = CPLX ? (double)dim[r] : 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (v < nvec) {
+                if (CPLX) {
+                    const double xr = (double)x[2 * (r * ldx + v)], xi = (double)x[2 * (r * ldx + v) + 1];
+                    acc_re[v] = dr * xr - di * xi;
+                    acc_im[v] = dr * xi + di * xr;
+                } else {
+                    acc_re[v] = dr * (double)x[r * ldx + v];
+                    acc_im[v] = 0.0;
+                }
+            } else {
+                acc_re[v] = acc_im[v] = 0.0;
+            }
+        }
+    }
+    row_groups<Wp, ET, true>(s, h, key, hrow, valid, [&](int64_t j, ET vre, ET vim) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (v < nvec) {
+                if (CPLX) {
+                    const double xr = (double)x[2 * (j * ldx + v)], xi = (double)x[2 * (j * ldx + v) + 1];
+                    acc_re[v] += (double)vre * xr - (double)vim * xi;
+                    acc_im[v] += (double)vre * xi + (double)vim * xr;
+                } else {
+                    acc_re[v] += (double)vre * (double)x[j * ldx + v];
+                }
+            }
+        }
+    });
+    if (!valid) return;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (v < nvec) {
+            if (CPLX) {
+                y[2 * (i * ldy + v)] = (ET)acc_re[v];
+                y[2 * (i * ldy + v) + 1] = (ET)acc_im[v];
+            } else {
+                y[i * ldy + v] = (ET)acc_re[v];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------- CSR
+
+template <int Wp>
+__global__ __launch_bounds__(kBlock) void k_csr_count(SubView s, HamView h, int64_t *__restrict__ counts) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = i < s.N;
+    const int64_t r = valid ? i : s.N - 1;
+    uint64_t key[Wp];
+#pragma unroll
+    for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + r];
+    int64_t cnt = 1;  // diagonal
+    row_groups<Wp, double, false>(s, h, key, s.hkey[r], valid, [&](int64_t, double, double) { ++cnt; });
+    if (valid) counts[i] = cnt;
+}
+
+// Work counters of one SpMV: probes issued (live groups that reach the hash table) and hits.
+template <int Wp>
+__global__ __launch_bounds__(kBlock) void k_probe_count(SubView s, HamView h, unsigned long long *__restrict__ acc) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = i < s.N;
+    const int64_t r = valid ? i : s.N - 1;
+    uint64_t key[Wp];
+#pragma unroll
+    for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + r];
+    const uint64_t hrow = s.hkey[r];
+    unsigned long long probes = 0, hits = 0;
+    for (int64_t g = 0; g < h.G; ++g) {
+        const uint32_t info = h.g_info[g];
+        uint32_t lo, hi;
+        bool live;
+        if (info & kInfoLadder) {
+            const uint64_t pos = h.g_pos[g];
+            uint32_t L = 0;
+            for (uint32_t j = 0; j < (info & kInfoKMask); ++j)
+                L |= row_bit<Wp>(key, (uint32_t)(pos >> (16 * j)) & 0xFFFFu) << j;
+            live = (info >> (16 + L)) & 1u;
+            lo = h.g_iptr[g * kIptr + L];
+            hi = h.g_iptr[g * kIptr + L + 1];
+        } else {
+            lo = 0;
+            hi = h.g_nterm[g];
+            live = true;
+        }
+        if (!live || !valid) continue;
+        const uint32_t t0 = h.g_term0[g];
+        if (info & kInfoCare) {
+            bool anyp = false;
+            for (uint32_t t = lo; t < hi && !anyp; ++t) anyp = term_pass<Wp>(key, h.t_cws + (int64_t)(t0 + t) * 3 * Wp);
+            if (!anyp) continue;
+        }
+        ++probes;
+        uint64_t col[Wp];
+#pragma unroll
+        for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ h.g_mask[g * Wp + w];
+        if (probe<Wp>(s, hrow ^ h.g_hash[g], col) >= 0) ++hits;
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        probes += __shfl_xor(probes, d, 64);
+        hits += __shfl_xor(hits, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&acc[0], probes);
+        atomicAdd(&acc[1], hits);
+    }
+}
+
+// Unsorted fill into scratch: columns (int64) and values (double2 / float2).
+template <int Wp, class ET>
+__global__ __launch_bounds__(kBlock) void k_csr_fill(SubView s, HamView h, const ET *__restrict__ dre,
+                                                     const ET *__restrict__ dim, const int64_t *__restrict__ indptr,
+                                                     int64_t *__restrict__ cols, typename C2<ET>::T *__restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = i < s.N;
+    const int64_t r = valid ? i : s.N - 1;
+    uint64_t key[Wp];
+#pragma unroll
+    for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + r];
+    int64_t o = indptr[r];
+    if (valid) {
+        cols[o] = i;
+        typename C2<ET>::T d;
+        d.x = dre[i];
+        d.y = dim ? dim[i] : (ET)0;
+        vals[o] = d;
+    }
+    ++o;
+    row_groups<Wp, ET, true>(s, h, key, s.hkey[r], valid, [&](int64_t j, ET vre, ET vim) {
+        typename C2<ET>::T v;
+        v.x = vre;
+        v.y = vim;
+        cols[o] = j;
+        vals[o] = v;
+        ++o;
+    });
+}
+
+// Sort each row's entries by column: one workgroup per row; for rows up to kSortLds entries
+// the columns sit in LDS and each thread ranks its elements by counting smaller columns
+// (columns within a row are distinct).  Longer rows rank against global memory.
+constexpr int kSortLds = 4096;
+
+template <class ET, class IT, bool CPLX>
+__global__ __launch_bounds__(kBlock) void k_csr_sort(const int64_t *__restrict__ indptr,
+                                                     const int64_t *__restrict__ cols,
+                                                     const typename C2<ET>::T *__restrict__ vals,
+                                                     IT *__restrict__ out_idx, ET *__restrict__ out_val) {
+    __shared__ int64_t sc[kSortLds];
+    const int64_t row = blockIdx.x;
+    const int64_t a = indptr[row], b = indptr[row + 1];
+    const int64_t len = b - a;
+    const bool in_lds = len <= kSortLds;
+    if (in_lds) {
+        for (int64_t e = threadIdx.x; e < len; e += kBlock) sc[e] = cols[a + e];
+        __syncthreads();
+    }
+    for (int64_t e = threadIdx.x; e < len; e += kBlock) {
+        const int64_t c = cols[a + e];
+        int64_t rank = 0;
+        if (in_lds) {
+            for (int64_t f = 0; f < len; ++f) rank += sc[f] < c;
+        } else {
+            for (int64_t f = 0; f < len; ++f) rank += cols[a + f] < c;
+        }
+        out_idx[a + rank] = (IT)c;
+        const typename C2<ET>::T v = vals[a + e];
+        if (CPLX) {
+            out_val[2 * (a + rank)] = v.x;
+            out_val[2 * (a + rank) + 1] = v.y;
+        } else {
+            out_val[a + rank] = v.x;
+        }
+    }
+}
+
+inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+HamView view_of(const qsd_ham *h, bool f32) {
+    return HamView{h->g_mask, h->g_hash, h->g_pos,  h->g_info, h->g_term0, h->g_nterm,
+                   h->g_iptr, h->t_cws,  f32 ? (const void *)h->t_coef32 : (const void *)h->t_coef, h->G};
+}
+
+SubView sview(const qsd_subspace *s) {
+    return SubView{s->keys, s->hkey, s->slots, s->bitmap, s->N, (uint32_t)(s->C - 1)};
+}
+
+template <class T>
+int upload(T **dst, const std::vector<T> &src, hipStream_t st) {
+    QSD_TRY(dev_alloc(dst, src.size()));
+    if (!src.empty()) QSD_CHECK_HIP(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return QSD_OK;
+}
+
+void free_ham(qsd_ham *h) {
+    if (!h) return;
+    dev_free(h->diag);
+    dev_free(h->diag_im);
+    dev_free(h->g_mask);
+    dev_free(h->g_hash);
+    dev_free(h->g_pos);
+    dev_free(h->g_info);
+    dev_free(h->g_term0);
+    dev_free(h->g_nterm);
+    dev_free(h->g_iptr);
+    dev_free(h->t_cws);
+    dev_free(h->t_coef);
+    dev_free(h->t_coef32);
+    dev_free(h->diag32);
+    dev_free(h->diag32_im);
+    delete h;
+}
+
+template <int Wp>
+void launch_diag(const qsd_ham *h, const uint64_t *cws, const double *coef, int64_t Td,
+                 hipStream_t st) {
+    k_diag<Wp><<<grid_for(h->N, kBlock), kBlock, 0, st>>>(sview(h->s), cws, coef, Td, h->diag, h->diag_im);
+}
+
+int create_impl(qsd_ham *h, hipStream_t st) {
+    const qsd_op *op = h->op;
+    QSD_TRY(upload(&h->g_mask, op->g_mask, st));
+    QSD_TRY(upload(&h->g_hash, op->g_hash, st));
+    QSD_TRY(upload(&h->g_pos, op->g_pos, st));
+    QSD_TRY(upload(&h->g_info, op->g_info, st));
+    QSD_TRY(upload(&h->g_term0, op->g_term0, st));
+    QSD_TRY(upload(&h->g_nterm, op->g_nterm, st));
+    QSD_TRY(upload(&h->g_iptr, op->g_iptr, st));
+    QSD_TRY(upload(&h->t_cws, op->t_cws, st));
+    QSD_TRY(upload(&h->t_coef, op->t_coef, st));
+    std::vector<float> c32(op->t_coef.size());
+    for (size_t k = 0; k < c32.size(); ++k) c32[k] = (float)op->t_coef[k];
+    QSD_TRY(upload(&h->t_coef32, c32, st));
+    QSD_TRY(dev_alloc(&h->diag, h->N));
+    QSD_TRY(dev_alloc(&h->diag32, h->N));
+    if (h->is_complex) {
+        QSD_TRY(dev_alloc(&h->diag_im, h->N));
+        QSD_TRY(dev_alloc(&h->diag32_im, h->N));
+    }
+    uint64_t *dcws = nullptr;
+    double *dcoef = nullptr;
+    const int64_t Td = (int64_t)op->diag_coef.size() / 2;
+    QSD_TRY(upload(&dcws, op->diag_cws, st));
+    int rc = upload(&dcoef, op->diag_coef, st);
+    if (rc == QSD_OK) {
+        switch (h->Wp) {
+            case 1: launch_diag<1>(h, dcws, dcoef, Td, st); break;
+            case 2: launch_diag<2>(h, dcws, dcoef, Td, st); break;
+            case 4: launch_diag<4>(h, dcws, dcoef, Td, st); break;
+            case 8: launch_diag<8>(h, dcws, dcoef, Td, st); break;
+            case 16: launch_diag<16>(h, dcws, dcoef, Td, st); break;
+        }
+        k_to_f32<<<1024, kBlock, 0, st>>>(h->diag, h->diag32, h->N);
+        if (h->is_complex) k_to_f32<<<1024, kBlock, 0, st>>>(h->diag_im, h->diag32_im, h->N);
+        if (hipStreamSynchronize(st) != hipSuccess)
+            rc = fail(QSD_ERR_HIP, "diagonal kernel failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    dev_free(dcws);
+    dev_free(dcoef);
+    return rc;
+}
+
+template <int Wp, int NV, class ET, bool CPLX>
+void launch_mv(const qsd_ham *h, const void *x, int64_t ldx, void *y, int64_t ldy, int nvec, hipStream_t st) {
+    const bool f32 = std::is_same<ET, float>::value;
+    const ET *dre = f32 ? (const ET *)h->diag32 : (const ET *)h->diag;
+    const ET *dim = CPLX ? (f32 ? (const ET *)h->diag32_im : (const ET *)h->diag_im) : nullptr;
+    k_matvec<Wp, NV, ET, CPLX><<<grid_for(h->N, kBlock), kBlock, 0, st>>>(sview(h->s), view_of(h, f32), dre, dim,
+                                                                          (const ET *)x, ldx, (ET *)y, ldy, nvec);
+}
+
+template <int Wp, class ET, bool CPLX>
+void dispatch_nv(const qsd_ham *h, const void *x, int64_t ldx, void *y, int64_t ldy, int nvec, hipStream_t st) {
+    if (nvec <= 1)
+        launch_mv<Wp, 1, ET, CPLX>(h, x, ldx, y, ldy, nvec, st);
+    else if (nvec <= 2)
+        launch_mv<Wp, 2, ET, CPLX>(h, x, ldx, y, ldy, nvec, st);
+    else if (nvec <= 4 || CPLX)
+        launch_mv<Wp, 4, ET, CPLX>(h, x, ldx, y, ldy, nvec, st);
+    else if (nvec <= 8)
+        launch_mv<Wp, CPLX ? 4 : 8, ET, CPLX>(h, x, ldx, y, ldy, nvec, st);
+    else
+        launch_mv<Wp, CPLX ? 4 : 16, ET, CPLX>(h, x, ldx, y, ldy, nvec, st);
+}
+
+template <class ET, bool CPLX>
+void dispatch_w(const qsd_ham *h, const void *x, int64_t ldx, void *y, int64_t ldy, int nvec, hipStream_t st) {
+    switch (h->Wp) {
+        case 1: dispatch_nv<1, ET, CPLX>(h, x, ldx, y, ldy, nvec, st); break;
+        case 2: dispatch_nv<2, ET, CPLX>(h, x, ldx, y, ldy, nvec, st); break;
+        case 4: dispatch_nv<4, ET, CPLX>(h, x, ldx, y, ldy, nvec, st); break;
+        case 8: dispatch_nv<8, ET, CPLX>(h, x, ldx, y, ldy, nvec, st); break;
+        case 16: dispatch_nv<16, ET, CPLX>(h, x, ldx, y, ldy, nvec, st); break;
+    }
+}
+
+template <int Wp>
+void launch_count(const qsd_ham *h, int64_t *counts, hipStream_t st) {
+    k_csr_count<Wp><<<grid_for(h->N, kBlock), kBlock, 0, st>>>(sview(h->s), view_of(h, false), counts);
+}
+
+template <int Wp, class ET>
+void launch_fill(const qsd_ham *h, const int64_t *indptr, int64_t *cols, void *vals, hipStream_t st) {
+    const bool f32 = std::is_same<ET, float>::value;
+    const ET *dre = f32 ? (const ET *)h->diag32 : (const ET *)h->diag;
+    const ET *dim = h->is_complex ? (f32 ? (const ET *)h->diag32_im : (const ET *)h->diag_im) : nullptr;
+    k_csr_fill<Wp, ET><<<grid_for(h->N, kBlock), kBlock, 0, st>>>(sview(h->s), view_of(h, f32), dre, dim, indptr, cols,
+                                                                   (typename C2<ET>::T *)vals);
+}
+
+template <class ET>
+void fill_w(const qsd_ham *h, const int64_t *indptr, int64_t *cols, void *vals, hipStream_t st) {
+    switch (h->Wp) {
+        case 1: launch_fill<1, ET>(h, indptr, cols, vals, st); break;
+        case 2: launch_fill<2, ET>(h, indptr, cols, vals, st); break;
+        case 4: launch_fill<4, ET>(h, indptr, cols, vals, st); break;
+        case 8: launch_fill<8, ET>(h, indptr, cols, vals, st); break;
+        case 16: launch_fill<16, ET>(h, indptr, cols, vals, st); break;
+    }
+}
+
+int check_dtype(const qsd_ham *h, int32_t dtype) {
+    if (dtype < QSD_F64 || dtype > QSD_C64) return fail(QSD_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+    const bool want_c = dtype == QSD_C128 || dtype == QSD_C64;
+    if (want_c != h->is_complex)
+        return fail(QSD_ERR_DTYPE, "dtype %d does not match a %s operator", dtype, h->is_complex ? "complex" : "real");
+    return QSD_OK;
+}
+
+}  // namespace
+}  // namespace qsd
+
+using namespace qsd;
+
+extern "C" int qsd_ham_create(const qsd_subspace *s, const qsd_op *op, uint32_t flags, void *stream, qsd_ham **out) {
+    clear_error();
+    if (!out) return fail(QSD_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!s || !op) return fail(QSD_ERR_INVALID_ARG, "NULL subspace or operator");
+    if (s->n_qubits != op->n_qubits)
+        return fail(QSD_ERR_INVALID_ARG, "subspace has %d qubits, operator %d", s->n_qubits, op->n_qubits);
+    (void)flags;
+    auto *h = new (std::nothrow) qsd_ham();
+    if (!h) return fail(QSD_ERR_OUT_OF_MEMORY, "host allocation failed");
+    h->s = s;
+    h->op = op;
+    h->N = s->N;
+    h->G = (int64_t)op->g_info.size();
+    h->Wp = s->Wp;
+    h->is_complex = op->is_complex;
+    int rc = create_impl(h, (hipStream_t)stream);
+    if (rc != QSD_OK) {
+        free_ham(h);
+        return rc;
+    }
+    *out = h;
+    return QSD_OK;
+}
+
+extern "C" int qsd_ham_info(const qsd_ham *h, int64_t *N, int64_t *G, int32_t *is_complex) {
+    clear_error();
+    if (!h) return fail(QSD_ERR_INVALID_ARG, "ham is NULL");
+    if (N) *N = h->N;
+    if (G) *G = h->G + 1;
+    if (is_complex) *is_complex = h->is_complex ? 1 : 0;
+    return QSD_OK;
+}
+
+extern "C" int qsd_ham_diagonal(const qsd_ham *h, double *d_out, void *stream) {
+    clear_error();
+    if (!h || !d_out) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+    QSD_CHECK_HIP(hipMemcpyAsync(d_out, h->diag, h->N * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return QSD_OK;
+}
+
+extern "C" int qsd_ham_destroy(qsd_ham *h) {
+    clear_error();
+    free_ham(h);
+    return QSD_OK;
+}
+
+extern "C" int qsd_matvec(const qsd_ham *h, int32_t nvec, const void *d_x, int64_t ldx, void *d_y, int64_t ldy,
+                          int32_t dtype, void *stream) {
+    clear_error();
+    if (!h || !d_x || !d_y) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+    if (nvec < 1 || nvec > 16) return fail(QSD_ERR_INVALID_ARG, "nvec must be in [1, 16]");
+    if (ldx < nvec || ldy < nvec) return fail(QSD_ERR_INVALID_ARG, "leading dimension smaller than nvec");
+    QSD_TRY(check_dtype(h, dtype));
+    hipStream_t st = (hipStream_t)stream;
+    const int chunk = (dtype == QSD_C128 || dtype == QSD_C64) ? 4 : 16;
+    const size_t esz = dtype == QSD_F64 ? 8 : dtype == QSD_F32 ? 4 : dtype == QSD_C128 ? 16 : 8;
+    for (int v0 = 0; v0 < nvec; v0 += chunk) {
+        const int nv = std::min(chunk, nvec - v0);
+        const void *x = (const char *)d_x + v0 * esz;
+        void *y = (char *)d_y + v0 * esz;
+        switch (dtype) {
+            case QSD_F64: dispatch_w<double, false>(h, x, ldx, y, ldy, nv, st); break;
+            case QSD_F32: dispatch_w<float, false>(h, x, ldx, y, ldy, nv, st); break;
+            case QSD_C128: dispatch_w<double, true>(h, x, ldx, y, ldy, nv, st); break;
+            case QSD_C64: dispatch_w<float, true>(h, x, ldx, y, ldy, nv, st); break;
+        }
+    }
+    QSD_CHECK_HIP(hipGetLastError());
+    return QSD_OK;
+}
+
+extern "C" int qsd_csr_build(const qsd_ham *h, int64_t *d_indptr, void *d_indices, void *d_data, int32_t index_type,
+                             int32_t dtype, int64_t *nnz_out, void *stream) {
+    clear_error();
+    if (!h || !d_indptr) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+    if (index_type != QSD_INDEX_I32 && index_type != QSD_INDEX_I64)
+        return fail(QSD_ERR_INVALID_ARG, "unknown index type %d", index_type);
+    if (index_type == QSD_INDEX_I32 && h->N >= (1ll << 31))
+        return fail(QSD_ERR_CAPACITY, "N = %lld does not fit int32 column indices", (long long)h->N);
+    QSD_TRY(check_dtype(h, dtype));
+    hipStream_t st = (hipStream_t)stream;
+    const bool fill = d_indices && d_data;
+    if ((d_indices == nullptr) != (d_data == nullptr))
+        return fail(QSD_ERR_INVALID_ARG, "indices and data must both be NULL (count) or both set (fill)");
+    if (!fill) {
+        int64_t *counts = nullptr;
+        QSD_TRY(dev_alloc(&counts, h->N + 1));
+        switch (h->Wp) {
+            case 1: launch_count<1>(h, counts, st); break;
+            case 2: launch_count<2>(h, counts, st); break;
+            case 4: launch_count<4>(h, counts, st); break;
+            case 8: launch_count<8>(h, counts, st); break;
+            case 16: launch_count<16>(h, counts, st); break;
+        }
+        int64_t zero = 0;
+        int rc = QSD_OK;
+        if (hipMemcpyAsync(counts + h->N, &zero, 8, hipMemcpyHostToDevice, st) != hipSuccess)
+            rc = fail(QSD_ERR_HIP, "copy failed");
+        if (rc == QSD_OK) rc = exclusive_scan_i64(counts, d_indptr, h->N + 1, st);
+        int64_t nnz = 0;
+        if (rc == QSD_OK && (hipMemcpyAsync(&nnz, d_indptr + h->N, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                             hipStreamSynchronize(st) != hipSuccess))
+            rc = fail(QSD_ERR_HIP, "CSR count failed: %s", hipGetErrorString(hipGetLastError()));
+        dev_free(counts);
+        if (rc == QSD_OK && nnz_out) *nnz_out = nnz;
+        return rc;
+    }
+    int64_t nnz = 0;
+    QSD_CHECK_HIP(hipMemcpyAsync(&nnz, d_indptr + h->N, 8, hipMemcpyDeviceToHost, st));
+    QSD_CHECK_HIP(hipStreamSynchronize(st));
+    const bool f32 = dtype == QSD_F32 || dtype == QSD_C64;
+    int64_t *cols = nullptr;
+    void *vals = nullptr;
+    QSD_TRY(dev_alloc(&cols, nnz));
+    int rc = f32 ? dev_alloc((float2 **)&vals, nnz) : dev_alloc((double2 **)&vals, nnz);
+    if (rc == QSD_OK) {
+        if (f32)
+            fill_w<float>(h, d_indptr, cols, vals, st);
+        else
+            fill_w<double>(h, d_indptr, cols, vals, st);
+        const unsigned grid = (unsigned)h->N;
+        const bool cx = h->is_complex;
+        if (index_type == QSD_INDEX_I32) {
+            if (f32) {
+                if (cx) k_csr_sort<float, int32_t, true><<<grid, kBlock, 0, st>>>(d_indptr, cols, (const float2 *)vals, (int32_t *)d_indices, (float *)d_data);
+                else k_csr_sort<float, int32_t, false><<<grid, kBlock, 0, st>>>(d_indptr, cols, (const float2 *)vals, (int32_t *)d_indices, (float *)d_data);
+            } else {
+                if (cx) k_csr_sort<double, int32_t, true><<<grid, kBlock, 0, st>>>(d_indptr, cols, (const double2 *)vals, (int32_t *)d_indices, (double *)d_data);
+                else k_csr_sort<double, int32_t, false><<<grid, kBlock, 0, st>>>(d_indptr, cols, (const double2 *)vals, (int32_t *)d_indices, (double *)d_data);
+            }
+        } else {
+            if (f32) {
+                if (cx) k_csr_sort<float, int64_t, true><<<grid, kBlock, 0, st>>>(d_indptr, cols, (const float2 *)vals, (int64_t *)d_indices, (float *)d_data);
+                else k_csr_sort<float, int64_t, false><<<grid, kBlock, 0, st>>>(d_indptr, cols, (const float2 *)vals, (int64_t *)d_indices, (float *)d_data);
+            } else {
+                if (cx) k_csr_sort<double, int64_t, true><<<grid, kBlock, 0, st>>>(d_indptr, cols, (const double2 *)vals, (int64_t *)d_indices, (double *)d_data);
+                else k_csr_sort<double, int64_t, false><<<grid, kBlock, 0, st>>>(d_indptr, cols, (const double2 *)vals, (int64_t *)d_indices, (double *)d_data);
+            }
+        }
+        if (hipStreamSynchronize(st) != hipSuccess)
+            rc = fail(QSD_ERR_HIP, "CSR fill failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    dev_free(cols);
+    if (vals) (void)hipFree(vals);
+    if (nnz_out) *nnz_out = nnz;
+    return rc;
+}
+
+extern "C" int qsd_ham_work_counts(const qsd_ham *h, int64_t *probes, int64_t *hits, void *stream) {
+    clear_error();
+    if (!h) return fail(QSD_ERR_INVALID_ARG, "ham is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    unsigned long long *acc = nullptr;
+    QSD_TRY(dev_alloc(&acc, 2));
+    unsigned long long hv[2] = {0, 0};
+    int rc = QSD_OK;
+    if (hipMemcpyAsync(acc, hv, 16, hipMemcpyHostToDevice, st) != hipSuccess) rc = fail(QSD_ERR_HIP, "copy failed");
+    if (rc == QSD_OK) {
+        const unsigned g = grid_for(h->N, kBlock);
+        switch (h->Wp) {
+            case 1: k_probe_count<1><<<g, kBlock, 0, st>>>(sview(h->s), view_of(h, false), acc); break;
+            case 2: k_probe_count<2><<<g, kBlock, 0, st>>>(sview(h->s), view_of(h, false), acc); break;
+            case 4: k_probe_count<4><<<g, kBlock, 0, st>>>(sview(h->s), view_of(h, false), acc); break;
+            case 8: k_probe_count<8><<<g, kBlock, 0, st>>>(sview(h->s), view_of(h, false), acc); break;
+            case 16: k_probe_count<16><<<g, kBlock, 0, st>>>(sview(h->s), view_of(h, false), acc); break;
+        }
+        if (hipMemcpyAsync(hv, acc, 16, hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+            rc = fail(QSD_ERR_HIP, "work count failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    dev_free(acc);
+    if (rc != QSD_OK) return rc;
+    if (probes) *probes = (int64_t)hv[0];
+    if (hits) *hits = (int64_t)hv[1];
+    return QSD_OK;
+}

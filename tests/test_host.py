@@ -1,0 +1,185 @@
+"""Host-side tests of the library (no GPU): exported symbols, and the operator compiler
+(fermion ordering/merging, extended Jordan-Wigner, combining, grouping) against the oracle's
+dense routes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import dense as ode
+from oracle import fermion as ofe
+
+qsd = pytest.importorskip("paper_2603_18731_amd")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _lib_or_skip():
+    if not os.path.exists(qsd.LIB_PATH):
+        pytest.skip("libqsd.so not built")
+    return qsd.lib()
+
+
+def test_header_symbols_exported():
+    _lib_or_skip()
+    hdr = open(os.path.join(ROOT, "include", "qsd.h")).read()
+    declared = sorted(set(re.findall(r"\b(qsd_[a-z0-9_]+)\s*\(", hdr)))
+    assert len(declared) >= 20
+    lib = ctypes.CDLL(qsd.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(qsd.EXPORTED) <= set(declared)
+
+
+def _export_terms(op):
+    tp, oi, oc, coef, gp, gl = op.export()
+    terms = []
+    for t in range(len(coef)):
+        word = list(zip(oi[tp[t]:tp[t + 1]].tolist(), oc[tp[t]:tp[t + 1]].tolist()))
+        terms.append((coef[t], word))
+    return terms, gp, gl
+
+
+def _random_qubit_tl(rng, n, nterms):
+    terms = []
+    for _ in range(nterms):
+        m = int(rng.integers(0, 5))
+        qs = rng.choice(n, size=m, replace=False)
+        word = [(int(q), int(rng.integers(0, 7))) for q in qs]  # unsorted on purpose
+        terms.append((complex(rng.normal(), rng.normal()), word))
+    # duplicates to exercise combining
+    terms += [(complex(rng.normal()), w) for _, w in terms[:5]]
+    return wl.TermList.from_terms(n, terms)
+
+
+def _random_fermion_tl(rng, n, nterms):
+    terms = []
+    for _ in range(nterms):
+        m = int(rng.integers(1, 5))
+        ops = [(int(rng.integers(0, n)), int(rng.integers(5, 7))) for _ in range(m)]
+        terms.append((complex(rng.normal(), rng.normal()), ops))
+    return wl.TermList.from_terms(n, terms, fermionic=True)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_compile_qubit_matches_dense(seed):
+    _lib_or_skip()
+    rng = np.random.default_rng(seed)
+    n = 6
+    tl = _random_qubit_tl(rng, n, 40)
+    op = qsd.QubitOperator.from_termlist(tl)
+    terms, gp, gl = _export_terms(op)
+    A = ode.qubit_hamiltonian(n, list(tl.terms())).toarray()
+    B = ode.qubit_hamiltonian(n, terms).toarray()
+    np.testing.assert_allclose(B, A, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_compile_fermion_matches_dense(seed):
+    _lib_or_skip()
+    rng = np.random.default_rng(100 + seed)
+    n = 6
+    tl = _random_fermion_tl(rng, n, 60)
+    op = qsd.FermionicOperator.from_termlist(tl)
+    terms, gp, gl = _export_terms(op)
+    for _, w in terms:
+        assert all(k in (0, 1, 2, 5, 6) for _, k in w)  # JW output alphabet {Z, 0, 1, -, +}
+    A = ofe.dense_hamiltonian(n, list(tl.terms())).toarray()
+    B = ode.qubit_hamiltonian(n, terms).toarray()
+    np.testing.assert_allclose(B, A, atol=1e-12)
+
+
+def test_merge_rules_through_compiler():
+    """Single-mode products of two letters compile to the Table S1 result."""
+    _lib_or_skip()
+    code = {"-": 5, "+": 6}
+    letter_of = {5: "-", 6: "+", 1: "0", 2: "1"}
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "merge_rules.txt")) if ln.strip() and ln[0] != "#"]
+    for a, b, res in rows:
+        if a not in code or b not in code:
+            continue  # projector inputs are not fermionic letters
+        tl = wl.TermList.from_terms(3, [(1.0, [(1, code[a]), (1, code[b])])], fermionic=True)
+        op = qsd.FermionicOperator.from_termlist(tl)
+        terms, _, _ = _export_terms(op)
+        if res == "null":
+            assert terms == []
+        else:
+            assert len(terms) == 1 and terms[0][1] == [(1, {"-": 5, "+": 6, "0": 1, "1": 2}[res])]
+            assert terms[0][0] == 1.0
+    # three-operator products reproduce the projector rows, e.g. (f f^+) f = '0-' -> '-'
+    for seq, res in (((5, 6, 5), 5), ((6, 5, 6), 6), ((5, 6, 5, 6), 1), ((6, 5, 6, 5), 2)):
+        tl = wl.TermList.from_terms(2, [(1.0, [(0, c) for c in seq])], fermionic=True)
+        terms, _, _ = _export_terms(qsd.FermionicOperator.from_termlist(tl))
+        assert terms == [(1.0, [(0, res)])], (seq, terms)
+
+
+def test_grouping_invariants():
+    _lib_or_skip()
+    rng = np.random.default_rng(3)
+    tl = _random_fermion_tl(rng, 8, 200)
+    op = qsd.FermionicOperator.from_termlist(tl)
+    terms, gp, gl = _export_terms(op)
+    assert gp[0] == 0 and gp[-1] == len(terms)
+
+    def off(word):
+        return sum(1 << q for q, k in word if k > 2)
+
+    for t in range(gp[0], gp[1]):
+        assert off(terms[t][1]) == 0
+    keys = []
+    for g in range(1, len(gp) - 1):
+        masks = {off(terms[t][1]) for t in range(gp[g], gp[g + 1])}
+        assert len(masks) == 1
+        m = masks.pop()
+        assert m != 0
+        keys.append((bin(m).count("1"), m))
+        if gl[g]:
+            qs = [q for q in range(64) if m >> q & 1]
+            lints = []
+            for t in range(gp[g], gp[g + 1]):
+                w = dict(terms[t][1])
+                lints.append(sum((1 << k) for k, q in enumerate(qs) if w[q] == 6))
+            assert lints == sorted(lints)
+    assert keys == sorted(keys) and len(set(keys)) == len(keys)
+
+
+def test_compile_errors():
+    _lib_or_skip()
+    with pytest.raises(qsd.QsdError, match="INVALID_ARG"):
+        qsd.QubitOperator(3, [0, 2], [1, 1], [0, 3], [1.0])  # repeated qubit
+    with pytest.raises(qsd.QsdError, match="INVALID_ARG"):
+        qsd.QubitOperator(3, [0, 1], [3], [0], [1.0])  # index >= n
+    with pytest.raises(qsd.QsdError, match="INVALID_ARG"):
+        qsd.QubitOperator(3, [0, 1], [0], [9], [1.0])  # bad code
+    with pytest.raises(qsd.QsdError, match="NOT_HERMITIAN"):
+        qsd.QubitOperator(3, [0, 1], [0], [6], [1.0], check_hermitian=True)  # lone raising letter
+    herm = wl.TermList.from_terms(3, [(0.5, [(0, 6), (2, 5)]), (0.5, [(0, 5), (2, 6)]), (1.0, [(0, 4), (1, 4)])])
+    op = qsd.QubitOperator.from_termlist(herm, check_hermitian=True)
+    assert not op.is_complex  # c * (-i)^{#Y}: the YY term's elements are real
+    op = qsd.QubitOperator(3, [0, 1], [1], [4], [1.0], check_hermitian=True)
+    assert op.is_complex  # a single Y has imaginary elements
+    tl = wl.TermList.from_terms(3, [(1j, [(1, 3)]), (-1j, [(1, 3)])])
+    op = qsd.QubitOperator.from_termlist(tl)
+    assert op.n_terms == 1  # cancelled words are kept
+
+
+def test_molecular_compile_sizes():
+    _lib_or_skip()
+    h, eri = wl.molecular_integrals(16, seed=3)
+    tl = wl.molecular_terms(h, eri)
+    op = qsd.FermionicOperator.from_termlist(tl, check_hermitian=True)
+    tp, oi, oc, coef, gp, gl = op.export()
+    diag_terms = int(gp[1] - gp[0])
+    sizes = np.diff(gp[1:])
+    # number-conserving one- and two-body terms: off-diagonal structure on 2 or 4 qubits, all
+    # groups with ladder ranges
+    assert op.n_groups - 1 == 240 + 18040
+    assert diag_terms == 528
+    assert op.n_terms == 94848
+    assert gl[1:].all()
+    assert not op.is_complex
+    assert sizes.max() == 62
