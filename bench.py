@@ -95,6 +95,7 @@ def main():
     ap.add_argument("--workload", default="xxz6x6")
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--nvec", type=int, default=1)
+    ap.add_argument("--max-load", type=float, default=0.0, help="hash load factor (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     args = ap.parse_args()
@@ -114,7 +115,7 @@ def main():
     w = make_workload(args.workload)
     print("# workload %s: %d strings, %d qubits" % (w.name, w.keys.shape[0], w.ops.n_qubits), file=sys.stderr,
           flush=True)
-    sub = qsd.Subspace(w.keys, w.ops.n_qubits)
+    sub = qsd.Subspace(w.keys, w.ops.n_qubits, max_load=args.max_load)
     op = qsd.operator_from_termlist(w.ops)
     H = qsd.SubspaceHamiltonian(sub, op)
     N, W = sub.N, sub.W

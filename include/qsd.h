@@ -98,7 +98,8 @@ int qsd_version(void);
  *   n_in      number of input strings (>= 1).
  *   n_qubits  >= 1.  W = ceil(n_qubits / 64).
  *   flags     QSD_SUB_* bits.
- *   max_load  hash load factor in (0, 0.5]; 0 selects 0.5.
+ *   max_load  hash load factor in (0, 0.5]; 0 selects 0.125 (a low load lets most absent strings
+ *             stop at an empty occupancy bit).
  *   out       receives the new handle.
  *   Synchronizes `stream` (the unique count N is read back).  Errors: INVALID_ARG if n_in < 1,
  *   n_qubits < 1, a bit >= n_qubits is set, or max_load is out of range; CAPACITY if

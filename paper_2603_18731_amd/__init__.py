@@ -145,7 +145,7 @@ def _device_tensor(a, dtype=None):
 class Subspace:
     """Canonical bit-string subspace on the device (Methods, Subspace data structure)."""
 
-    def __init__(self, bits, n_qubits: int, max_load: float = 0.5, assume_sorted_unique: bool = False, stream=None):
+    def __init__(self, bits, n_qubits: int, max_load: float = 0.0, assume_sorted_unique: bool = False, stream=None):
         import torch
 
         b = _device_tensor(bits)

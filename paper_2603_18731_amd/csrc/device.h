@@ -40,6 +40,24 @@ __device__ __forceinline__ int64_t probe(const SubView &s, uint64_t h, const uin
     }
 }
 
+// Continues a probe at slot `pos` (known occupied or not) for a string with tag `tag`.
+template <int Wp>
+__device__ __forceinline__ int64_t probe_from(const SubView &s, uint32_t pos, uint32_t tag, const uint64_t (&col)[Wp]) {
+    while (true) {
+        const uint32_t word = s.bitmap[pos >> 5];
+        if (!((word >> (pos & 31)) & 1u)) return -1;
+        const uint64_t slot = s.slots[pos];
+        if ((uint32_t)(slot >> 32) == tag) {
+            const uint32_t r = (uint32_t)slot;
+            bool eq = true;
+#pragma unroll
+            for (int w = 0; w < Wp; ++w) eq &= (s.keys[(int64_t)w * s.N + r] == col[w]);
+            if (eq) return (int64_t)r;
+        }
+        pos = (pos + 1) & s.cmask;
+    }
+}
+
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
 
 }  // namespace qsd

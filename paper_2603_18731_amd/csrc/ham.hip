@@ -24,6 +24,8 @@
 namespace qsd {
 namespace {
 
+constexpr int kMlpBatch = 8;  // groups whose probes are in flight together
+
 struct HamView {
     const uint64_t *__restrict__ g_mask;
     const uint64_t *__restrict__ g_hash;
@@ -135,6 +137,122 @@ __device__ __forceinline__ void row_groups(const SubView &s, const HamView &h, c
     }
 }
 
+// Evaluates the terms of group g for a row with ladder integer L (ladder groups) or all terms
+// (other groups): sum of c'_t (-1)^popcount(row & S_t) over terms whose projector bits match.
+template <int Wp, class ET>
+__device__ __forceinline__ bool group_value(const HamView &h, const uint64_t (&key)[Wp], int64_t g, uint32_t info,
+                                            uint32_t L, ET &vre, ET &vim) {
+    using CT = typename C2<ET>::T;
+    const CT *__restrict__ coef = (const CT *)h.t_coef;
+    uint32_t lo, hi;
+    if (info & kInfoLadder) {
+        lo = h.g_iptr[g * kIptr + L];
+        hi = h.g_iptr[g * kIptr + L + 1];
+    } else {
+        lo = 0;
+        hi = h.g_nterm[g];
+    }
+    const uint32_t t0 = h.g_term0[g];
+    bool any = false;
+    vre = 0;
+    vim = 0;
+    for (uint32_t t = lo; t < hi; ++t) {
+        const uint64_t *cws = h.t_cws + (int64_t)(t0 + t) * 3 * Wp;
+        if (!term_pass<Wp>(key, cws)) continue;
+        any = true;
+        const CT c = coef[t0 + t];
+        if (term_parity<Wp>(key, cws)) {
+            vre -= c.x;
+            vim -= c.y;
+        } else {
+            vre += c.x;
+            vim += c.y;
+        }
+    }
+    return any;
+}
+
+// Same walk as row_groups, reorganized for memory-level parallelism: B groups at a time, each
+// phase issues its independent loads for all B groups before consuming any (ladder integers
+// and hashes; occupancy words; first slots; key compares), so a wave keeps up to B probes in
+// flight instead of one.  Probes that find their first slot occupied by another key continue
+// along the run with the serial probe.  Hits are consumed in group order, so the row sum is
+// formed in the same order as row_groups.  The projector refinement follows the lookup (the
+// paper's order); an element whose terms all fail contributes nothing.
+template <int Wp, class ET, int B, class OnHit>
+__device__ __forceinline__ void row_groups_mlp(const SubView &s, const HamView &h, const uint64_t (&key)[Wp],
+                                               uint64_t hrow, bool valid, OnHit &&on_hit) {
+    for (int64_t g0 = 0; g0 < h.G; g0 += B) {
+        uint32_t pos[B], Lv[B];
+        bool live[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int64_t g = g0 + b;
+            live[b] = false;
+            pos[b] = 0;
+            Lv[b] = 0;
+            if (g < h.G) {
+                const uint32_t info = h.g_info[g];
+                bool lv = true;
+                if (info & kInfoLadder) {
+                    const uint64_t gp = h.g_pos[g];
+                    uint32_t L = 0;
+                    for (uint32_t j = 0; j < (info & kInfoKMask); ++j)
+                        L |= row_bit<Wp>(key, (uint32_t)(gp >> (16 * j)) & 0xFFFFu) << j;
+                    lv = (info >> (16 + L)) & 1u;
+                    Lv[b] = L;
+                }
+                live[b] = lv && valid;
+                pos[b] = (uint32_t)(hrow ^ h.g_hash[g]) & s.cmask;
+            }
+        }
+        uint32_t word[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) word[b] = live[b] ? s.bitmap[pos[b] >> 5] : 0u;
+        uint64_t slot[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            live[b] = live[b] && ((word[b] >> (pos[b] & 31u)) & 1u);
+            slot[b] = live[b] ? s.slots[pos[b]] : ~0ull;
+        }
+        int64_t jv[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            jv[b] = -1;
+            if (!live[b]) continue;
+            const int64_t g = g0 + b;
+            const uint64_t hh = hrow ^ h.g_hash[g];
+            const uint32_t tag = (uint32_t)(hh >> 32);
+            if ((uint32_t)(slot[b] >> 32) == tag) {
+                const uint32_t r = (uint32_t)slot[b];
+                bool eq = true;
+#pragma unroll
+                for (int w = 0; w < Wp; ++w) eq &= s.keys[(int64_t)w * s.N + r] == (key[w] ^ h.g_mask[g * Wp + w]);
+                if (eq) {
+                    jv[b] = r;
+                    continue;
+                }
+            }
+            // first slot taken by another key: continue the run if the next slot is occupied
+            const uint32_t nxt = (pos[b] + 1) & s.cmask;
+            const uint32_t nw = ((nxt >> 5) == (pos[b] >> 5)) ? word[b] : s.bitmap[nxt >> 5];
+            if ((nw >> (nxt & 31u)) & 1u) {
+                uint64_t col[Wp];
+#pragma unroll
+                for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ h.g_mask[g * Wp + w];
+                jv[b] = probe_from<Wp>(s, nxt, tag, col);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            if (jv[b] < 0) continue;
+            const int64_t g = g0 + b;
+            ET vre, vim;
+            if (group_value<Wp, ET>(h, key, g, h.g_info[g], Lv[b], vre, vim)) on_hit(jv[b], vre, vim);
+        }
+    }
+}
+
 // ----------------------------------------------------------------------------- diagonal
 
 template <int Wp>
@@ -201,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec(SubView s, HamView h, const E
             }
         }
     }
-    row_groups<Wp, ET, true>(s, h, key, hrow, valid, [&](int64_t j, ET vre, ET vim) {
+    row_groups_mlp<Wp, ET, kMlpBatch>(s, h, key, hrow, valid, [&](int64_t j, ET vre, ET vim) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if (v < nvec) {

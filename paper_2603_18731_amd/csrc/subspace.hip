@@ -455,7 +455,7 @@ extern "C" int qsd_subspace_build(const uint64_t *d_bits, int64_t n_in, int32_t 
     if (!d_bits || n_in < 1) return fail(QSD_ERR_INVALID_ARG, "empty subspace (n_in = %lld)", (long long)n_in);
     if (n_qubits < 1) return fail(QSD_ERR_INVALID_ARG, "n_qubits must be >= 1");
     if (n_qubits > kMaxWords * 64) return fail(QSD_ERR_UNSUPPORTED, "n_qubits > %d", kMaxWords * 64);
-    if (max_load == 0.0) max_load = 0.5;
+    if (max_load == 0.0) max_load = 0.125;
     if (!(max_load > 0.0 && max_load <= 0.5)) return fail(QSD_ERR_INVALID_ARG, "max_load must be in (0, 0.5]");
     auto *sub = new (std::nothrow) qsd_subspace();
     if (!sub) return fail(QSD_ERR_OUT_OF_MEMORY, "host allocation failed");
