@@ -1,257 +1,15 @@
 // Subspace Hamiltonian on the device: cached diagonal, matrix-free SpMV / SpMM and the
-// two-pass CSR builder (Methods, Matrix evaluation).
-//
-// Row engine.  One lane owns one row bit-string; the 64 lanes of a wavefront walk the group
-// list in lockstep, so every group descriptor is a wave-uniform (scalar) load.  For each
-// group a lane
-//   1. forms its ladder integer from the row bits at the group's ladder qubits and takes the
-//      term range int_ptrs[L] .. int_ptrs[L+1]; an empty range skips the group with no probe
-//      (Methods, Fermionic Hamiltonians);
-//   2. if some term in range also constrains other qubits (projectors), tests those bits
-//      first and skips the group when every term fails;
-//   3. probes the hash table for col = row ^ mask: the row's hash XOR the group's hash (the
-//      hash is linear over GF(2)), occupancy bit first, then {tag, index} slots, then a key
-//      compare (Methods, Subspace data structure);
-//   4. on a hit sums c'_t (-1)^popcount(row & S_t) over the terms in range whose projector
-//      bits match (Methods, Matrix evaluation).
-// Groups where no lane of the wave is live are skipped by a wave vote.
+// two-pass CSR builder (Methods, Matrix evaluation).  The row walk itself is in engine.h.
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
 #include "device.h"
+#include "engine.h"
 
 namespace qsd {
 namespace {
-
-constexpr int kMlpBatch = 8;  // groups whose probes are in flight together
-
-struct HamView {
-    const uint64_t *__restrict__ g_mask;
-    const uint64_t *__restrict__ g_hash;
-    const uint64_t *__restrict__ g_pos;
-    const uint32_t *__restrict__ g_info;
-    const uint32_t *__restrict__ g_term0;
-    const uint32_t *__restrict__ g_nterm;
-    const uint16_t *__restrict__ g_iptr;
-    const uint64_t *__restrict__ t_cws;
-    const void *__restrict__ t_coef;  // double2 or float2 per term
-    int64_t G;
-};
-
-template <int Wp>
-__device__ __forceinline__ uint32_t row_bit(const uint64_t (&k)[Wp], uint32_t p) {
-    uint64_t w = k[0];
-#pragma unroll
-    for (int i = 1; i < Wp; ++i)
-        if ((p >> 6) == (uint32_t)i) w = k[i];
-    const uint32_t half = (p & 32u) ? (uint32_t)(w >> 32) : (uint32_t)w;
-    return (half >> (p & 31u)) & 1u;
-}
-
-template <int Wp>
-__device__ __forceinline__ bool term_pass(const uint64_t (&k)[Wp], const uint64_t *__restrict__ cws) {
-    bool ok = true;
-#pragma unroll
-    for (int w = 0; w < Wp; ++w) ok &= (k[w] & cws[w]) == cws[Wp + w];
-    return ok;
-}
-
-template <int Wp>
-__device__ __forceinline__ uint32_t term_parity(const uint64_t (&k)[Wp], const uint64_t *__restrict__ cws) {
-    uint32_t c = 0;
-#pragma unroll
-    for (int w = 0; w < Wp; ++w) c += (uint32_t)__popcll(k[w] & cws[2 * Wp + w]);
-    return c & 1u;
-}
-
-template <class ET>
-struct C2;
-template <>
-struct C2<double> {
-    using T = double2;
-};
-template <>
-struct C2<float> {
-    using T = float2;
-};
-
-// Walks the groups of one row and calls on_hit(j, re, im) for every present off-diagonal
-// entry (j = column index).  NEED_VALUE = false skips the value arithmetic (CSR count).
-template <int Wp, class ET, bool NEED_VALUE, class OnHit>
-__device__ __forceinline__ void row_groups(const SubView &s, const HamView &h, const uint64_t (&key)[Wp], uint64_t hrow,
-                                           bool valid, OnHit &&on_hit) {
-    using CT = typename C2<ET>::T;
-    const CT *__restrict__ coef = (const CT *)h.t_coef;
-    for (int64_t g = 0; g < h.G; ++g) {
-        const uint32_t info = h.g_info[g];
-        uint32_t lo, hi;
-        bool live;
-        if (info & kInfoLadder) {
-            const uint64_t pos = h.g_pos[g];
-            const uint32_t kk = info & kInfoKMask;
-            uint32_t L = 0;
-            for (uint32_t j = 0; j < kk; ++j) L |= row_bit<Wp>(key, (uint32_t)(pos >> (16 * j)) & 0xFFFFu) << j;
-            live = (info >> (16 + L)) & 1u;
-            lo = h.g_iptr[g * kIptr + L];
-            hi = h.g_iptr[g * kIptr + L + 1];
-        } else {
-            lo = 0;
-            hi = h.g_nterm[g];
-            live = true;
-        }
-        live = live && valid;
-        if (!__any(live)) continue;
-        if (!live) continue;
-        const uint32_t t0 = h.g_term0[g];
-        if (info & kInfoCare) {
-            bool anyp = false;
-            for (uint32_t t = lo; t < hi; ++t)
-                if (term_pass<Wp>(key, h.t_cws + (int64_t)(t0 + t) * 3 * Wp)) {
-                    anyp = true;
-                    break;
-                }
-            if (!anyp) continue;
-        }
-        uint64_t col[Wp];
-#pragma unroll
-        for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ h.g_mask[g * Wp + w];
-        const int64_t j = probe<Wp>(s, hrow ^ h.g_hash[g], col);
-        if (j < 0) continue;
-        ET vre = 0, vim = 0;
-        if (NEED_VALUE) {
-            for (uint32_t t = lo; t < hi; ++t) {
-                const uint64_t *cws = h.t_cws + (int64_t)(t0 + t) * 3 * Wp;
-                if (!term_pass<Wp>(key, cws)) continue;
-                const CT c = coef[t0 + t];
-                if (term_parity<Wp>(key, cws)) {
-                    vre -= c.x;
-                    vim -= c.y;
-                } else {
-                    vre += c.x;
-                    vim += c.y;
-                }
-            }
-        }
-        on_hit(j, vre, vim);
-    }
-}
-
-// Evaluates the terms of group g for a row with ladder integer L (ladder groups) or all terms
-// (other groups): sum of c'_t (-1)^popcount(row & S_t) over terms whose projector bits match.
-template <int Wp, class ET>
-__device__ __forceinline__ bool group_value(const HamView &h, const uint64_t (&key)[Wp], int64_t g, uint32_t info,
-                                            uint32_t L, ET &vre, ET &vim) {
-    using CT = typename C2<ET>::T;
-    const CT *__restrict__ coef = (const CT *)h.t_coef;
-    uint32_t lo, hi;
-    if (info & kInfoLadder) {
-        lo = h.g_iptr[g * kIptr + L];
-        hi = h.g_iptr[g * kIptr + L + 1];
-    } else {
-        lo = 0;
-        hi = h.g_nterm[g];
-    }
-    const uint32_t t0 = h.g_term0[g];
-    bool any = false;
-    vre = 0;
-    vim = 0;
-    for (uint32_t t = lo; t < hi; ++t) {
-        const uint64_t *cws = h.t_cws + (int64_t)(t0 + t) * 3 * Wp;
-        if (!term_pass<Wp>(key, cws)) continue;
-        any = true;
-        const CT c = coef[t0 + t];
-        if (term_parity<Wp>(key, cws)) {
-            vre -= c.x;
-            vim -= c.y;
-        } else {
-            vre += c.x;
-            vim += c.y;
-        }
-    }
-    return any;
-}
-
-// Same walk as row_groups, reorganized for memory-level parallelism: B groups at a time, each
-// phase issues its independent loads for all B groups before consuming any (ladder integers
-// and hashes; occupancy words; first slots; key compares), so a wave keeps up to B probes in
-// flight instead of one.  Probes that find their first slot occupied by another key continue
-// along the run with the serial probe.  Hits are consumed in group order, so the row sum is
-// formed in the same order as row_groups.  The projector refinement follows the lookup (the
-// paper's order); an element whose terms all fail contributes nothing.
-template <int Wp, class ET, int B, class OnHit>
-__device__ __forceinline__ void row_groups_mlp(const SubView &s, const HamView &h, const uint64_t (&key)[Wp],
-                                               uint64_t hrow, bool valid, OnHit &&on_hit) {
-    for (int64_t g0 = 0; g0 < h.G; g0 += B) {
-        uint32_t pos[B], Lv[B];
-        bool live[B];
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const int64_t g = g0 + b;
-            live[b] = false;
-            pos[b] = 0;
-            Lv[b] = 0;
-            if (g < h.G) {
-                const uint32_t info = h.g_info[g];
-                bool lv = true;
-                if (info & kInfoLadder) {
-                    const uint64_t gp = h.g_pos[g];
-                    uint32_t L = 0;
-                    for (uint32_t j = 0; j < (info & kInfoKMask); ++j)
-                        L |= row_bit<Wp>(key, (uint32_t)(gp >> (16 * j)) & 0xFFFFu) << j;
-                    lv = (info >> (16 + L)) & 1u;
-                    Lv[b] = L;
-                }
-                live[b] = lv && valid;
-                pos[b] = (uint32_t)(hrow ^ h.g_hash[g]) & s.cmask;
-            }
-        }
-        uint32_t word[B];
-#pragma unroll
-        for (int b = 0; b < B; ++b) word[b] = live[b] ? s.bitmap[pos[b] >> 5] : 0u;
-        uint64_t slot[B];
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            live[b] = live[b] && ((word[b] >> (pos[b] & 31u)) & 1u);
-            slot[b] = live[b] ? s.slots[pos[b]] : ~0ull;
-        }
-        int64_t jv[B];
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            jv[b] = -1;
-            if (!live[b]) continue;
-            const int64_t g = g0 + b;
-            const uint64_t hh = hrow ^ h.g_hash[g];
-            const uint32_t tag = (uint32_t)(hh >> 32);
-            if ((uint32_t)(slot[b] >> 32) == tag) {
-                const uint32_t r = (uint32_t)slot[b];
-                bool eq = true;
-#pragma unroll
-                for (int w = 0; w < Wp; ++w) eq &= s.keys[(int64_t)w * s.N + r] == (key[w] ^ h.g_mask[g * Wp + w]);
-                if (eq) {
-                    jv[b] = r;
-                    continue;
-                }
-            }
-            // first slot taken by another key: continue the run if the next slot is occupied
-            const uint32_t nxt = (pos[b] + 1) & s.cmask;
-            const uint32_t nw = ((nxt >> 5) == (pos[b] >> 5)) ? word[b] : s.bitmap[nxt >> 5];
-            if ((nw >> (nxt & 31u)) & 1u) {
-                uint64_t col[Wp];
-#pragma unroll
-                for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ h.g_mask[g * Wp + w];
-                jv[b] = probe_from<Wp>(s, nxt, tag, col);
-            }
-        }
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            if (jv[b] < 0) continue;
-            const int64_t g = g0 + b;
-            ET vre, vim;
-            if (group_value<Wp, ET>(h, key, g, h.g_info[g], Lv[b], vre, vim)) on_hit(jv[b], vre, vim);
-        }
-    }
-}
 
 // ----------------------------------------------------------------------------- diagonal
 
@@ -286,25 +44,35 @@ __global__ void k_to_f32(const double *__restrict__ in, float *__restrict__ out,
         out[i] = (float)in[i];
 }
 
+// Loads the lane's row (clamped to a valid row for lanes past the end).
+template <int Wp>
+__device__ __forceinline__ int64_t load_row(const SubView &s, uint64_t (&key)[Wp], uint64_t &hrow, bool &valid) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    valid = i < s.N;
+    const int64_t r = valid ? i : s.N - 1;
+#pragma unroll
+    for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + r];
+    hrow = s.hkey[r];
+    return r;
+}
+
 // ------------------------------------------------------------------------------- matvec
 
 template <int Wp, int NV, class ET, bool CPLX>
 __global__ __launch_bounds__(kBlock) void k_matvec(SubView s, HamView h, const ET *__restrict__ dre,
                                                    const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
                                                    ET *__restrict__ y, int64_t ldy, int nvec) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = i < s.N;
-    const int64_t r = valid ? i : s.N - 1;
-    uint64_t key[Wp];
-#pragma unroll
-    for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + r];
-    const uint64_t hrow = s.hkey[r];
+    __shared__ ChunkLds<Wp> lds;
+    uint64_t key[Wp], hrow;
+    bool valid;
+    const int64_t r = load_row<Wp>(s, key, hrow, valid);
     double acc_re[NV], acc_im[NV];
     {
         const double dr = (double)dre[r];
         const double di = CPLX ? (double)dim[r] : 0.0;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
+            acc_re[v] = acc_im[v] = 0.0;
             if (v < nvec) {
                 if (CPLX) {
                     const double xr = (double)x[2 * (r * ldx + v)], xi = (double)x[2 * (r * ldx + v) + 1];
@@ -312,14 +80,13 @@ __global__ __launch_bounds__(kBlock) void k_matvec(SubView s, HamView h, const E
                     acc_im[v] = dr * xi + di * xr;
                 } else {
                     acc_re[v] = dr * (double)x[r * ldx + v];
-                    acc_im[v] = 0.0;
                 }
-            } else {
-                acc_re[v] = acc_im[v] = 0.0;
             }
         }
     }
-    row_groups_mlp<Wp, ET, kMlpBatch>(s, h, key, hrow, valid, [&](int64_t j, ET vre, ET vim) {
+    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t j, int64_t g) {
+        ET vre, vim;
+        if (!group_value<Wp, ET>(h, key, g, vre, vim)) return;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if (v < nvec) {
@@ -338,10 +105,10 @@ __global__ __launch_bounds__(kBlock) void k_matvec(SubView s, HamView h, const E
     for (int v = 0; v < NV; ++v) {
         if (v < nvec) {
             if (CPLX) {
-                y[2 * (i * ldy + v)] = (ET)acc_re[v];
-                y[2 * (i * ldy + v) + 1] = (ET)acc_im[v];
+                y[2 * (r * ldy + v)] = (ET)acc_re[v];
+                y[2 * (r * ldy + v) + 1] = (ET)acc_im[v];
             } else {
-                y[i * ldy + v] = (ET)acc_re[v];
+                y[r * ldy + v] = (ET)acc_re[v];
             }
         }
     }
@@ -351,58 +118,29 @@ __global__ __launch_bounds__(kBlock) void k_matvec(SubView s, HamView h, const E
 
 template <int Wp>
 __global__ __launch_bounds__(kBlock) void k_csr_count(SubView s, HamView h, int64_t *__restrict__ counts) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = i < s.N;
-    const int64_t r = valid ? i : s.N - 1;
-    uint64_t key[Wp];
-#pragma unroll
-    for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + r];
+    __shared__ ChunkLds<Wp> lds;
+    uint64_t key[Wp], hrow;
+    bool valid;
+    const int64_t r = load_row<Wp>(s, key, hrow, valid);
     int64_t cnt = 1;  // diagonal
-    row_groups<Wp, double, false>(s, h, key, s.hkey[r], valid, [&](int64_t, double, double) { ++cnt; });
-    if (valid) counts[i] = cnt;
+    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t, int64_t g) {
+        if (group_any<Wp>(h, key, g)) ++cnt;
+    });
+    if (valid) counts[r] = cnt;
 }
 
-// Work counters of one SpMV: probes issued (live groups that reach the hash table) and hits.
+// Work counters of one SpMV: probes (live groups that reach the hash table) and stored
+// off-diagonal entries.
 template <int Wp>
 __global__ __launch_bounds__(kBlock) void k_probe_count(SubView s, HamView h, unsigned long long *__restrict__ acc) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = i < s.N;
-    const int64_t r = valid ? i : s.N - 1;
-    uint64_t key[Wp];
-#pragma unroll
-    for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + r];
-    const uint64_t hrow = s.hkey[r];
+    __shared__ ChunkLds<Wp> lds;
+    uint64_t key[Wp], hrow;
+    bool valid;
+    load_row<Wp>(s, key, hrow, valid);
     unsigned long long probes = 0, hits = 0;
-    for (int64_t g = 0; g < h.G; ++g) {
-        const uint32_t info = h.g_info[g];
-        uint32_t lo, hi;
-        bool live;
-        if (info & kInfoLadder) {
-            const uint64_t pos = h.g_pos[g];
-            uint32_t L = 0;
-            for (uint32_t j = 0; j < (info & kInfoKMask); ++j)
-                L |= row_bit<Wp>(key, (uint32_t)(pos >> (16 * j)) & 0xFFFFu) << j;
-            live = (info >> (16 + L)) & 1u;
-            lo = h.g_iptr[g * kIptr + L];
-            hi = h.g_iptr[g * kIptr + L + 1];
-        } else {
-            lo = 0;
-            hi = h.g_nterm[g];
-            live = true;
-        }
-        if (!live || !valid) continue;
-        const uint32_t t0 = h.g_term0[g];
-        if (info & kInfoCare) {
-            bool anyp = false;
-            for (uint32_t t = lo; t < hi && !anyp; ++t) anyp = term_pass<Wp>(key, h.t_cws + (int64_t)(t0 + t) * 3 * Wp);
-            if (!anyp) continue;
-        }
-        ++probes;
-        uint64_t col[Wp];
-#pragma unroll
-        for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ h.g_mask[g * Wp + w];
-        if (probe<Wp>(s, hrow ^ h.g_hash[g], col) >= 0) ++hits;
-    }
+    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t, int64_t g) {
+        if (group_any<Wp>(h, key, g)) ++hits;
+    }, &probes);
     for (int d = 32; d >= 1; d >>= 1) {
         probes += __shfl_xor(probes, d, 64);
         hits += __shfl_xor(hits, d, 64);
@@ -418,25 +156,22 @@ template <int Wp, class ET>
 __global__ __launch_bounds__(kBlock) void k_csr_fill(SubView s, HamView h, const ET *__restrict__ dre,
                                                      const ET *__restrict__ dim, const int64_t *__restrict__ indptr,
                                                      int64_t *__restrict__ cols, typename C2<ET>::T *__restrict__ vals) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = i < s.N;
-    const int64_t r = valid ? i : s.N - 1;
-    uint64_t key[Wp];
-#pragma unroll
-    for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + r];
+    __shared__ ChunkLds<Wp> lds;
+    uint64_t key[Wp], hrow;
+    bool valid;
+    const int64_t r = load_row<Wp>(s, key, hrow, valid);
     int64_t o = indptr[r];
     if (valid) {
-        cols[o] = i;
+        cols[o] = r;
         typename C2<ET>::T d;
-        d.x = dre[i];
-        d.y = dim ? dim[i] : (ET)0;
+        d.x = dre[r];
+        d.y = dim ? dim[r] : (ET)0;
         vals[o] = d;
     }
     ++o;
-    row_groups<Wp, ET, true>(s, h, key, s.hkey[r], valid, [&](int64_t j, ET vre, ET vim) {
+    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t j, int64_t g) {
         typename C2<ET>::T v;
-        v.x = vre;
-        v.y = vim;
+        if (!group_value<Wp, ET>(h, key, g, v.x, v.y)) return;
         cols[o] = j;
         vals[o] = v;
         ++o;
