@@ -114,6 +114,7 @@ struct qsd_op {
     std::vector<uint64_t> g_mask;         // [G-1][Wp]
     std::vector<uint64_t> g_hash;         // [G-1]
     std::vector<uint64_t> g_pos;          // [G-1] four 16-bit ladder positions
+    std::vector<uint64_t> g_scan;         // [G-1] scan record: live table over 4 bits | 4 x 12-bit shifts
     std::vector<uint32_t> g_info;         // [G-1] k | ladder<<3 | care<<4 | live16<<16
     std::vector<uint32_t> g_term0;        // [G-1] first off-diagonal term
     std::vector<uint32_t> g_nterm;        // [G-1]
@@ -142,6 +143,7 @@ struct qsd_ham {
     uint64_t *g_mask = nullptr;
     uint64_t *g_hash = nullptr;
     uint64_t *g_pos = nullptr;
+    uint64_t *g_scan = nullptr;
     uint32_t *g_info = nullptr;
     uint32_t *g_term0 = nullptr;
     uint32_t *g_nterm = nullptr;

@@ -31,14 +31,14 @@
 
 namespace qsd {
 
-constexpr int kChunk = 128;               // groups per chunk
-constexpr int kMaskWords = kChunk / 32;   // per-lane live bits per chunk
-constexpr int kProbeBatch = 2;            // probes in flight per lane
+constexpr int kChunk = 64;      // groups per chunk (one 64-bit live mask per lane)
+constexpr int kProbeBatch = 2;  // probes in flight per lane
 
 struct HamView {
     const uint64_t *__restrict__ g_mask;   // [G][Wp]
     const uint64_t *__restrict__ g_hash;   // [G]
     const uint64_t *__restrict__ g_pos;    // [G] four 16-bit ladder qubits
+    const uint64_t *__restrict__ g_scan;   // [G padded to 8] live table | 4 x 12-bit shifts
     const uint32_t *__restrict__ g_info;   // [G] k | ladder | care | live16 << 16
     const uint32_t *__restrict__ g_term0;  // [G]
     const uint32_t *__restrict__ g_nterm;  // [G]
@@ -60,16 +60,6 @@ struct C2<float> {
 };
 
 template <int Wp>
-__device__ __forceinline__ uint32_t row_bit(const uint64_t (&k)[Wp], uint32_t p) {
-    uint64_t w = k[0];
-#pragma unroll
-    for (int i = 1; i < Wp; ++i)
-        if ((p >> 6) == (uint32_t)i) w = k[i];
-    const uint32_t half = (p & 32u) ? (uint32_t)(w >> 32) : (uint32_t)w;
-    return (half >> (p & 31u)) & 1u;
-}
-
-template <int Wp>
 __device__ __forceinline__ bool term_pass(const uint64_t (&k)[Wp], const uint64_t *__restrict__ cws) {
     bool ok = true;
 #pragma unroll
@@ -85,45 +75,21 @@ __device__ __forceinline__ uint32_t term_parity(const uint64_t (&k)[Wp], const u
     return c & 1u;
 }
 
-template <int Wp>
-__device__ __forceinline__ uint32_t ladder_int(const uint64_t (&k)[Wp], uint64_t pos, uint32_t kk) {
-    uint32_t L = 0;
-    for (uint32_t j = 0; j < kk; ++j) L |= row_bit<Wp>(k, (uint32_t)(pos >> (16 * j)) & 0xFFFFu) << j;
-    return L;
-}
-
-// Term range of group g for a row: the ladder-integer range, or all terms.
-template <int Wp>
-__device__ __forceinline__ void term_range(const HamView &h, const uint64_t (&key)[Wp], int64_t g, uint32_t &lo,
-                                           uint32_t &hi) {
-    const uint32_t info = h.g_info[g];
-    if (info & kInfoLadder) {
-        const uint32_t L = ladder_int<Wp>(key, h.g_pos[g], info & kInfoKMask);
-        lo = h.g_iptr[g * kIptr + L];
-        hi = h.g_iptr[g * kIptr + L + 1];
-    } else {
-        lo = 0;
-        hi = h.g_nterm[g];
-    }
-}
-
-// Element value of group g for a row: sum over the range of c'_t (-1)^popcount(b & S_t) over the
-// terms whose projector bits match.  Returns false when no term matches (no stored entry).
+// Sum of the terms [t0, t0 + len) that match the row's projector bits, with popcount-parity
+// signs.  Returns false when no term matches (no stored entry).
 template <int Wp, class ET>
-__device__ __forceinline__ bool group_value(const HamView &h, const uint64_t (&key)[Wp], int64_t g, ET &vre, ET &vim) {
+__device__ __forceinline__ bool range_value(const HamView &h, const uint64_t (&key)[Wp], uint32_t t0, uint32_t len,
+                                            ET &vre, ET &vim) {
     using CT = typename C2<ET>::T;
     const CT *__restrict__ coef = (const CT *)h.t_coef;
-    uint32_t lo, hi;
-    term_range<Wp>(h, key, g, lo, hi);
-    const uint32_t t0 = h.g_term0[g];
     bool any = false;
     vre = 0;
     vim = 0;
-    for (uint32_t t = lo; t < hi; ++t) {
-        const uint64_t *cws = h.t_cws + (int64_t)(t0 + t) * 3 * Wp;
+    for (uint32_t t = t0; t < t0 + len; ++t) {
+        const uint64_t *cws = h.t_cws + (int64_t)t * 3 * Wp;
         if (!term_pass<Wp>(key, cws)) continue;
         any = true;
-        const CT c = coef[t0 + t];
+        const CT c = coef[t];
         if (term_parity<Wp>(key, cws)) {
             vre -= c.x;
             vim -= c.y;
@@ -135,88 +101,118 @@ __device__ __forceinline__ bool group_value(const HamView &h, const uint64_t (&k
     return any;
 }
 
-// True iff some term of group g's range matches the row's projector bits.
+// 4-bit ladder integer of a row from a scan record: bit j = row bit at qubit (shift_j + j).
+// One-word keys are shifted in registers (one funnel shift per bit); wider keys read the
+// needed 32-bit half of the row from LDS (`keyh`, one word per lane per half), which avoids
+// indexing a register array with a run-time word number.  Unused positions are don't-cares
+// of the replicated live table.
 template <int Wp>
-__device__ __forceinline__ bool group_any(const HamView &h, const uint64_t (&key)[Wp], int64_t g) {
-    uint32_t lo, hi;
-    term_range<Wp>(h, key, g, lo, hi);
-    if (!(h.g_info[g] & kInfoCare)) return lo < hi;
-    const uint32_t t0 = h.g_term0[g];
-    for (uint32_t t = lo; t < hi; ++t)
-        if (term_pass<Wp>(key, h.t_cws + (int64_t)(t0 + t) * 3 * Wp)) return true;
-    return false;
+__device__ __forceinline__ uint32_t scan_lint(const uint64_t (&key)[Wp], uint64_t rec,
+                                              const uint32_t (*keyh)[kBlock]) {
+    uint32_t L = 0;
+    if (Wp == 1) {
+        const uint32_t lo = (uint32_t)key[0], hi = (uint32_t)(key[0] >> 32);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t sh = (uint32_t)(rec >> (16 + 12 * j)) & 0xFFFu;
+            const uint32_t t = sh < 32u ? __builtin_amdgcn_alignbit(hi, lo, sh) : (hi >> (sh - 32u));
+            L |= t & (1u << j);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t p = ((uint32_t)(rec >> (16 + 12 * j)) & 0xFFFu) + (uint32_t)j;
+            L |= ((keyh[p >> 5][threadIdx.x] >> (p & 31u)) & 1u) << j;
+        }
+    }
+    return L;
 }
 
-// LDS staging of one chunk: the group hashes and masks read by the probes.
+// LDS staging of one chunk: what the probes and the hit ranges read.
 template <int Wp>
 struct ChunkLds {
     uint64_t hash[kChunk];
     uint64_t mask[kChunk][Wp];
-    uint32_t live[kMaskWords][kBlock];  // per-lane live bits of the chunk
+    uint32_t term0[kChunk];
+    uint32_t nterm[kChunk];
+    uint32_t lmask[kChunk];              // ladder-integer bits used for the range (0: all terms)
+    uint16_t iptr[kChunk][kIptr];
+    uint32_t lint[kChunk / 8][kBlock];   // per-lane ladder integers, 8 nibbles per word
+    uint32_t keyh[Wp == 1 ? 1 : 2 * Wp][kBlock];  // row keys as 32-bit halves (wide keys)
 };
 
-// Pops the lowest set bit of the lane's chunk mask (current word `cur`, index `qi`, later
-// words in LDS); returns the chunk-relative group or -1.
-__device__ __forceinline__ int pop_group(uint32_t &cur, int &qi, const uint32_t (*live)[kBlock]) {
-    while (cur == 0 && qi + 1 < kMaskWords) {
-        ++qi;
-        cur = live[qi][threadIdx.x];
-    }
-    if (cur == 0) return -1;
-    const int c = qi * 32 + __builtin_ctz(cur);
-    cur &= cur - 1;
+// Pops the lowest set bit of a 64-bit mask held as two words; -1 when empty.
+__device__ __forceinline__ int pop_group(uint32_t &mlo, uint32_t &mhi) {
+    const bool use_lo = mlo != 0u;
+    const uint32_t w = use_lo ? mlo : mhi;
+    const int c = w ? (int)__builtin_ctz(w) + (use_lo ? 0 : 32) : -1;
+    const uint32_t nw = w & (w - 1u);
+    mlo = use_lo ? nw : mlo;
+    mhi = use_lo ? mhi : nw;
     return c;
 }
 
-// Walks all groups for the lane's row and calls on_hit(j, g) for every probe whose column
-// b_i ^ M_g is in the subspace (j = its index), in increasing g.  All threads of the block
-// must call it (it stages chunks through LDS with barriers).  `valid` = the lane owns a row.
+// Walks all groups for the lane's row and calls on_hit(j, t0, len) for every probe whose
+// column b_i ^ M_g is in the subspace (j = its index; [t0, t0 + len) = the group's terms for
+// the row's ladder integer), in increasing g.  All threads of the block must call it (chunks
+// are staged through LDS with barriers).  `valid` = the lane owns a row.
 template <int Wp, class OnHit>
 __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, const uint64_t (&key)[Wp],
                                            uint64_t hrow, bool valid, ChunkLds<Wp> &lds, OnHit &&on_hit,
                                            unsigned long long *probes = nullptr) {
+    if (Wp > 1) {
+#pragma unroll
+        for (int w = 0; w < Wp; ++w) {
+            lds.keyh[(2 * w) % (Wp == 1 ? 1 : 2 * Wp)][threadIdx.x] = (uint32_t)key[w];
+            lds.keyh[(2 * w + 1) % (Wp == 1 ? 1 : 2 * Wp)][threadIdx.x] = (uint32_t)(key[w] >> 32);
+        }
+    }
     for (int64_t g0 = 0; g0 < h.G; g0 += kChunk) {
         const int nc = (int)((h.G - g0) < kChunk ? (h.G - g0) : kChunk);
         __syncthreads();
         for (int c = threadIdx.x; c < nc; c += kBlock) {
-            lds.hash[c] = h.g_hash[g0 + c];
+            const int64_t g = g0 + c;
+            lds.hash[c] = h.g_hash[g];
 #pragma unroll
-            for (int w = 0; w < Wp; ++w) lds.mask[c][w] = h.g_mask[(g0 + c) * Wp + w];
+            for (int w = 0; w < Wp; ++w) lds.mask[c][w] = h.g_mask[g * Wp + w];
+            const uint32_t info = h.g_info[g];
+            lds.term0[c] = h.g_term0[g];
+            lds.nterm[c] = h.g_nterm[g];
+            lds.lmask[c] = (info & kInfoLadder) ? ((1u << (info & kInfoKMask)) - 1u) : 0u;
+#pragma unroll
+            for (int q = 0; q < kIptr; ++q) lds.iptr[c][q] = h.g_iptr[g * kIptr + q];
         }
-        // scan: one live bit per group
-        uint32_t m0 = 0;
+        // scan: a live bit and the ladder integer per group; records are read 8 at a time
+        uint32_t mw[2] = {0u, 0u};
 #pragma unroll
-        for (int q = 0; q < kMaskWords; ++q) {
+        for (int q = 0; q < 2; ++q) {
             uint32_t m = 0;
-            const int cend = nc - 32 * q < 32 ? nc - 32 * q : 32;
-            for (int b = 0; b < cend; ++b) {
-                const int64_t g = g0 + 32 * q + b;
-                const uint32_t info = h.g_info[g];
-                uint32_t live = 1u;
-                if (info & kInfoLadder) live = (info >> (16 + ladder_int<Wp>(key, h.g_pos[g], info & kInfoKMask))) & 1u;
-                m |= live << b;
+            for (int c8 = 32 * q; c8 < 32 * q + 32 && c8 < nc; c8 += 8) {
+                uint64_t rec[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) rec[u] = h.g_scan[g0 + c8 + u];  // padded array
+                uint32_t lp = 0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const uint32_t L = scan_lint<Wp>(key, rec[u], lds.keyh);
+                    const uint32_t live = ((uint32_t)(rec[u] >> L) & 1u) & (c8 + u < nc ? 1u : 0u);
+                    m |= live << (c8 + u - 32 * q);
+                    lp |= L << (4 * u);
+                }
+                lds.lint[c8 / 8][threadIdx.x] = lp;
             }
-            if (!valid) m = 0;
-            if (q == 0)
-                m0 = m;
-            else
-                lds.live[q][threadIdx.x] = m;
+            mw[q] = valid ? m : 0u;
         }
+        uint32_t mlo = mw[0], mhi = mw[1];
+        if (probes) *probes += (unsigned long long)(__popc(mlo) + __popc(mhi));
         __syncthreads();
-        if (probes) {
-            unsigned long long cnt = __popc(m0);
-            for (int q = 1; q < kMaskWords; ++q) cnt += __popc(lds.live[q][threadIdx.x]);
-            *probes += cnt;
-        }
         // probe: each lane pops its own live groups, kProbeBatch at a time
-        uint32_t cur = m0;
-        int qi = 0;
         while (true) {
             int c[kProbeBatch];
             bool anyc = false;
 #pragma unroll
             for (int b = 0; b < kProbeBatch; ++b) {
-                c[b] = pop_group(cur, qi, lds.live);
+                c[b] = pop_group(mlo, mhi);
                 anyc |= c[b] >= 0;
             }
             if (!__any(anyc)) break;
@@ -256,7 +252,14 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                     const uint32_t nw = ((nxt >> 5) == (pos[b] >> 5)) ? word[b] : s.bitmap[nxt >> 5];
                     if ((nw >> (nxt & 31u)) & 1u) j = probe_from<Wp>(s, nxt, tag, col);
                 }
-                if (j >= 0) on_hit(j, g0 + c[b]);
+                if (j >= 0) {
+                    const int cc = c[b];
+                    const uint32_t lm = lds.lmask[cc];
+                    const uint32_t L = (lds.lint[cc >> 3][threadIdx.x] >> (4 * (cc & 7))) & lm;
+                    const uint32_t lo = lds.iptr[cc][L];
+                    const uint32_t hi = lm ? (uint32_t)lds.iptr[cc][L + 1] : lds.nterm[cc];
+                    on_hit(j, lds.term0[cc] + lo, hi - lo);
+                }
             }
         }
     }

@@ -84,9 +84,9 @@ __global__ __launch_bounds__(kBlock) void k_matvec(SubView s, HamView h, const E
             }
         }
     }
-    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t j, int64_t g) {
+    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t j, uint32_t t0, uint32_t len) {
         ET vre, vim;
-        if (!group_value<Wp, ET>(h, key, g, vre, vim)) return;
+        if (!range_value<Wp, ET>(h, key, t0, len, vre, vim)) return;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if (v < nvec) {
@@ -123,8 +123,9 @@ __global__ __launch_bounds__(kBlock) void k_csr_count(SubView s, HamView h, int6
     bool valid;
     const int64_t r = load_row<Wp>(s, key, hrow, valid);
     int64_t cnt = 1;  // diagonal
-    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t, int64_t g) {
-        if (group_any<Wp>(h, key, g)) ++cnt;
+    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t, uint32_t t0, uint32_t len) {
+        double vre, vim;
+        if (range_value<Wp, double>(h, key, t0, len, vre, vim)) ++cnt;
     });
     if (valid) counts[r] = cnt;
 }
@@ -138,8 +139,9 @@ __global__ __launch_bounds__(kBlock) void k_probe_count(SubView s, HamView h, un
     bool valid;
     load_row<Wp>(s, key, hrow, valid);
     unsigned long long probes = 0, hits = 0;
-    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t, int64_t g) {
-        if (group_any<Wp>(h, key, g)) ++hits;
+    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t, uint32_t t0, uint32_t len) {
+        double vre, vim;
+        if (range_value<Wp, double>(h, key, t0, len, vre, vim)) ++hits;
     }, &probes);
     for (int d = 32; d >= 1; d >>= 1) {
         probes += __shfl_xor(probes, d, 64);
@@ -169,9 +171,9 @@ __global__ __launch_bounds__(kBlock) void k_csr_fill(SubView s, HamView h, const
         vals[o] = d;
     }
     ++o;
-    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t j, int64_t g) {
+    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t j, uint32_t t0, uint32_t len) {
         typename C2<ET>::T v;
-        if (!group_value<Wp, ET>(h, key, g, v.x, v.y)) return;
+        if (!range_value<Wp, ET>(h, key, t0, len, v.x, v.y)) return;
         cols[o] = j;
         vals[o] = v;
         ++o;
@@ -219,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_csr_sort(const int64_t *__restrict__
 inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 HamView view_of(const qsd_ham *h, bool f32) {
-    return HamView{h->g_mask, h->g_hash, h->g_pos,  h->g_info, h->g_term0, h->g_nterm,
+    return HamView{h->g_mask, h->g_hash, h->g_pos,  h->g_scan, h->g_info, h->g_term0, h->g_nterm,
                    h->g_iptr, h->t_cws,  f32 ? (const void *)h->t_coef32 : (const void *)h->t_coef, h->G};
 }
 
@@ -241,6 +243,7 @@ void free_ham(qsd_ham *h) {
     dev_free(h->g_mask);
     dev_free(h->g_hash);
     dev_free(h->g_pos);
+    dev_free(h->g_scan);
     dev_free(h->g_info);
     dev_free(h->g_term0);
     dev_free(h->g_nterm);
@@ -264,6 +267,7 @@ int create_impl(qsd_ham *h, hipStream_t st) {
     QSD_TRY(upload(&h->g_mask, op->g_mask, st));
     QSD_TRY(upload(&h->g_hash, op->g_hash, st));
     QSD_TRY(upload(&h->g_pos, op->g_pos, st));
+    QSD_TRY(upload(&h->g_scan, op->g_scan, st));
     QSD_TRY(upload(&h->g_info, op->g_info, st));
     QSD_TRY(upload(&h->g_term0, op->g_term0, st));
     QSD_TRY(upload(&h->g_nterm, op->g_nterm, st));

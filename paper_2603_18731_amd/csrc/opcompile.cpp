@@ -373,6 +373,24 @@ extern "C" int qsd_op_compile(int32_t n_qubits, int64_t n_terms, const int64_t *
         op->g_mask.insert(op->g_mask.end(), M.begin(), M.end());
         op->g_hash.push_back(gh);
         op->g_pos.push_back(gpos);
+        // Scan record.  The device forms a 4-bit ladder integer from four positions (unused
+        // ones repeat qubit j's bit, so they are don't-cares): bits 0..15 hold the live table
+        // replicated over the don't-care bits (all ones for groups scanned term by term);
+        // bits 16 + 12j hold p_j - j, the right shift that brings qubit p_j to bit j.
+        {
+            uint64_t rec = 0;
+            const int kk = ladder ? (int)pos.size() : 0;
+            for (int L = 0; L < 16; ++L) {
+                const int Lk = kk ? (L & ((1 << kk) - 1)) : 0;
+                const bool lv = ladder ? ((live >> Lk) & 1u) : true;
+                if (lv) rec |= 1ull << L;
+            }
+            for (int j = 0; j < 4; ++j) {
+                const int p = (ladder && j < kk) ? pos[j] : j;
+                rec |= (uint64_t)(p - j) << (16 + 12 * j);
+            }
+            op->g_scan.push_back(rec);
+        }
         op->g_info.push_back((uint32_t)(ladder ? pos.size() : 0) | (ladder ? kInfoLadder : 0) |
                              (care ? kInfoCare : 0) | (live << 16));
         op->g_term0.push_back(term0);
@@ -383,6 +401,8 @@ extern "C" int qsd_op_compile(int32_t n_qubits, int64_t n_terms, const int64_t *
         op->max_group_terms = std::max<int64_t>(op->max_group_terms, (int64_t)(j - i));
         i = j;
     }
+    // the device reads scan records 8 at a time
+    while (op->g_scan.size() % 8 != 0 || op->g_scan.size() < op->g_info.size() + 8) op->g_scan.push_back(0);
     op->is_complex = cplx_mat;
     *out = op;
     return QSD_OK;
