@@ -24,6 +24,52 @@ sys.path.insert(0, ROOT)
 
 METRIC = "matrix elements/s in matrix-free SpMV; ground-state solve s; serve p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2603_18731_amd/csrc/engine.h", "paper_2603_18731_amd/csrc/ham.hip",
+                  "paper_2603_18731_amd/csrc/device.h"]
+
+
+def kernel_digest():
+    """Digest of the SpMV kernel's sources (ties a stored counter profile to the code)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload, dtype, nvec):
+    """HBM bytes per SpMV launch from the committed counter profile of this workload, or None
+    when there is none or it was taken on other kernel sources.  The profile records
+    FETCH_SIZE and WRITE_SIZE per dispatch (KiB) and the factors that scale them to the bytes a
+    plain copy of known size moves."""
+    path = os.path.join(ROOT, "profiles", "k_matvec_%s_%s_nvec%d.md" % (workload, dtype, nvec))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic:"):
+                for kv in line.split()[1:]:
+                    k, v = kv.split("=")
+                    vals[k] = v
+    if vals.get("source_digest") != kernel_digest():
+        return None
+    return float(vals["hbm_bytes_per_launch"])
+
+
+def calibrate_copy():
+    """A plain device copy of known size, profiled to scale FETCH_SIZE / WRITE_SIZE."""
+    import torch
+
+    n = 64 << 20  # doubles: 512 MiB
+    a = torch.rand(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "copies": 3}))
 
 
 def algorithmic_bytes(N, W, probes, hits, nvec, esz):
@@ -98,7 +144,12 @@ def main():
     ap.add_argument("--max-load", type=float, default=0.0, help="hash load factor (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true", help="run the plain-copy kernel used to scale "
+                    "rocprofv3 FETCH_SIZE / WRITE_SIZE and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the subspace SpMV is not sharded across GPUs in this "
               "build (requested --gpus %d)" % args.gpus, file=sys.stderr)
@@ -176,8 +227,9 @@ def main():
         "config": {"workload": w.name, "n_qubits": w.ops.n_qubits, "subspace_dim": N, "nnz": nnz,
                    "groups": op.n_groups, "terms": op.n_terms, "nvec": args.nvec, "kernel": "k_matvec"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": balg,
-                     "kernel_ms": k_avg},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": stored_traffic(w.name, args.dtype, args.nvec), "bytes_per_launch": balg,
+                     "kernel_ms": k_avg, "kernel_source_digest": kernel_digest()},
         "work": {"probes": probes, "hits": hits, "evaluations": N * op.n_groups,
                  "probes_per_s": probes / (k_avg / 1e3), "evaluations_per_s": N * op.n_groups / (k_avg / 1e3)},
     }
