@@ -144,11 +144,21 @@ def main():
     ap.add_argument("--max-load", type=float, default=0.0, help="hash load factor (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--gather-ceiling", action="store_true", help="measure the random-gather rate for "
+                    "buffer sizes 256 KiB .. 1 GiB and exit")
     ap.add_argument("--calibrate-copy", action="store_true", help="run the plain-copy kernel used to scale "
                     "rocprofv3 FETCH_SIZE / WRITE_SIZE and exit")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.gather_ceiling:
+        import paper_2603_18731_amd as qsd
+
+        for kib in (256, 1024, 2048, 4096, 8192, 32768, 131072, 524288, 1048576):
+            for ilp in (1, 2, 4, 8):
+                r = qsd.device_gather_rate(kib << 10, ilp)
+                print(json.dumps({"buffer_kib": kib, "ilp": ilp, "loads_per_s": r}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the subspace SpMV is not sharded across GPUs in this "

@@ -267,6 +267,14 @@ void qsd_lanczos_default_opts(qsd_lanczos_opts *opts);
 int qsd_lanczos(const qsd_ham *h, const qsd_lanczos_opts *opts, double *eval_out, void *d_evec,
                 qsd_lanczos_info *info, void *stream);
 
+/* ====================================================================== diagnostics */
+
+/* Random-gather rate of the current device: `ilp` (1, 2, 4, 8) independent random 4-byte loads
+ * in flight per lane from a buffer of `bytes` (a power of two, 1 KiB .. 16 GiB, allocated and
+ * freed by the call).  The rate bounds hash probing (one random load per occupancy test).
+ * Host output, synchronizes. */
+int qsd_device_gather_rate(int64_t bytes, int32_t ilp, double *loads_per_s, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,6 +35,7 @@ EXPORTED = [
     "qsd_subspace_keys", "qsd_subspace_lookup", "qsd_subspace_probe_stats", "qsd_subspace_destroy",
     "qsd_op_compile", "qsd_op_info", "qsd_op_export", "qsd_op_destroy", "qsd_ham_create", "qsd_ham_diagonal",
     "qsd_ham_destroy", "qsd_ham_info", "qsd_ham_work_counts", "qsd_matvec", "qsd_csr_build", "qsd_lanczos_default_opts", "qsd_lanczos",
+    "qsd_device_gather_rate",
 ]
 
 
@@ -95,6 +96,7 @@ def lib():
         "qsd_csr_build": ([P, P, P, P, I32, I32, P, P], ctypes.c_int),
         "qsd_lanczos_default_opts": ([ctypes.POINTER(LanczosOpts)], None),
         "qsd_lanczos": ([P, ctypes.POINTER(LanczosOpts), P, P, ctypes.POINTER(LanczosInfo), P], ctypes.c_int),
+        "qsd_device_gather_rate": ([I64, I32, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -138,6 +140,13 @@ def _device_tensor(a, dtype=None):
     if dtype is not None:
         t = t.to(dtype)
     return t.cuda().contiguous()
+
+
+def device_gather_rate(nbytes: int, ilp: int = 4, stream=None) -> float:
+    """Random 4-byte loads per second from a buffer of ``nbytes`` (power of two)."""
+    r = ctypes.c_double()
+    _check(lib().qsd_device_gather_rate(int(nbytes), int(ilp), ctypes.byref(r), _stream(stream)))
+    return r.value
 
 
 # ----------------------------------------------------------------------------- classes
