@@ -211,6 +211,17 @@ int qsd_ham_work_counts(const qsd_ham *h, int64_t *probes, int64_t *hits, void *
 int qsd_matvec(const qsd_ham *h, int32_t nvec, const void *d_x, int64_t ldx, void *d_y, int64_t ldy, int32_t dtype,
                void *stream);
 
+/* Y_i = H_i X_i for n independent requests in one launch per key width (per chunk of four
+ * complex vectors): the row tiles of all requests form one grid, so small subspaces share the
+ * GPU instead of each under-filling it.  Per request: hams[i], device vectors xs[i] and ys[i]
+ * with nvecs[i] (1..16) interleaved vectors (leading dimension nvecs[i]); dtype as for
+ * qsd_matvec, the same for all requests and matching every operator (DTYPE otherwise).  Every
+ * row is evaluated exactly as by qsd_matvec, so the results are bitwise those of n separate
+ * calls.  The request table is uploaded to stream-ordered memory (hipMallocAsync) on `stream`;
+ * the call does not synchronize.  Not in the paper (serving pattern). */
+int qsd_matvec_batched(int32_t n, const qsd_ham *const *hams, const void *const *xs, void *const *ys,
+                       const int32_t *nvecs, int32_t dtype, void *stream);
+
 /* ============================================================================= CSR
  *
  * qsd_csr_build - Methods, Matrix evaluation (two-pass CSR).
@@ -266,6 +277,50 @@ void qsd_lanczos_default_opts(qsd_lanczos_opts *opts);
  */
 int qsd_lanczos(const qsd_ham *h, const qsd_lanczos_opts *opts, double *eval_out, void *d_evec,
                 qsd_lanczos_info *info, void *stream);
+
+/* ========================================================= batched Lanczos (serving)
+ *
+ * Many ground-state solves advance together: qsd_batch_step takes one Lanczos iteration (the
+ * same algorithm as qsd_lanczos: FP64 basis, classical Gram-Schmidt applied twice) for every
+ * active request with one SpMV launch over all requests' rows and a fixed number of BLAS
+ * launches, so requests of different sizes share the GPU at iteration granularity (continuous
+ * batching: requests are added and removed between steps).  A request's reductions are
+ * partitioned by its own size only, so its iterates are bitwise identical alone and in any
+ * mix.  Not in the paper (it hands its operator to external eigensolvers).
+ *
+ * qsd_batch_create     up to max_requests slots, at most max_iter iterations per request,
+ *                      SpMV in spmv_dtype (QSD_F64, or QSD_F32 with FP64 accumulation).
+ * qsd_batch_footprint  device bytes of one request's workspace for `h` (Krylov basis, work
+ *                      vectors, partial sums, tridiagonal state).
+ * qsd_batch_add        binds a real operator `h` (it must outlive the request) and starts
+ *                      its Lanczos run from v0_mode (UNIFORM, MIN_DIAG or RANDOM(seed)); the
+ *                      request converges when beta_k |s_k| <= tol |theta|.  `workspace` is
+ *                      device memory of at least qsd_batch_footprint bytes, 256-byte aligned,
+ *                      owned by the caller and kept valid until the slot is removed and the
+ *                      work enqueued before has finished; NULL makes the library allocate it
+ *                      (hipMalloc) and free it at removal.  All requests of a batch must have
+ *                      the same key width.  Errors: CAPACITY (no free slot), OUT_OF_MEMORY,
+ *                      UNSUPPORTED (complex operator or other key width), INVALID_ARG (empty
+ *                      subspace, short or misaligned workspace).  Synchronizes `stream`.
+ * qsd_batch_step       `iterations` iterations for every active request (requests at their
+ *                      limit idle).  Enqueued on `stream`.
+ * qsd_batch_poll       solves every active request's tridiagonal problem and reports, per
+ *                      slot (host arrays of max_requests entries, any may be NULL): status
+ *                      0 free, 1 running, 2 converged, 3 iteration limit; energy (theta);
+ *                      iterations taken; Ritz residual estimate.  Synchronizes.
+ * qsd_batch_remove     frees a slot; a library-allocated workspace is released with hipFree
+ *                      (which waits for the device).
+ */
+typedef struct qsd_batch qsd_batch;
+int qsd_batch_create(int32_t max_requests, int32_t max_iter, int32_t spmv_dtype, qsd_batch **out);
+int qsd_batch_footprint(const qsd_ham *h, int32_t max_iter, int32_t spmv_dtype, int64_t *bytes);
+int qsd_batch_add(qsd_batch *b, const qsd_ham *h, int32_t v0_mode, uint64_t seed, double tol, void *workspace,
+                  int64_t workspace_bytes, int32_t *slot_out, void *stream);
+int qsd_batch_step(qsd_batch *b, int32_t iterations, void *stream);
+int qsd_batch_poll(qsd_batch *b, int32_t *status, double *energy, int32_t *iterations, double *ritz_residual,
+                   void *stream);
+int qsd_batch_remove(qsd_batch *b, int32_t slot);
+int qsd_batch_destroy(qsd_batch *b);
 
 /* ====================================================================== diagnostics */
 

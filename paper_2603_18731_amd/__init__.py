@@ -35,7 +35,8 @@ EXPORTED = [
     "qsd_subspace_keys", "qsd_subspace_lookup", "qsd_subspace_probe_stats", "qsd_subspace_destroy",
     "qsd_op_compile", "qsd_op_info", "qsd_op_export", "qsd_op_destroy", "qsd_ham_create", "qsd_ham_diagonal",
     "qsd_ham_destroy", "qsd_ham_info", "qsd_ham_work_counts", "qsd_matvec", "qsd_csr_build", "qsd_lanczos_default_opts", "qsd_lanczos",
-    "qsd_device_gather_rate",
+    "qsd_device_gather_rate", "qsd_batch_create", "qsd_batch_footprint", "qsd_batch_add", "qsd_batch_step",
+    "qsd_batch_poll", "qsd_batch_remove", "qsd_batch_destroy", "qsd_matvec_batched",
 ]
 
 
@@ -97,6 +98,14 @@ def lib():
         "qsd_lanczos_default_opts": ([ctypes.POINTER(LanczosOpts)], None),
         "qsd_lanczos": ([P, ctypes.POINTER(LanczosOpts), P, P, ctypes.POINTER(LanczosInfo), P], ctypes.c_int),
         "qsd_device_gather_rate": ([I64, I32, P, P], ctypes.c_int),
+        "qsd_batch_create": ([I32, I32, I32, PP], ctypes.c_int),
+        "qsd_batch_footprint": ([P, I32, I32, P], ctypes.c_int),
+        "qsd_batch_add": ([P, P, I32, ctypes.c_uint64, D, P, I64, P, P], ctypes.c_int),
+        "qsd_matvec_batched": ([I32, P, P, P, P, I32, P], ctypes.c_int),
+        "qsd_batch_step": ([P, I32, P], ctypes.c_int),
+        "qsd_batch_poll": ([P, P, P, P, P, P], ctypes.c_int),
+        "qsd_batch_remove": ([P, I32], ctypes.c_int),
+        "qsd_batch_destroy": ([P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -370,4 +379,82 @@ class SubspaceHamiltonian:
         h = getattr(self, "_h", None)
         if h and _lib is not None:
             _lib.qsd_ham_destroy(h)
+            self._h = None
+
+
+def matvec_batched(hams, xs, ys=None, stream=None):
+    """``ys[i] = hams[i] @ xs[i]`` for every request in one launch per key width
+    (``qsd_matvec_batched``); vectors are ``[N]`` or ``[N][nvec]`` contiguous device tensors of
+    one dtype."""
+    import torch
+
+    n = len(hams)
+    if ys is None:
+        ys = [torch.empty_like(x) for x in xs]
+    if n == 0:
+        return ys
+    code = SubspaceHamiltonian._dtype_code(xs[0])
+    for h, x, y in zip(hams, xs, ys):
+        if not (x.is_contiguous() and y.is_contiguous()) or x.shape[0] != h.N or y.shape != x.shape:
+            raise ValueError("vectors must be contiguous [N] or [N][nvec] tensors matching their operator")
+    H = (ctypes.c_void_p * n)(*[h.handle.value for h in hams])
+    X = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+    Y = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ys])
+    nv = np.array([1 if x.dim() == 1 else x.shape[1] for x in xs], dtype=np.int32)
+    _check(lib().qsd_matvec_batched(n, ctypes.cast(H, ctypes.c_void_p), ctypes.cast(X, ctypes.c_void_p),
+                                    ctypes.cast(Y, ctypes.c_void_p), _ptr(nv), code, _stream(stream)))
+    return ys
+
+
+class LanczosBatch:
+    """Continuous-batching Lanczos: many ground-state solves advance one iteration per step
+    with one batched SpMV launch (``qsd_batch_*``)."""
+
+    RUNNING, CONVERGED, LIMIT = 1, 2, 3
+
+    def __init__(self, max_requests: int, max_iter: int = 300, spmv_dtype: str = "f64"):
+        self.max_requests, self.max_iter = int(max_requests), int(max_iter)
+        self.dtype = {"f64": F64, "f32": F32}[spmv_dtype]
+        h = ctypes.c_void_p()
+        _check(lib().qsd_batch_create(self.max_requests, self.max_iter, self.dtype, ctypes.byref(h)))
+        self._h = h
+        self._hams = {}
+
+    def footprint(self, ham: "SubspaceHamiltonian") -> int:
+        b = ctypes.c_int64()
+        _check(lib().qsd_batch_footprint(ham.handle, self.max_iter, self.dtype, ctypes.byref(b)))
+        return b.value
+
+    def add(self, ham: "SubspaceHamiltonian", v0: str = "uniform", seed: int = 0, tol: float = 1e-10,
+            workspace=None, stream=None):
+        """Start a solve; ``workspace`` (a device tensor of at least ``footprint`` bytes) is kept
+        by the batch until the slot is removed; ``None`` lets the library allocate."""
+        mode = {"uniform": V0_UNIFORM, "min_diag": V0_MIN_DIAG, "random": V0_RANDOM}[v0]
+        slot = ctypes.c_int32()
+        nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+        _check(lib().qsd_batch_add(self._h, ham.handle, mode, seed, tol, _ptr(workspace), nbytes, ctypes.byref(slot),
+                                   _stream(stream)))
+        self._hams[slot.value] = (ham, workspace)  # both stay alive while the request runs
+        return slot.value
+
+    def step(self, iterations: int = 1, stream=None):
+        _check(lib().qsd_batch_step(self._h, int(iterations), _stream(stream)))
+
+    def poll(self, stream=None):
+        n = self.max_requests
+        st = np.zeros(n, dtype=np.int32)
+        e = np.zeros(n, dtype=np.float64)
+        it = np.zeros(n, dtype=np.int32)
+        rr = np.zeros(n, dtype=np.float64)
+        _check(lib().qsd_batch_poll(self._h, _ptr(st), _ptr(e), _ptr(it), _ptr(rr), _stream(stream)))
+        return st, e, it, rr
+
+    def remove(self, slot: int):
+        _check(lib().qsd_batch_remove(self._h, int(slot)))
+        self._hams.pop(int(slot), None)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.qsd_batch_destroy(h)
             self._h = None

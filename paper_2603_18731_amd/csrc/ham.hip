@@ -7,6 +7,7 @@
 #include "common.h"
 #include "device.h"
 #include "engine.h"
+#include "matvec.h"
 
 namespace qsd {
 namespace {
@@ -44,18 +45,6 @@ __global__ void k_to_f32(const double *__restrict__ in, float *__restrict__ out,
         out[i] = (float)in[i];
 }
 
-// Loads the lane's row (clamped to a valid row for lanes past the end).
-template <int Wp>
-__device__ __forceinline__ int64_t load_row(const SubView &s, uint64_t (&key)[Wp], uint64_t &hrow, bool &valid) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    valid = i < s.N;
-    const int64_t r = valid ? i : s.N - 1;
-#pragma unroll
-    for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + r];
-    hrow = s.hkey[r];
-    return r;
-}
-
 // ------------------------------------------------------------------------------- matvec
 
 template <int Wp, int NV, class ET, bool CPLX>
@@ -63,55 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec(SubView s, HamView h, const E
                                                    const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
                                                    ET *__restrict__ y, int64_t ldy, int nvec) {
     __shared__ ChunkLds<Wp> lds;
-    uint64_t key[Wp], hrow;
-    bool valid;
-    const int64_t r = load_row<Wp>(s, key, hrow, valid);
-    double acc_re[NV], acc_im[NV];
-    {
-        const double dr = (double)dre[r];
-        const double di = CPLX ? (double)dim[r] : 0.0;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            acc_re[v] = acc_im[v] = 0.0;
-            if (v < nvec) {
-                if (CPLX) {
-                    const double xr = (double)x[2 * (r * ldx + v)], xi = (double)x[2 * (r * ldx + v) + 1];
-                    acc_re[v] = dr * xr - di * xi;
-                    acc_im[v] = dr * xi + di * xr;
-                } else {
-                    acc_re[v] = dr * (double)x[r * ldx + v];
-                }
-            }
-        }
-    }
-    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t j, uint32_t t0, uint32_t len) {
-        ET vre, vim;
-        if (!range_value<Wp, ET>(h, key, t0, len, vre, vim)) return;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            if (v < nvec) {
-                if (CPLX) {
-                    const double xr = (double)x[2 * (j * ldx + v)], xi = (double)x[2 * (j * ldx + v) + 1];
-                    acc_re[v] += (double)vre * xr - (double)vim * xi;
-                    acc_im[v] += (double)vre * xi + (double)vim * xr;
-                } else {
-                    acc_re[v] += (double)vre * (double)x[j * ldx + v];
-                }
-            }
-        }
-    });
-    if (!valid) return;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        if (v < nvec) {
-            if (CPLX) {
-                y[2 * (r * ldy + v)] = (ET)acc_re[v];
-                y[2 * (r * ldy + v) + 1] = (ET)acc_im[v];
-            } else {
-                y[r * ldy + v] = (ET)acc_re[v];
-            }
-        }
-    }
+    matvec_block<Wp, NV, ET, CPLX>(s, h, dre, dim, x, ldx, y, ldy, nvec, (int64_t)blockIdx.x * kBlock, lds);
 }
 
 // ---------------------------------------------------------------------------------- CSR
@@ -121,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_csr_count(SubView s, HamView h, int6
     __shared__ ChunkLds<Wp> lds;
     uint64_t key[Wp], hrow;
     bool valid;
-    const int64_t r = load_row<Wp>(s, key, hrow, valid);
+    const int64_t r = load_row<Wp>(s, (int64_t)blockIdx.x * kBlock, key, hrow, valid);
     int64_t cnt = 1;  // diagonal
     row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t, uint32_t t0, uint32_t len) {
         double vre, vim;
@@ -137,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_probe_count(SubView s, HamView h, un
     __shared__ ChunkLds<Wp> lds;
     uint64_t key[Wp], hrow;
     bool valid;
-    load_row<Wp>(s, key, hrow, valid);
+    load_row<Wp>(s, (int64_t)blockIdx.x * kBlock, key, hrow, valid);
     unsigned long long probes = 0, hits = 0;
     row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t, uint32_t t0, uint32_t len) {
         double vre, vim;
@@ -161,7 +102,7 @@ __global__ __launch_bounds__(kBlock) void k_csr_fill(SubView s, HamView h, const
     __shared__ ChunkLds<Wp> lds;
     uint64_t key[Wp], hrow;
     bool valid;
-    const int64_t r = load_row<Wp>(s, key, hrow, valid);
+    const int64_t r = load_row<Wp>(s, (int64_t)blockIdx.x * kBlock, key, hrow, valid);
     int64_t o = indptr[r];
     if (valid) {
         cols[o] = r;

@@ -1,0 +1,80 @@
+// SpMV of one block of 256 rows, shared by the single-operator kernel and the batched
+// (serving) kernel.
+#pragma once
+
+#include "engine.h"
+
+namespace qsd {
+
+// Loads the lane's row `row0 + lane` (clamped to a valid row for lanes past the end).
+template <int Wp>
+__device__ __forceinline__ int64_t load_row(const SubView &s, int64_t row0, uint64_t (&key)[Wp], uint64_t &hrow,
+                                            bool &valid) {
+    const int64_t i = row0 + threadIdx.x;
+    valid = i < s.N;
+    const int64_t r = valid ? i : s.N - 1;
+#pragma unroll
+    for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + r];
+    hrow = s.hkey[r];
+    return r;
+}
+
+// y[r] = d_r x[r] + sum over the row's present elements of H_rj x[j] for rows row0 .. row0+255,
+// all `nvec` interleaved vectors; FP64 accumulation in group order.
+template <int Wp, int NV, class ET, bool CPLX>
+__device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h, const ET *__restrict__ dre,
+                                             const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
+                                             ET *__restrict__ y, int64_t ldy, int nvec, int64_t row0,
+                                             ChunkLds<Wp> &lds) {
+    uint64_t key[Wp], hrow;
+    bool valid;
+    const int64_t r = load_row<Wp>(s, row0, key, hrow, valid);
+    double acc_re[NV], acc_im[NV];
+    {
+        const double dr = (double)dre[r];
+        const double di = CPLX ? (double)dim[r] : 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            acc_re[v] = acc_im[v] = 0.0;
+            if (v < nvec) {
+                if (CPLX) {
+                    const double xr = (double)x[2 * (r * ldx + v)], xi = (double)x[2 * (r * ldx + v) + 1];
+                    acc_re[v] = dr * xr - di * xi;
+                    acc_im[v] = dr * xi + di * xr;
+                } else {
+                    acc_re[v] = dr * (double)x[r * ldx + v];
+                }
+            }
+        }
+    }
+    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t j, uint32_t t0, uint32_t len) {
+        ET vre, vim;
+        if (!range_value<Wp, ET>(h, key, t0, len, vre, vim)) return;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (v < nvec) {
+                if (CPLX) {
+                    const double xr = (double)x[2 * (j * ldx + v)], xi = (double)x[2 * (j * ldx + v) + 1];
+                    acc_re[v] += (double)vre * xr - (double)vim * xi;
+                    acc_im[v] += (double)vre * xi + (double)vim * xr;
+                } else {
+                    acc_re[v] += (double)vre * (double)x[j * ldx + v];
+                }
+            }
+        }
+    });
+    if (!valid) return;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (v < nvec) {
+            if (CPLX) {
+                y[2 * (r * ldy + v)] = (ET)acc_re[v];
+                y[2 * (r * ldy + v) + 1] = (ET)acc_im[v];
+            } else {
+                y[r * ldy + v] = (ET)acc_re[v];
+            }
+        }
+    }
+}
+
+}  // namespace qsd

@@ -1,0 +1,737 @@
+// Batched Lanczos for serving: many ground-state solves advance together, one iteration per
+// step for every active request, with one SpMV launch and a fixed set of BLAS launches per
+// iteration whatever the number of requests (continuous batching at iteration granularity).
+//
+// Requests are independent: every reduction of a request is partitioned by its own size only
+// (2048-row tiles, summed in a fixed order), and its SpMV rows are evaluated exactly as by
+// qsd_matvec, so a request's iterates are bitwise the same alone and in any mix.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+#include "matvec.h"
+#include "tridiag.h"
+
+namespace qsd {
+namespace {
+
+constexpr int kBT = 2048;  // rows per BLAS tile
+
+struct ReqDev {
+    SubView s;
+    HamView h;
+    const double *diag;
+    const float *diag32;
+    int64_t N;
+    double *V;  // [m+1][N]
+    double *x, *w;
+    float *x32, *w32;
+    double *part;  // [(m+1)][nbt]
+    double *hv;    // [m+1]
+    double *alpha, *beta;
+    int *kdev;
+    double *tri;  // [m+4]
+    int m;
+    int nbt;
+};
+
+struct Tile {
+    int slot;
+    int idx;
+};
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+template <int Wp, class ET>
+__global__ __launch_bounds__(kBlock) void kb_matvec(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles) {
+    __shared__ ChunkLds<Wp> lds;
+    const Tile t = tiles[blockIdx.x];
+    const ReqDev &R = reqs[t.slot];
+    if (*R.kdev >= R.m) return;  // at its iteration limit (uniform for the block)
+    const bool f32 = std::is_same<ET, float>::value;
+    const ET *dre = f32 ? (const ET *)R.diag32 : (const ET *)R.diag;
+    const ET *x = f32 ? (const ET *)R.x32 : (const ET *)R.x;
+    ET *y = f32 ? (ET *)R.w32 : (ET *)R.w;
+    matvec_block<Wp, 1, ET, false>(R.s, R.h, dre, nullptr, x, 1, y, 1, 1, (int64_t)t.idx * kBlock, lds);
+}
+
+// x32 = x (to_f32) or w = w32 (back), over 2048-row tiles
+__global__ __launch_bounds__(256) void kb_convert(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles,
+                                                  int to_f32) {
+    const Tile t = tiles[blockIdx.x];
+    const ReqDev &R = reqs[t.slot];
+    if (*R.kdev >= R.m) return;
+    const int64_t a = (int64_t)t.idx * kBT, b = min(R.N, a + kBT);
+    for (int64_t i = a + threadIdx.x; i < b; i += 256) {
+        if (to_f32)
+            R.x32[i] = (float)R.x[i];
+        else
+            R.w[i] = (double)R.w32[i];
+    }
+}
+
+// part[j][tile] = sum over the tile's rows of V[j][i] w[i], j = 0..k
+__global__ __launch_bounds__(256) void kb_gemv_t(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles) {
+    const Tile t = tiles[blockIdx.x];
+    const ReqDev &R = reqs[t.slot];
+    if (*R.kdev >= R.m) return;
+    const int cnt = *R.kdev + 1;
+    const int64_t a = (int64_t)t.idx * kBT, b = min(R.N, a + kBT);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = wave; j < cnt; j += 4) {
+        const double *vj = R.V + (int64_t)j * R.N;
+        double s = 0.0;
+        for (int64_t i = a + lane; i < b; i += 64) s += vj[i] * R.w[i];
+        s = wsum(s);
+        if (lane == 0) R.part[(int64_t)j * R.nbt + t.idx] = s;
+    }
+}
+
+// hv[j] = sum of part[j][*] in tile order; alpha[k] += hv[k].  One wave per j, four per block.
+__global__ __launch_bounds__(256) void kb_reduce(const ReqDev *__restrict__ reqs, int nslots) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), slot = blockIdx.y, lane = threadIdx.x & 63;
+    if (slot >= nslots) return;
+    const ReqDev &R = reqs[slot];
+    if (R.N == 0) return;
+    const int k = *R.kdev;
+    if (k >= R.m || j > k) return;  // whole waves leave together
+    double s = 0.0;
+    for (int p = lane; p < R.nbt; p += 64) s += R.part[(int64_t)j * R.nbt + p];
+    s = wsum(s);
+    if (lane == 0) {
+        R.hv[j] = s;
+        if (j == k) R.alpha[k] += s;
+    }
+}
+
+// w[i] -= sum_{j <= k} V[j][i] hv[j] over 256-row tiles
+__global__ __launch_bounds__(kBlock) void kb_gemv_n_sub(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles) {
+    const Tile t = tiles[blockIdx.x];
+    const ReqDev &R = reqs[t.slot];
+    if (*R.kdev >= R.m) return;
+    const int cnt = *R.kdev + 1;
+    const int64_t i = (int64_t)t.idx * kBlock + threadIdx.x;
+    if (i >= R.N) return;
+    double acc = 0.0;
+    for (int j = 0; j < cnt; ++j) acc += R.V[(int64_t)j * R.N + i] * R.hv[j];
+    R.w[i] -= acc;
+}
+
+__global__ __launch_bounds__(256) void kb_sq_part(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles) {
+    __shared__ double ws[4];
+    const Tile t = tiles[blockIdx.x];
+    const ReqDev &R = reqs[t.slot];
+    if (*R.kdev >= R.m) return;  // uniform for the block
+    const int64_t a = (int64_t)t.idx * kBT, b = min(R.N, a + kBT);
+    double s = 0.0;
+    for (int64_t i = a + threadIdx.x; i < b; i += 256) s += R.w[i] * R.w[i];
+    s = wsum(s);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) R.part[t.idx] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ __launch_bounds__(64) void kb_beta(const ReqDev *__restrict__ reqs, int nslots) {
+    const int slot = blockIdx.x;
+    if (slot >= nslots) return;
+    const ReqDev &R = reqs[slot];
+    if (R.N == 0 || *R.kdev >= R.m) return;
+    double s = 0.0;
+    for (int p = threadIdx.x; p < R.nbt; p += 64) s += R.part[p];
+    s = wsum(s);
+    if (threadIdx.x == 0) R.beta[*R.kdev] = sqrt(s);
+}
+
+// x = V[k+1] = w / beta[k] (breakdown: zeros, first breakdown recorded in tri[2])
+__global__ __launch_bounds__(kBlock) void kb_next(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles) {
+    const Tile t = tiles[blockIdx.x];
+    const ReqDev &R = reqs[t.slot];
+    const int k = *R.kdev;
+    if (k >= R.m) return;
+    const double b = R.beta[k];
+    const double scale = fabs(R.alpha[k]) + (k > 0 ? R.beta[k - 1] : 0.0);
+    const bool brk = R.tri[2] != 0.0 || !(b > 1e-12 * scale) || !(b > 1e-300);
+    const double inv = brk ? 0.0 : 1.0 / b;
+    const int64_t i = (int64_t)t.idx * kBlock + threadIdx.x;
+    if (i < R.N) {
+        const double v = R.w[i] * inv;
+        R.x[i] = v;
+        if (k + 1 <= R.m) R.V[(int64_t)(k + 1) * R.N + i] = v;
+    }
+}
+
+// Breakdown bookkeeping and k += 1, one thread per slot (after kb_next has read k).
+__global__ void kb_bump(const ReqDev *__restrict__ reqs, int nslots) {
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= nslots) return;
+    const ReqDev &R = reqs[slot];
+    if (R.N == 0) return;
+    const int k = *R.kdev;
+    if (k >= R.m) return;
+    const double b = R.beta[k];
+    const double scale = fabs(R.alpha[k]) + (k > 0 ? R.beta[k - 1] : 0.0);
+    const bool brk = !(b > 1e-12 * scale) || !(b > 1e-300);
+    if (brk && R.tri[2] == 0.0) {
+        R.tri[2] = (double)(k + 1);
+        R.beta[k] = 0.0;
+    }
+    if (k + 1 < R.m) *R.kdev = k + 1;
+    else *R.kdev = R.m;  // saturates: no further iterations are taken
+}
+
+__global__ __launch_bounds__(kTriThreads) void kb_tridiag(const ReqDev *__restrict__ reqs, int nslots,
+                                                         double *__restrict__ out /*[nslots][4]*/) {
+    __shared__ TridiagLds L;
+    const int slot = blockIdx.x;
+    const ReqDev &R = reqs[slot];
+    if (R.N == 0) return;
+    const int done = R.tri[2] != 0.0 ? (int)R.tri[2] : *R.kdev;  // iterations with valid alpha
+    if (done < 1) {
+        if (threadIdx.x == 0) {
+            out[4 * slot + 0] = 0.0;
+            out[4 * slot + 1] = INFINITY;
+            out[4 * slot + 2] = 0.0;
+            out[4 * slot + 3] = 0.0;
+        }
+        return;
+    }
+    tridiag_lowest(R.alpha, R.beta, done, R.tri, L);
+    if (threadIdx.x == 0) {
+        out[4 * slot + 0] = R.tri[0];
+        out[4 * slot + 1] = R.tri[2] != 0.0 ? 0.0 : R.tri[1];
+        out[4 * slot + 2] = (double)done;
+        out[4 * slot + 3] = R.tri[2];
+    }
+}
+
+__global__ void kb_init(const ReqDev *__restrict__ reqs, int slot, int mode, uint64_t seed, int64_t spike) {
+    const ReqDev &R = reqs[slot];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < R.N; i += (int64_t)gridDim.x * blockDim.x) {
+        double v;
+        if (mode == QSD_V0_UNIFORM) {
+            v = 1.0;
+        } else if (mode == QSD_V0_MIN_DIAG) {
+            v = (i == spike) ? 1.0 : 0.0;
+        } else {
+            uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            z ^= z >> 31;
+            v = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+        }
+        R.x[i] = v;
+    }
+}
+
+// x /= ||x||, V[0] = x, alpha = beta = 0, k = 0 (one block: setup only)
+__global__ __launch_bounds__(256) void kb_start(const ReqDev *__restrict__ reqs, int slot) {
+    __shared__ double ws[4];
+    __shared__ double inv;
+    const ReqDev &R = reqs[slot];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < R.N; i += 256) s += R.x[i] * R.x[i];
+    s = wsum(s);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) inv = 1.0 / sqrt(ws[0] + ws[1] + ws[2] + ws[3]);
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < R.N; i += 256) {
+        R.x[i] *= inv;
+        R.V[i] = R.x[i];
+    }
+    for (int j = threadIdx.x; j < R.m; j += 256) {
+        R.alpha[j] = 0.0;
+        R.beta[j] = 0.0;
+    }
+    if (threadIdx.x < 4) R.tri[threadIdx.x] = 0.0;
+    if (threadIdx.x == 0) *R.kdev = 0;
+}
+
+__global__ __launch_bounds__(256) void kb_argmin(const double *__restrict__ d, int64_t N, int64_t *__restrict__ out) {
+    __shared__ double bv[256];
+    __shared__ int64_t bi[256];
+    double v = INFINITY;
+    int64_t idx = N;
+    for (int64_t i = threadIdx.x; i < N; i += 256)
+        if (d[i] < v) {
+            v = d[i];
+            idx = i;
+        }
+    bv[threadIdx.x] = v;
+    bi[threadIdx.x] = idx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int t = 1; t < 256; ++t)
+            if (bv[t] < v || (bv[t] == v && bi[t] < idx)) {
+                v = bv[t];
+                idx = bi[t];
+            }
+        *out = idx;
+    }
+}
+
+
+// Batched SpMV over independent operators: tile t of the launch is 256 rows of request
+// tiles[t].slot; every row is evaluated exactly as by qsd_matvec.
+struct MvReq {
+    SubView s;
+    HamView h;
+    const void *dre, *dim;
+    const void *x;
+    void *y;
+    int64_t ld;  // leading dimension of x and y (the request's vector count)
+    int nv;      // vectors of this launch (at most the template width)
+};
+
+template <int Wp, int NV, class ET, bool CPLX>
+__global__ __launch_bounds__(kBlock) void kbm_matvec(const MvReq *__restrict__ reqs, const Tile *__restrict__ tiles) {
+    __shared__ ChunkLds<Wp> lds;
+    const Tile t = tiles[blockIdx.x];
+    const MvReq &R = reqs[t.slot];
+    matvec_block<Wp, NV, ET, CPLX>(R.s, R.h, (const ET *)R.dre, (const ET *)R.dim, (const ET *)R.x, R.ld, (ET *)R.y,
+                                   R.ld, R.nv, (int64_t)t.idx * kBlock, lds);
+}
+
+}  // namespace
+}  // namespace qsd
+
+using namespace qsd;
+
+struct qsd_batch {
+    int max_slots = 0;
+    int max_iter = 0;
+    bool f32 = false;
+    int Wp = 0;
+    struct Slot {
+        bool used = false;
+        const qsd_ham *h = nullptr;
+        ReqDev d{};
+        void *mem = nullptr;  // the request's workspace
+        bool owned = false;   // allocated by the library (else the caller's)
+        double tol = 1e-10;
+        int steps = 0;
+    };
+    std::vector<Slot> slots;
+    ReqDev *d_reqs = nullptr;
+    Tile *d_mv = nullptr, *d_bl = nullptr;  // 256-row and 2048-row tiles
+    int n_mv = 0, n_bl = 0;
+    size_t cap_mv = 0, cap_bl = 0;
+    double *d_out = nullptr;  // [max_slots][4]
+    int64_t *d_spike = nullptr;
+    bool dirty = true;
+};
+
+namespace {
+
+void free_slot(qsd_batch::Slot &S) {
+    if (S.owned) dev_free(S.mem);
+    S = qsd_batch::Slot();
+}
+
+// Workspace layout of one request: every array starts on a 256-byte boundary.
+struct Layout {
+    int64_t V, x, w, x32, w32, part, hv, alpha, beta, kdev, tri, total;
+};
+
+Layout layout_of(int64_t N, int m, bool f32) {
+    const int64_t nbt = (N + kBT - 1) / kBT;
+    Layout L{};
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    L.V = take((int64_t)(m + 1) * N * 8);
+    L.x = take(N * 8);
+    L.w = take(N * 8);
+    L.x32 = f32 ? take(N * 4) : -1;
+    L.w32 = f32 ? take(N * 4) : -1;
+    L.part = take((int64_t)(m + 1) * nbt * 8);
+    L.hv = take((int64_t)(m + 1) * 8);
+    L.alpha = take((int64_t)m * 8);
+    L.beta = take((int64_t)m * 8);
+    L.kdev = take(8);
+    L.tri = take((int64_t)(m + 4) * 8);
+    L.total = off;
+    return L;
+}
+
+int sync_tables(qsd_batch *b, hipStream_t st) {
+    if (!b->dirty) return QSD_OK;
+    std::vector<ReqDev> host(b->max_slots);
+    std::vector<Tile> mv, bl;
+    for (int i = 0; i < b->max_slots; ++i) {
+        const auto &S = b->slots[i];
+        if (!S.used) {
+            host[i] = ReqDev{};
+            host[i].N = 0;
+            continue;
+        }
+        host[i] = S.d;
+        for (int64_t t = 0; t < (S.d.N + kBlock - 1) / kBlock; ++t) mv.push_back({i, (int)t});
+        for (int t = 0; t < S.d.nbt; ++t) bl.push_back({i, t});
+    }
+    if (mv.size() > b->cap_mv) {
+        dev_free(b->d_mv);
+        b->cap_mv = mv.size() * 2;
+        QSD_TRY(dev_alloc(&b->d_mv, b->cap_mv));
+    }
+    if (bl.size() > b->cap_bl) {
+        dev_free(b->d_bl);
+        b->cap_bl = bl.size() * 2;
+        QSD_TRY(dev_alloc(&b->d_bl, b->cap_bl));
+    }
+    QSD_CHECK_HIP(hipMemcpyAsync(b->d_reqs, host.data(), host.size() * sizeof(ReqDev), hipMemcpyHostToDevice, st));
+    if (!mv.empty()) QSD_CHECK_HIP(hipMemcpyAsync(b->d_mv, mv.data(), mv.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
+    if (!bl.empty()) QSD_CHECK_HIP(hipMemcpyAsync(b->d_bl, bl.data(), bl.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
+    // the host vectors are staged by the runtime before the calls return (pageable copies)
+    QSD_CHECK_HIP(hipStreamSynchronize(st));
+    b->n_mv = (int)mv.size();
+    b->n_bl = (int)bl.size();
+    b->dirty = false;
+    return QSD_OK;
+}
+
+template <int Wp>
+void launch_bmv(qsd_batch *b, hipStream_t st) {
+    if (b->f32)
+        kb_matvec<Wp, float><<<b->n_mv, kBlock, 0, st>>>(b->d_reqs, b->d_mv);
+    else
+        kb_matvec<Wp, double><<<b->n_mv, kBlock, 0, st>>>(b->d_reqs, b->d_mv);
+}
+
+}  // namespace
+
+extern "C" int qsd_batch_create(int32_t max_requests, int32_t max_iter, int32_t spmv_dtype, qsd_batch **out) {
+    clear_error();
+    if (!out) return fail(QSD_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (max_requests < 1 || max_requests > 4096) return fail(QSD_ERR_INVALID_ARG, "max_requests must be in [1, 4096]");
+    if (max_iter < 2 || max_iter > 1000) return fail(QSD_ERR_INVALID_ARG, "max_iter must be in [2, 1000]");
+    if (spmv_dtype != QSD_F64 && spmv_dtype != QSD_F32) return fail(QSD_ERR_DTYPE, "spmv_dtype must be F64 or F32");
+    auto *b = new (std::nothrow) qsd_batch();
+    if (!b) return fail(QSD_ERR_OUT_OF_MEMORY, "host allocation failed");
+    b->max_slots = max_requests;
+    b->max_iter = max_iter;
+    b->f32 = spmv_dtype == QSD_F32;
+    b->slots.resize(max_requests);
+    int rc = dev_alloc(&b->d_reqs, max_requests);
+    if (rc == QSD_OK) rc = dev_alloc(&b->d_out, 4 * (size_t)max_requests);
+    if (rc == QSD_OK) rc = dev_alloc(&b->d_spike, 1);
+    if (rc != QSD_OK) {
+        dev_free(b->d_reqs);
+        dev_free(b->d_out);
+        dev_free(b->d_spike);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return QSD_OK;
+}
+
+extern "C" int qsd_batch_footprint(const qsd_ham *h, int32_t max_iter, int32_t spmv_dtype, int64_t *bytes) {
+    clear_error();
+    if (!h || !bytes) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+    if (max_iter < 2 || max_iter > 1000) return fail(QSD_ERR_INVALID_ARG, "max_iter must be in [2, 1000]");
+    *bytes = layout_of(h->N, (int)std::min<int64_t>(max_iter, h->N), spmv_dtype == QSD_F32).total;
+    return QSD_OK;
+}
+
+extern "C" int qsd_batch_add(qsd_batch *b, const qsd_ham *h, int32_t v0_mode, uint64_t seed, double tol,
+                             void *workspace, int64_t workspace_bytes, int32_t *slot_out, void *stream) {
+    clear_error();
+    if (!b || !h || !slot_out) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+    if (h->is_complex) return fail(QSD_ERR_UNSUPPORTED, "batched Lanczos is real only");
+    if (v0_mode != QSD_V0_UNIFORM && v0_mode != QSD_V0_MIN_DIAG && v0_mode != QSD_V0_RANDOM)
+        return fail(QSD_ERR_INVALID_ARG, "v0_mode must be UNIFORM, MIN_DIAG or RANDOM");
+    if (!(tol > 0)) return fail(QSD_ERR_INVALID_ARG, "tol must be > 0");
+    if (h->N < 1) return fail(QSD_ERR_INVALID_ARG, "empty subspace");
+    bool any = false;
+    for (auto &S : b->slots) any |= S.used;
+    if (any && h->Wp != b->Wp) return fail(QSD_ERR_UNSUPPORTED, "all requests of a batch must have the same key width");
+    int slot = -1;
+    for (int i = 0; i < b->max_slots; ++i)
+        if (!b->slots[i].used) {
+            slot = i;
+            break;
+        }
+    if (slot < 0) return fail(QSD_ERR_CAPACITY, "no free request slot");
+    hipStream_t st = (hipStream_t)stream;
+    auto &S = b->slots[slot];
+    S = qsd_batch::Slot();
+    ReqDev &d = S.d;
+    const int64_t N = h->N;
+    d.N = N;
+    d.m = (int)std::min<int64_t>(b->max_iter, N);
+    d.nbt = (int)((N + kBT - 1) / kBT);
+    d.s = SubView{h->s->keys, h->s->hkey, h->s->slots, h->s->bitmap, h->s->N, (uint32_t)(h->s->C - 1)};
+    d.h = HamView{h->g_mask, h->g_hash, h->g_pos, h->g_scan, h->g_info, h->g_term0, h->g_nterm, h->g_iptr, h->t_cws,
+                  b->f32 ? (const void *)h->t_coef32 : (const void *)h->t_coef, h->G};
+    d.diag = h->diag;
+    d.diag32 = h->diag32;
+    const Layout L = layout_of(N, d.m, b->f32);
+    int rc = QSD_OK;
+    if (workspace) {
+        if (((uintptr_t)workspace & 255) != 0) return fail(QSD_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+        if (workspace_bytes < L.total)
+            return fail(QSD_ERR_INVALID_ARG, "workspace of %lld bytes is smaller than the %lld needed",
+                        (long long)workspace_bytes, (long long)L.total);
+        S.mem = workspace;
+        S.owned = false;
+    } else {
+        uint8_t *p = nullptr;
+        if ((rc = dev_alloc(&p, (size_t)L.total)) != QSD_OK) {
+            S = qsd_batch::Slot();
+            return rc;
+        }
+        S.mem = p;
+        S.owned = true;
+    }
+    uint8_t *base = (uint8_t *)S.mem;
+    d.V = (double *)(base + L.V);
+    d.x = (double *)(base + L.x);
+    d.w = (double *)(base + L.w);
+    d.x32 = b->f32 ? (float *)(base + L.x32) : nullptr;
+    d.w32 = b->f32 ? (float *)(base + L.w32) : nullptr;
+    d.part = (double *)(base + L.part);
+    d.hv = (double *)(base + L.hv);
+    d.alpha = (double *)(base + L.alpha);
+    d.beta = (double *)(base + L.beta);
+    d.kdev = (int *)(base + L.kdev);
+    d.tri = (double *)(base + L.tri);
+    S.used = true;
+    S.h = h;
+    S.tol = tol;
+    b->Wp = h->Wp;
+    b->dirty = true;
+    if ((rc = sync_tables(b, st)) != QSD_OK) {
+        free_slot(S);
+        b->dirty = true;
+        return rc;
+    }
+    int64_t spike = 0;
+    if (v0_mode == QSD_V0_MIN_DIAG) {
+        kb_argmin<<<1, 256, 0, st>>>(h->diag, N, b->d_spike);
+        if (hipMemcpyAsync(&spike, b->d_spike, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            rc = fail(QSD_ERR_HIP, "argmin failed");
+    }
+    if (rc == QSD_OK) {
+        kb_init<<<256, 256, 0, st>>>(b->d_reqs, slot, v0_mode, seed, spike);
+        kb_start<<<1, 256, 0, st>>>(b->d_reqs, slot);
+        if (hipGetLastError() != hipSuccess) rc = fail(QSD_ERR_HIP, "request start failed");
+    }
+    if (rc != QSD_OK) {
+        free_slot(S);
+        b->dirty = true;
+        return rc;
+    }
+    *slot_out = slot;
+    return QSD_OK;
+}
+
+extern "C" int qsd_batch_step(qsd_batch *b, int32_t iterations, void *stream) {
+    clear_error();
+    if (!b || iterations < 0) return fail(QSD_ERR_INVALID_ARG, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    QSD_TRY(sync_tables(b, st));
+    if (b->n_mv == 0) return QSD_OK;
+    const int ns = b->max_slots;
+    for (int it = 0; it < iterations; ++it) {
+        if (b->f32) kb_convert<<<b->n_bl, 256, 0, st>>>(b->d_reqs, b->d_bl, 1);
+        switch (b->Wp) {
+            case 1: launch_bmv<1>(b, st); break;
+            case 2: launch_bmv<2>(b, st); break;
+            case 4: launch_bmv<4>(b, st); break;
+            case 8: launch_bmv<8>(b, st); break;
+            case 16: launch_bmv<16>(b, st); break;
+        }
+        if (b->f32) kb_convert<<<b->n_bl, 256, 0, st>>>(b->d_reqs, b->d_bl, 0);
+        for (int pass = 0; pass < 2; ++pass) {
+            kb_gemv_t<<<b->n_bl, 256, 0, st>>>(b->d_reqs, b->d_bl);
+            kb_reduce<<<dim3((b->max_iter + 4) / 4, ns), 256, 0, st>>>(b->d_reqs, ns);
+            kb_gemv_n_sub<<<b->n_mv, kBlock, 0, st>>>(b->d_reqs, b->d_mv);
+        }
+        kb_sq_part<<<b->n_bl, 256, 0, st>>>(b->d_reqs, b->d_bl);
+        kb_beta<<<ns, 64, 0, st>>>(b->d_reqs, ns);
+        kb_next<<<b->n_mv, kBlock, 0, st>>>(b->d_reqs, b->d_mv);
+        kb_bump<<<(ns + 63) / 64, 64, 0, st>>>(b->d_reqs, ns);
+    }
+    for (auto &S : b->slots)
+        if (S.used) S.steps += iterations;
+    QSD_CHECK_HIP(hipGetLastError());
+    return QSD_OK;
+}
+
+extern "C" int qsd_batch_poll(qsd_batch *b, int32_t *status, double *energy, int32_t *iterations,
+                              double *ritz_residual, void *stream) {
+    clear_error();
+    if (!b) return fail(QSD_ERR_INVALID_ARG, "batch is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    QSD_TRY(sync_tables(b, st));
+    const int ns = b->max_slots;
+    std::vector<double> out(4 * (size_t)ns, 0.0);
+    if (b->n_mv > 0) {
+        kb_tridiag<<<ns, kTriThreads, 0, st>>>(b->d_reqs, ns, b->d_out);
+        QSD_CHECK_HIP(hipMemcpyAsync(out.data(), b->d_out, out.size() * 8, hipMemcpyDeviceToHost, st));
+        QSD_CHECK_HIP(hipStreamSynchronize(st));
+    }
+    for (int i = 0; i < ns; ++i) {
+        const auto &S = b->slots[i];
+        int stv = 0;  // 0 = free slot
+        if (S.used) {
+            const double th = out[4 * i], rr = out[4 * i + 1];
+            const int done = (int)out[4 * i + 2];
+            const bool brk = out[4 * i + 3] != 0.0;
+            if (brk || (done > 0 && rr <= S.tol * std::fabs(th)))
+                stv = 2;  // converged
+            else if (done >= S.d.m)
+                stv = 3;  // iteration limit
+            else
+                stv = 1;  // running
+            if (energy) energy[i] = th;
+            if (iterations) iterations[i] = done;
+            if (ritz_residual) ritz_residual[i] = rr;
+        }
+        if (status) status[i] = stv;
+    }
+    return QSD_OK;
+}
+
+extern "C" int qsd_batch_remove(qsd_batch *b, int32_t slot) {
+    clear_error();
+    if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(QSD_ERR_INVALID_ARG, "bad slot");
+    // device work that reads the slot was enqueued before; hipFree of an owned workspace waits
+    // for the device, a caller's workspace must stay valid until that work has finished
+    free_slot(b->slots[slot]);
+    b->dirty = true;
+    return QSD_OK;
+}
+
+extern "C" int qsd_batch_destroy(qsd_batch *b) {
+    clear_error();
+    if (!b) return QSD_OK;
+    for (auto &S : b->slots)
+        if (S.used) free_slot(S);
+    dev_free(b->d_reqs);
+    dev_free(b->d_mv);
+    dev_free(b->d_bl);
+    dev_free(b->d_out);
+    dev_free(b->d_spike);
+    delete b;
+    return QSD_OK;
+}
+
+namespace {
+
+template <int Wp, class ET, bool CPLX>
+void launch_bmv_any(int nv_max, int tiles, const MvReq *reqs, const Tile *tl, hipStream_t st) {
+    if (nv_max <= 1)
+        kbm_matvec<Wp, 1, ET, CPLX><<<tiles, kBlock, 0, st>>>(reqs, tl);
+    else if (nv_max <= 4 || CPLX)
+        kbm_matvec<Wp, 4, ET, CPLX><<<tiles, kBlock, 0, st>>>(reqs, tl);
+    else
+        kbm_matvec<Wp, 16, ET, CPLX><<<tiles, kBlock, 0, st>>>(reqs, tl);
+}
+
+template <class ET, bool CPLX>
+void launch_bmv_w(int Wp, int nv_max, int tiles, const MvReq *reqs, const Tile *tl, hipStream_t st) {
+    switch (Wp) {
+        case 1: launch_bmv_any<1, ET, CPLX>(nv_max, tiles, reqs, tl, st); break;
+        case 2: launch_bmv_any<2, ET, CPLX>(nv_max, tiles, reqs, tl, st); break;
+        case 4: launch_bmv_any<4, ET, CPLX>(nv_max, tiles, reqs, tl, st); break;
+        case 8: launch_bmv_any<8, ET, CPLX>(nv_max, tiles, reqs, tl, st); break;
+        case 16: launch_bmv_any<16, ET, CPLX>(nv_max, tiles, reqs, tl, st); break;
+    }
+}
+
+}  // namespace
+
+extern "C" int qsd_matvec_batched(int32_t n, const qsd_ham *const *hams, const void *const *xs, void *const *ys,
+                                  const int32_t *nvecs, int32_t dtype, void *stream) {
+    clear_error();
+    if (n < 0 || (n > 0 && (!hams || !xs || !ys || !nvecs))) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+    if (dtype < QSD_F64 || dtype > QSD_C64) return fail(QSD_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+    const bool cplx = dtype == QSD_C128 || dtype == QSD_C64;
+    const bool f32 = dtype == QSD_F32 || dtype == QSD_C64;
+    const size_t esz = dtype == QSD_F64 ? 8 : dtype == QSD_F32 ? 4 : dtype == QSD_C128 ? 16 : 8;
+    for (int i = 0; i < n; ++i) {
+        if (!hams[i] || !xs[i] || !ys[i]) return fail(QSD_ERR_INVALID_ARG, "NULL operator or vector in request %d", i);
+        if (nvecs[i] < 1 || nvecs[i] > 16) return fail(QSD_ERR_INVALID_ARG, "nvecs[%d] must be in [1, 16]", i);
+        if (hams[i]->is_complex != cplx)
+            return fail(QSD_ERR_DTYPE, "dtype %d does not match the %s operator of request %d", dtype,
+                        hams[i]->is_complex ? "complex" : "real", i);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    // One launch per (key width, vector chunk); complex vectors go in chunks of four.
+    const int chunk = cplx ? 4 : 16;
+    std::vector<MvReq> reqs;
+    std::vector<Tile> tiles;
+    struct Launch {
+        int Wp, nv_max;
+        size_t t0, nt;
+    };
+    std::vector<Launch> launches;
+    for (int Wp : {1, 2, 4, 8, 16}) {
+        for (int c0 = 0; c0 < 16; c0 += chunk) {
+            Launch L{Wp, 0, tiles.size(), 0};
+            for (int i = 0; i < n; ++i) {
+                const qsd_ham *h = hams[i];
+                if (h->Wp != Wp || nvecs[i] <= c0 || h->N == 0) continue;
+                MvReq R{};
+                R.s = SubView{h->s->keys, h->s->hkey, h->s->slots, h->s->bitmap, h->s->N, (uint32_t)(h->s->C - 1)};
+                R.h = HamView{h->g_mask, h->g_hash, h->g_pos, h->g_scan, h->g_info, h->g_term0, h->g_nterm, h->g_iptr,
+                              h->t_cws, f32 ? (const void *)h->t_coef32 : (const void *)h->t_coef, h->G};
+                R.dre = f32 ? (const void *)h->diag32 : (const void *)h->diag;
+                R.dim = cplx ? (f32 ? (const void *)h->diag32_im : (const void *)h->diag_im) : nullptr;
+                R.x = (const char *)xs[i] + c0 * esz;
+                R.y = (char *)ys[i] + c0 * esz;
+                R.ld = nvecs[i];
+                R.nv = std::min(chunk, nvecs[i] - c0);
+                L.nv_max = std::max(L.nv_max, R.nv);
+                const int slot = (int)reqs.size();
+                reqs.push_back(R);
+                for (int64_t t = 0; t < (h->N + kBlock - 1) / kBlock; ++t) tiles.push_back({slot, (int)t});
+            }
+            L.nt = tiles.size() - L.t0;
+            if (L.nt > 0) launches.push_back(L);
+        }
+    }
+    if (launches.empty()) return QSD_OK;
+    if (tiles.size() > (size_t)INT32_MAX) return fail(QSD_ERR_CAPACITY, "too many row tiles");
+    // Stream-ordered tables: allocated, filled, used and released in order on `stream`.
+    MvReq *d_reqs = nullptr;
+    Tile *d_tiles = nullptr;
+    QSD_CHECK_HIP(hipMallocAsync((void **)&d_reqs, reqs.size() * sizeof(MvReq), st));
+    if (hipMallocAsync((void **)&d_tiles, tiles.size() * sizeof(Tile), st) != hipSuccess) {
+        (void)hipFreeAsync(d_reqs, st);
+        return fail(QSD_ERR_OUT_OF_MEMORY, "tile table allocation failed");
+    }
+    int rc = QSD_OK;
+    // pageable sources: the copies return once the host data is staged
+    if (hipMemcpyAsync(d_reqs, reqs.data(), reqs.size() * sizeof(MvReq), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = fail(QSD_ERR_HIP, "table upload failed");
+    if (rc == QSD_OK) {
+        for (const auto &L : launches) {
+            const Tile *tl = d_tiles + L.t0;
+            switch (dtype) {
+                case QSD_F64: launch_bmv_w<double, false>(L.Wp, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
+                case QSD_F32: launch_bmv_w<float, false>(L.Wp, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
+                case QSD_C128: launch_bmv_w<double, true>(L.Wp, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
+                case QSD_C64: launch_bmv_w<float, true>(L.Wp, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
+            }
+        }
+        if (hipGetLastError() != hipSuccess) rc = fail(QSD_ERR_HIP, "batched matvec launch failed");
+    }
+    (void)hipFreeAsync(d_tiles, st);
+    (void)hipFreeAsync(d_reqs, st);
+    return rc;
+}

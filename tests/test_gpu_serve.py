@@ -1,0 +1,215 @@
+"""Serving: batched SpMV and batched (continuous-batching) Lanczos through the C-ABI.
+
+* ``qsd_matvec_batched`` is bitwise equal to separate ``qsd_matvec`` calls (same row engine).
+* A request's iterates in a batch depend on its own data only: energies and residual estimates
+  are bitwise the same alone and in a mix, whatever joins or leaves meanwhile.
+* Batched ground energies agree with the single-request solver and the oracle within 1e-10
+  relative (FP64), or within the FP32-SpMV tolerance.
+* The server admits by HBM footprint: the resident workspace never exceeds the budget.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import closed_forms as ocf
+from oracle import lanczos as olz
+from oracle import rowwise as orw
+from oracle import subspace as osub
+
+from _util import c2_keys, c3_parts, dyadic, dyadic_vector, heavy_hex_small, say
+
+torch = pytest.importorskip("torch")
+qsd = pytest.importorskip("paper_2603_18731_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    qsd.lib()
+
+
+def _ham(keys, tl):
+    sub = qsd.Subspace(keys, tl.n_qubits)
+    op = qsd.operator_from_termlist(tl)
+    return qsd.SubspaceHamiltonian(sub, op)
+
+
+@pytest.fixture(scope="module")
+def hams():
+    c1 = wl.c1_tfim12()
+    ops3, keys3 = c3_parts(40, 40)
+    return {
+        "tfim12": _ham(c1.keys, c1.ops),
+        "xxz20k": _ham(c2_keys(20_000), wl.xxz_grid_6x6()),
+        "fermi1600": _ham(keys3, ops3),
+        "xxz3k": _ham(c2_keys(3_000), wl.xxz_grid_6x6()),
+    }
+
+
+@pytest.fixture(scope="module")
+def oracle_energies():
+    out = {"tfim12": -2.0 / math.sin(math.pi / 24)}
+    ops3, keys3 = c3_parts(40, 40)
+    for name, keys, tl in (("xxz20k", c2_keys(20_000), wl.xxz_grid_6x6()), ("fermi1600", keys3, ops3)):
+        A = orw.csr_c(osub.canonical_keys(keys), tl).real.tocsr()
+        e, _, _ = olz.lanczos_ground(lambda v, A=A: A @ v, A.shape[0], tol=1e-13, max_iter=800)
+        out[name] = e
+    return out
+
+
+def _run_to_end(batch, polls=100, k=5):
+    for _ in range(polls):
+        batch.step(k)
+        st, e, it, rr = batch.poll()
+        act = st[st != 0]
+        if np.all((act == 2) | (act == 3)):
+            return st, e, it, rr
+    raise AssertionError("batch did not finish")
+
+
+# ------------------------------------------------------------------ batched SpMV
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_matvec_batched_bitwise(hams, dtype):
+    rng = np.random.default_rng(7)
+    hh, ops_hex_keys = heavy_hex_small(4_000)
+    H4 = _ham(ops_hex_keys, hh)  # four key words: a second launch
+    hs = [hams["tfim12"], hams["xxz20k"], H4, hams["fermi1600"], hams["xxz3k"]]
+    nvecs = [1, 3, 8, 16, 2]
+    xs = []
+    for h, nv in zip(hs, nvecs):
+        x = rng.standard_normal((h.N, nv)) if nv > 1 else rng.standard_normal(h.N)
+        xs.append(torch.from_numpy(x).to(dtype).cuda())
+    say("matvec_batched", dtype, [h.N for h in hs])
+    ys = qsd.matvec_batched(hs, xs)
+    for h, x, y in zip(hs, xs, ys):
+        ref = h.matvec(x)
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref)
+
+
+def test_matvec_batched_complex():
+    rng = np.random.default_rng(12)
+    n = 10
+    terms = []
+    for _ in range(40):
+        m = int(rng.integers(1, 4))
+        qs = rng.choice(n, size=m, replace=False)
+        word = [(int(q), int(rng.integers(0, 7))) for q in qs]
+        c = complex(rng.normal(), rng.normal())
+        terms.append((c, word))
+        terms.append((c.conjugate(), [(q, {5: 6, 6: 5}.get(k, k)) for q, k in word]))
+    tl = dyadic(wl.TermList.from_terms(n, terms))
+    keys = osub.ints_to_keys(sorted(rng.choice(1 << n, size=700, replace=False).tolist()), 1)
+    H = _ham(keys, tl)
+    assert H.is_complex
+    ck = osub.canonical_keys(keys)
+    x = dyadic_vector(rng, H.N, nvec=6) + 1j * dyadic_vector(rng, H.N, nvec=6)
+    x1 = dyadic_vector(rng, H.N) + 1j * dyadic_vector(rng, H.N)
+    say("matvec_batched complex")
+    ys = qsd.matvec_batched([H, H], [torch.from_numpy(x).cuda(), torch.from_numpy(x1).cuda()])
+    np.testing.assert_array_equal(ys[0].cpu().numpy(), orw.matvec_c(ck, tl, x))
+    np.testing.assert_array_equal(ys[1].cpu().numpy(), orw.matvec_c(ck, tl, x1[:, None])[:, 0])
+    with pytest.raises(qsd.QsdError, match="DTYPE"):
+        qsd.matvec_batched([H], [torch.zeros(H.N, dtype=torch.float64, device="cuda")])
+
+
+# ------------------------------------------------------------------ batched Lanczos
+
+def test_batch_energies(hams, oracle_energies):
+    b = qsd.LanczosBatch(8, max_iter=300)
+    slots = {name: b.add(hams[name], tol=1e-10) for name in ("tfim12", "xxz20k", "fermi1600")}
+    say("batch energies", slots)
+    st, e, it, rr = _run_to_end(b)
+    for name, s in slots.items():
+        assert st[s] == 2, (name, st[s], it[s], rr[s])
+        e_single, _, info = hams[name].lanczos(tol=1e-10)
+        e_o = oracle_energies[name]
+        say(name, "batch", e[s], "iters", it[s], "single", e_single, info["iterations"], "oracle", e_o)
+        assert abs(e[s] - e_o) / abs(e_o) < 1e-10
+        assert abs(e[s] - e_single) / abs(e_single) < 1e-10
+
+
+@pytest.mark.parametrize("spmv_dtype", ["f64", "f32"])
+def test_alone_vs_mix_bitwise(hams, spmv_dtype):
+    """Request A takes 30 iterations alone, and 30 in a batch where B runs from the start and
+    C joins after 10 iterations and B leaves after 20: A's results are bitwise the same."""
+    A = hams["fermi1600"]
+    alone = qsd.LanczosBatch(4, max_iter=200, spmv_dtype=spmv_dtype)
+    sa = alone.add(A, v0="random", seed=11)
+    alone.step(30)
+    ra = alone.poll()
+
+    mix = qsd.LanczosBatch(4, max_iter=200, spmv_dtype=spmv_dtype)
+    sb = mix.add(hams["xxz20k"], v0="min_diag")
+    sm = mix.add(A, v0="random", seed=11)
+    assert sm != sa  # A sits in another slot of the table
+    mix.step(10)
+    sc = mix.add(hams["tfim12"])
+    mix.step(10)
+    mix.poll()
+    mix.remove(sb)
+    mix.step(10)
+    rm = mix.poll()
+    say("alone vs mix", spmv_dtype, ra[1][sa], rm[1][sm], ra[3][sa], rm[3][sm])
+    assert ra[2][sa] == rm[2][sm] == 30
+    assert ra[1][sa] == rm[1][sm]  # energy, bitwise
+    assert ra[3][sa] == rm[3][sm]  # residual estimate, bitwise
+    assert rm[0][sc] == 1 and rm[2][sc] == 20
+    assert rm[0][sb] == 0
+
+
+def test_batch_f32_energy(hams, oracle_energies):
+    b = qsd.LanczosBatch(4, max_iter=300, spmv_dtype="f32")
+    s = b.add(hams["xxz20k"], tol=1e-7, v0="min_diag")
+    st, e, it, rr = _run_to_end(b)
+    err = abs(e[s] - oracle_energies["xxz20k"]) / abs(oracle_energies["xxz20k"])
+    say("batch f32 xxz20k rel err", err, "iters", it[s])
+    assert st[s] == 2 and err < 1e-5
+
+
+def test_batch_errors(hams):
+    b = qsd.LanczosBatch(1, max_iter=50)
+    b.add(hams["tfim12"])
+    with pytest.raises(qsd.QsdError, match="CAPACITY"):
+        b.add(hams["xxz3k"])
+    b2 = qsd.LanczosBatch(2, max_iter=50)
+    hh, keys = heavy_hex_small(2_000)
+    b2.add(hams["tfim12"])
+    with pytest.raises(qsd.QsdError, match="UNSUPPORTED"):
+        b2.add(_ham(keys, hh))  # four key words after one
+    fp = b2.footprint(hams["xxz3k"])
+    short = torch.empty(fp - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(qsd.QsdError, match="INVALID_ARG"):
+        b2.add(hams["xxz3k"], workspace=short)
+    with pytest.raises(qsd.QsdError, match="INVALID_ARG"):
+        b2.remove(1)
+    cx = wl.TermList.from_terms(3, [(1.0, [(0, 4)]), (0.5, [(1, 3)])])  # Y on qubit 0: complex
+    b3 = qsd.LanczosBatch(2, max_iter=50)
+    with pytest.raises(qsd.QsdError, match="UNSUPPORTED"):
+        b3.add(_ham(wl.full_space(3), cx))
+
+
+def test_server_admission(hams):
+    from paper_2603_18731_amd import serve
+
+    names = ["xxz20k", "fermi1600", "tfim12", "xxz3k", "xxz20k", "tfim12"]
+    srv = serve.Server(hbm_budget=1, max_iter=300, lane_bounds=(5000,), lane_slots=(4, 4))
+    fps = [srv.footprint(serve.Request(i, hams[n])) for i, n in enumerate(names)]
+    budget = int(max(fps) * 1.6)  # at most one large request resident at a time
+    srv = serve.Server(hbm_budget=budget, max_iter=300, lane_bounds=(5000,), lane_slots=(4, 4))
+    reqs = [serve.Request(i, hams[n], arrival=0.002 * i) for i, n in enumerate(names)]
+    done = srv.run(reqs)
+    say("server peak", srv.peak_used, "budget", budget, "peak active", srv.peak_active)
+    assert len(done) == len(names) and srv.used == 0
+    assert srv.peak_used <= budget
+    singles = {n: hams[n].lanczos(tol=1e-10)[0] for n in set(names)}
+    for r in done:
+        assert r.status == 2
+        assert r.finished >= r.admitted >= r.arrival
+        assert abs(r.energy - singles[names[r.rid]]) / abs(singles[names[r.rid]]) < 1e-10
