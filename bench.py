@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "matrix elements/s in matrix-free SpMV; ground-state solve s; serve p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2603_18731_amd/csrc/engine.h", "paper_2603_18731_amd/csrc/ham.hip",
+                  "paper_2603_18731_amd/csrc/matvec.h",
                   "paper_2603_18731_amd/csrc/device.h"]
 
 
@@ -133,6 +134,109 @@ def cpu_baseline(w, nnz_total, budget_s=12.0):
             "sample": sample, "matvec_s": t_mv}
 
 
+def serve_bench(args):
+    """Serving workload: requests drawn from the three families (TFIM-12, XXZ 6x6 at weight 18,
+    16-orbital molecular), subspace sizes log-uniform in [1e3, smax], each a ground-state solve to
+    1e-10 (FP64 SpMV) or 1e-7 (FP32 SpMV).  Baseline: the plain FP64 single-vector solver serving
+    the same requests FIFO one at a time; its per-request solve times are measured, and its
+    latencies under the same arrival times follow from the FIFO recurrence."""
+    import numpy as np
+    import torch
+
+    import paper_2603_18731_amd as qsd
+    import workloads as wl
+    from paper_2603_18731_amd import serve
+
+    torch.cuda.set_device(0)
+    t_setup = time.perf_counter()
+    specs = wl.serving_requests(args.serve_requests, smax=args.serve_smax)
+    h, eri = wl.molecular_integrals(16, 3)
+    fam_ops = {"tfim12": wl.tfim_chain(12, 1.0, 1.0, True), "xxz6x6": wl.xxz_grid_6x6(),
+               "fermi16": wl.molecular_terms(h, eri)}
+    ops = {k: qsd.operator_from_termlist(v) for k, v in fam_ops.items()}
+    hams = []
+    for i, (fam, size, sub_seed) in enumerate(specs):
+        keys = wl.serving_subspace(fam, size, sub_seed)
+        hams.append(qsd.SubspaceHamiltonian(qsd.Subspace(keys, fam_ops[fam].n_qubits), ops[fam]))
+        if (i + 1) % 32 == 0:
+            print("# built %d/%d request operators (%.0f s)" % (i + 1, len(specs), time.perf_counter() - t_setup),
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    sizes = np.array([H.N for H in hams])
+    n = len(hams)
+    print("# %d requests, %d rows in total, setup %.0f s" % (n, sizes.sum(), time.perf_counter() - t_setup),
+          file=sys.stderr, flush=True)
+    tol = 1e-10 if args.dtype == "f64" else 1e-7
+    max_iter = 300
+
+    # FIFO baseline: plain FP64 single-vector Lanczos, one request at a time
+    service = np.zeros(n)
+    e_fifo = np.zeros(n)
+    iters_fifo = np.zeros(n, dtype=np.int64)
+    for i, H in enumerate(hams):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e, _, info = H.lanczos(tol=1e-10, max_iter=max_iter, v0="uniform", raise_on_nonconv=False)
+        service[i] = time.perf_counter() - t0
+        e_fifo[i], iters_fifo[i] = e, info["iterations"]
+        if (i + 1) % 32 == 0:
+            print("# fifo %d/%d solved (%.1f s of service so far)" % (i + 1, n, service.sum()), file=sys.stderr,
+                  flush=True)
+    mu_fifo = n / service.sum()
+
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.85 * free)
+
+    def run(arrivals, label):
+        srv = serve.Server(budget, max_iter=max_iter, spmv_dtype=args.dtype)
+        reqs = [serve.Request(i, hams[i], arrival=float(arrivals[i]), tol=tol) for i in range(n)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = srv.run(reqs, progress=lambda k: k % 32 == 0 and print(
+            "# %s: %d/%d done (%.1f s)" % (label, k, n, time.perf_counter() - t0), file=sys.stderr, flush=True))
+        span = max(r.finished for r in done)
+        lat = np.array([r.latency for r in sorted(done, key=lambda r: r.rid)])
+        en = np.array([r.energy for r in sorted(done, key=lambda r: r.rid)])
+        err = np.abs(en - e_fifo) / np.abs(e_fifo)
+        res = dict(serve.percentiles(lat), solves_per_s=n / span, makespan_s=span,
+                   converged=int(sum(r.status == 2 for r in done)),
+                   energy_max_rel_err_vs_fp64=float(err.max()), peak_hbm_gb=srv.peak_used / 1e9,
+                   peak_active=srv.peak_active)
+        print("# %s: %s" % (label, json.dumps(res)), file=sys.stderr, flush=True)
+        return res
+
+    closed = run(np.zeros(n), "closed loop")
+    mu = closed["solves_per_s"]
+    fifo_closed_lat = serve.fifo_latencies(np.zeros(n), service)
+    out_open = {}
+    fifo_open = {}
+    for f in (0.7, 0.9):
+        arr = serve.poisson_arrivals(n, f * mu, seed=5 + int(f * 10))
+        out_open["lambda_%.1f_mu" % f] = dict(run(arr, "open loop %.1f mu" % f), rate_per_s=f * mu)
+        fifo_open["lambda_%.1f_mu" % f] = serve.percentiles(serve.fifo_latencies(arr, service))
+    out = {
+        "metric": "serve p50/p99 ms; solves/s",
+        "value": mu,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": n,
+        "warmup": 0,
+        "ms_per_step": closed["makespan_s"] * 1e3 / n,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "serve_%d_requests_1e3_%.0e" % (n, args.serve_smax), "rows_total": int(sizes.sum()),
+                   "tol": tol, "max_iter": max_iter, "hbm_budget_gb": budget / 1e9},
+        "serve": {"closed_loop": closed, **out_open},
+        "fifo_fp64_single_vector": {"solves_per_s": mu_fifo, "service_s_total": float(service.sum()),
+                                    "closed_loop": serve.percentiles(fifo_closed_lat), **fifo_open,
+                                    "iterations_mean": float(iters_fifo.mean())},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,13 +246,24 @@ def main():
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--nvec", type=int, default=1)
     ap.add_argument("--max-load", type=float, default=0.0, help="hash load factor (0 = library default)")
+    ap.add_argument("--schedule", default="auto", help="SpMV schedule bits, or 'auto' for the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--gather-ceiling", action="store_true", help="measure the random-gather rate for "
                     "buffer sizes 256 KiB .. 1 GiB and exit")
     ap.add_argument("--calibrate-copy", action="store_true", help="run the plain-copy kernel used to scale "
                     "rocprofv3 FETCH_SIZE / WRITE_SIZE and exit")
+    ap.add_argument("--serve", action="store_true", help="serving benchmark: batched Lanczos requests with "
+                    "Poisson arrivals against the FIFO single-vector solver")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-smax", type=float, default=2e6)
     args = ap.parse_args()
+    if args.serve:
+        if args.gpus != 1:
+            print("bench.py measures one GPU only (requested --gpus %d)" % args.gpus, file=sys.stderr)
+            sys.exit(2)
+        serve_bench(args)
+        return
     if args.calibrate_copy:
         calibrate_copy()
         return
@@ -190,11 +305,17 @@ def main():
     nnz = nnz_c.value
     probes, hits = H.work_counts()
     del indptr
+    dt = torch.float64 if args.dtype == "f64" else torch.float32
+    if args.schedule == "auto":
+        sched, tune_ms = H.autotune(nvec=args.nvec, dtype=dt, reps=3)
+        print("# autotuner: schedule %d (%.4f ms per SpMV)" % (sched, tune_ms), file=sys.stderr, flush=True)
+    else:
+        H.schedule = int(args.schedule)
+    sched = H.schedule
     setup_s = time.perf_counter() - t_setup
     print("# setup %.1f s: N=%d nnz=%d probes=%d hits=%d groups=%d" % (setup_s, N, nnz, probes, hits, op.n_groups),
           file=sys.stderr, flush=True)
 
-    dt = torch.float64 if args.dtype == "f64" else torch.float32
     esz = 8 if args.dtype == "f64" else 4
     g = torch.Generator(device="cuda")
     g.manual_seed(1)
@@ -235,7 +356,8 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": w.name, "n_qubits": w.ops.n_qubits, "subspace_dim": N, "nnz": nnz,
-                   "groups": op.n_groups, "terms": op.n_terms, "nvec": args.nvec, "kernel": "k_matvec"},
+                   "groups": op.n_groups, "terms": op.n_terms, "nvec": args.nvec, "kernel": "k_matvec",
+                   "schedule": sched},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": stored_traffic(w.name, args.dtype, args.nvec), "bytes_per_launch": balg,

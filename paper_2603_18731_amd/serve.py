@@ -59,7 +59,7 @@ class Server:
     iterations are enqueued per lane between two convergence checks."""
 
     def __init__(self, hbm_budget: int, max_iter: int = 300, spmv_dtype: str = "f64",
-                 lane_bounds=(1 << 15, 1 << 18), lane_slots=(64, 32, 16), steps_per_poll: int = 4):
+                 lane_bounds=(1 << 15, 1 << 18), lane_slots=(128, 16, 2), steps_per_poll: int = 4):
         import torch
 
         self.budget = int(hbm_budget)
@@ -96,8 +96,9 @@ class Server:
         self.peak_used = max(self.peak_used, self.used)
         return True
 
-    def run(self, requests: List[Request], clock=time.perf_counter) -> List[Request]:
-        """Serves ``requests`` (arrival times relative to the start) to completion in real time."""
+    def run(self, requests: List[Request], clock=time.perf_counter, progress=None) -> List[Request]:
+        """Serves ``requests`` (arrival times relative to the start) to completion in real time;
+        ``progress(k)`` is called after the k-th completion."""
         import torch
 
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -130,6 +131,8 @@ class Server:
                             self.used -= r.footprint
                             done.append(r)
                             progressed = True
+                            if progress is not None:
+                                progress(len(done))
                 # admissions into this lane happen while it is idle, in arrival order
                 for r in list(waiting):
                     if self.lane_of(r) == li and self._admit(lane, li, r, now):
