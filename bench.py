@@ -306,9 +306,10 @@ def main():
     probes, hits = H.work_counts()
     del indptr
     dt = torch.float64 if args.dtype == "f64" else torch.float32
+    tune = None
     if args.schedule == "auto":
-        sched, tune_ms = H.autotune(nvec=args.nvec, dtype=dt, reps=3)
-        print("# autotuner: schedule %d (%.4f ms per SpMV)" % (sched, tune_ms), file=sys.stderr, flush=True)
+        tune = H.autotune(nvec=args.nvec, dtype=dt, reps=3, load=args.max_load == 0.0)
+        print("# autotuner: %s" % json.dumps(tune), file=sys.stderr, flush=True)
     else:
         H.schedule = int(args.schedule)
     sched = H.schedule
@@ -357,7 +358,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n_qubits": w.ops.n_qubits, "subspace_dim": N, "nnz": nnz,
                    "groups": op.n_groups, "terms": op.n_terms, "nvec": args.nvec, "kernel": "k_matvec",
-                   "schedule": sched},
+                   "schedule": sched, "hash_capacity": sub.capacity, "autotune": tune},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": stored_traffic(w.name, args.dtype, args.nvec), "bytes_per_launch": balg,

@@ -115,6 +115,12 @@ int32_t qsd_max_qubits(void);
  * (slots).  Any output pointer may be NULL. */
 int qsd_subspace_info(const qsd_subspace *s, int64_t *N, int32_t *n_qubits, int32_t *W, int64_t *capacity);
 
+/* Rebuilds the hash table (slots and occupancy bitmap) for a new max_load in (0, 0.5] (0 = the
+ * default 1/8); keys, canonical indices and every lookup result are unchanged.  The subspace
+ * must not be in use on any stream meanwhile (operators bound to it see the new table at their
+ * next launch; serving requests hold the old one and must be removed first).  Synchronizes. */
+int qsd_subspace_rehash(qsd_subspace *s, double max_load, void *stream);
+
 /* Copies the canonical (sorted, unique) strings to device memory d_out, [N][W] row-major. */
 int qsd_subspace_keys(const qsd_subspace *s, uint64_t *d_out, void *stream);
 
@@ -195,6 +201,36 @@ int qsd_ham_info(const qsd_ham *h, int64_t *N, int64_t *G, int32_t *is_complex);
  * projector bits match), `hits` = those whose column is in the subspace (the off-diagonal
  * stored entries).  Host outputs; either may be NULL. */
 int qsd_ham_work_counts(const qsd_ham *h, int64_t *probes, int64_t *hits, void *stream);
+
+/* SpMV schedule (launch shape only: every schedule gives bitwise the same results, since each
+ * row is evaluated by one lane in the same group order whatever workgroup runs it).
+ *   QSD_SCHED_XCD_REMAP  workgroups dispatched to one XCD take contiguous row tiles, so rows
+ *                        whose columns and probes overlap share that XCD's L2.
+ * qsd_ham_set_schedule sets the bits (INVALID_ARG for unknown bits). */
+#define QSD_SCHED_XCD_REMAP 1u
+int qsd_ham_set_schedule(qsd_ham *h, uint32_t schedule);
+int qsd_ham_get_schedule(const qsd_ham *h, uint32_t *schedule);
+
+/* Autotuner (not in the paper).  Times `reps` SpMVs (nvec vectors of `dtype`, internal buffers)
+ * with HIP events for every candidate and keeps the fastest:
+ *   QSD_TUNE_SCHEDULE  every schedule above;
+ *   QSD_TUNE_LOAD      hash-table loads 1/16, 1/8, 1/4, 1/2: the subspace's table is rebuilt
+ *                      (qsd_subspace_rehash), so the subspace must not be used meanwhile by
+ *                      any other handle, batch or stream.  The best table depends on how the
+ *                      occupancy bitmap and the slots fit the caches.
+ * Neither changes any result bit.  `result` (host, may be NULL) receives the choice, the time
+ * per SpMV before and after.  Synchronizes; allocates 2 N nvec elements while it runs. */
+#define QSD_TUNE_SCHEDULE 1u
+#define QSD_TUNE_LOAD 2u
+typedef struct {
+    uint32_t schedule; /* QSD_SCHED_* bits kept */
+    int64_t capacity;  /* hash slots kept */
+    double max_load;   /* load parameter of the kept table */
+    double ms;         /* SpMV time with the kept choice */
+    double ms_before;  /* SpMV time before tuning */
+} qsd_tune_result;
+int qsd_ham_autotune(qsd_ham *h, int32_t nvec, int32_t dtype, int32_t reps, uint32_t flags, qsd_tune_result *result,
+                     void *stream);
 
 /* ==================================================================== matrix-free SpMV
  *
@@ -277,6 +313,25 @@ void qsd_lanczos_default_opts(qsd_lanczos_opts *opts);
  */
 int qsd_lanczos(const qsd_ham *h, const qsd_lanczos_opts *opts, double *eval_out, void *d_evec,
                 qsd_lanczos_info *info, void *stream);
+
+/* Block Lanczos (not in the paper): `block` (4 or 8) vectors per step, so every hash probe of
+ * the SpMM serves `block` vectors.  Block classical Gram-Schmidt applied twice against the
+ * whole basis, Cholesky QR applied twice for the next block, FP64 basis and recurrence;
+ * spmv_dtype F32 stores SpMM elements and vectors in single precision with FP64 accumulation.
+ * The lowest eigenvalue of the block tridiagonal T is found on the device by bisection with a
+ * banded Cholesky positive-definiteness test, its eigenvector by inverse iteration; the
+ * residual estimate is || B_k s_last ||.
+ *   opts->max_iter   block steps, 1 .. 80 (capped at N / block - 1).
+ *   opts->v0_mode    sets the first column of the start block (USER: d_evec); the other
+ *                    columns are random (splitmix64 of seed, column, row).
+ *   eval_out, d_evec, info, use_graph, check_every: as for qsd_lanczos (info->iterations counts
+ *   block steps).
+ * Synchronizes.  Returns NOT_CONVERGED (outputs filled) at the step limit or after a
+ * rank-deficient residual block; INVALID_ARG if the subspace is smaller than 2 * block.
+ * The basis needs (max_iter + 1) * N * block * 8 bytes of device memory.
+ */
+int qsd_block_lanczos(const qsd_ham *h, int32_t block, const qsd_lanczos_opts *opts, double *eval_out, void *d_evec,
+                      qsd_lanczos_info *info, void *stream);
 
 /* ========================================================= batched Lanczos (serving)
  *

@@ -27,6 +27,8 @@ INDEX_I32, INDEX_I64 = 0, 1
 OP_FERMIONIC, OP_CHECK_HERMITIAN, OP_FORCE_COMPLEX, OP_NO_LADDER_INT = 1, 2, 4, 8
 SUB_ASSUME_SORTED_UNIQUE = 1
 V0_UNIFORM, V0_MIN_DIAG, V0_RANDOM, V0_USER = 0, 1, 2, 3
+SCHED_XCD_REMAP = 1
+TUNE_SCHEDULE, TUNE_LOAD = 1, 2
 ERR_NAMES = {-1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "HIP", -4: "CAPACITY", -5: "NOT_HERMITIAN",
              -6: "NOT_CONVERGED", -7: "DTYPE", -8: "UNSUPPORTED"}
 
@@ -36,7 +38,8 @@ EXPORTED = [
     "qsd_op_compile", "qsd_op_info", "qsd_op_export", "qsd_op_destroy", "qsd_ham_create", "qsd_ham_diagonal",
     "qsd_ham_destroy", "qsd_ham_info", "qsd_ham_work_counts", "qsd_matvec", "qsd_csr_build", "qsd_lanczos_default_opts", "qsd_lanczos",
     "qsd_device_gather_rate", "qsd_batch_create", "qsd_batch_footprint", "qsd_batch_add", "qsd_batch_step",
-    "qsd_batch_poll", "qsd_batch_remove", "qsd_batch_destroy", "qsd_matvec_batched",
+    "qsd_batch_poll", "qsd_batch_remove", "qsd_batch_destroy", "qsd_matvec_batched", "qsd_block_lanczos",
+    "qsd_ham_set_schedule", "qsd_ham_get_schedule", "qsd_ham_autotune", "qsd_subspace_rehash",
 ]
 
 
@@ -44,6 +47,14 @@ class QsdError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("%s (%d): %s" % (ERR_NAMES.get(code, "ERROR"), code, msg))
         self.code = code
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_uint32), ("capacity", ctypes.c_int64), ("max_load", ctypes.c_double),
+                ("ms", ctypes.c_double), ("ms_before", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class LanczosOpts(ctypes.Structure):
@@ -102,6 +113,12 @@ def lib():
         "qsd_batch_footprint": ([P, I32, I32, P], ctypes.c_int),
         "qsd_batch_add": ([P, P, I32, ctypes.c_uint64, D, P, I64, P, P], ctypes.c_int),
         "qsd_matvec_batched": ([I32, P, P, P, P, I32, P], ctypes.c_int),
+        "qsd_ham_set_schedule": ([P, U32], ctypes.c_int),
+        "qsd_ham_get_schedule": ([P, P], ctypes.c_int),
+        "qsd_ham_autotune": ([P, I32, I32, I32, U32, P, P], ctypes.c_int),
+        "qsd_subspace_rehash": ([P, D, P], ctypes.c_int),
+        "qsd_block_lanczos": ([P, I32, ctypes.POINTER(LanczosOpts), P, P, ctypes.POINTER(LanczosInfo), P],
+                              ctypes.c_int),
         "qsd_batch_step": ([P, I32, P], ctypes.c_int),
         "qsd_batch_poll": ([P, P, P, P, P, P], ctypes.c_int),
         "qsd_batch_remove": ([P, I32], ctypes.c_int),
@@ -203,6 +220,16 @@ class Subspace:
         out = torch.empty(qt.shape[0], dtype=torch.int64, device="cuda")
         _check(lib().qsd_subspace_lookup(self._h, _ptr(qt), qt.shape[0], _ptr(out), _stream(stream)))
         return out
+
+    def _refresh(self):
+        N, nq, Wo, C = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().qsd_subspace_info(self._h, ctypes.byref(N), ctypes.byref(nq), ctypes.byref(Wo), ctypes.byref(C)))
+        self.capacity = C.value
+
+    def rehash(self, max_load: float, stream=None):
+        """Rebuilds the hash table for another load (lookups are unchanged)."""
+        _check(lib().qsd_subspace_rehash(self._h, max_load, _stream(stream)))
+        self._refresh()
 
     def probe_stats(self, stream=None):
         m, x = ctypes.c_double(), ctypes.c_int64()
@@ -315,6 +342,30 @@ class SubspaceHamiltonian:
         _check(lib().qsd_ham_work_counts(self._h, ctypes.byref(p), ctypes.byref(h), _stream(stream)))
         return p.value, h.value
 
+    @property
+    def schedule(self) -> int:
+        v = ctypes.c_uint32()
+        _check(lib().qsd_ham_get_schedule(self._h, ctypes.byref(v)))
+        return v.value
+
+    @schedule.setter
+    def schedule(self, value: int):
+        _check(lib().qsd_ham_set_schedule(self._h, int(value)))
+
+    def autotune(self, nvec: int = 1, dtype=None, reps: int = 3, schedule: bool = True, load: bool = True,
+                 stream=None) -> dict:
+        """Times the SpMV under every candidate schedule and hash load and keeps the fastest
+        (the subspace's table is rebuilt when ``load``)."""
+        import torch
+
+        dtype = dtype or (torch.complex128 if self.is_complex else torch.float64)
+        code = {torch.float64: F64, torch.float32: F32, torch.complex128: C128, torch.complex64: C64}[dtype]
+        flags = (TUNE_SCHEDULE if schedule else 0) | (TUNE_LOAD if load else 0)
+        r = TuneResult()
+        _check(lib().qsd_ham_autotune(self._h, nvec, code, reps, flags, ctypes.byref(r), _stream(stream)))
+        self.subspace._refresh()
+        return r.as_dict()
+
     def matvec(self, x, out=None, stream=None):
         """``H @ x`` for ``x`` of shape ``[N]`` or ``[N][nvec]`` (row-major, interleaved vectors)."""
         import torch
@@ -352,8 +403,10 @@ class SubspaceHamiltonian:
         return indptr, idx[: nnz.value], data[: nnz.value]
 
     def lanczos(self, max_iter=300, tol=1e-10, v0="uniform", seed=0, spmv_dtype="f64", check_every=5,
-                want_vector=False, use_graph=False, v0_vector=None, stream=None, raise_on_nonconv=True):
-        """Lowest eigenvalue by GPU Lanczos: ``(energy, vector or None, info dict)``."""
+                want_vector=False, use_graph=False, v0_vector=None, stream=None, raise_on_nonconv=True, block=1):
+        """Lowest eigenvalue by GPU Lanczos: ``(energy, vector or None, info dict)``.
+
+        ``block`` 4 or 8 runs block Lanczos (``max_iter`` then counts block steps)."""
         import torch
 
         o = LanczosOpts()
@@ -369,8 +422,12 @@ class SubspaceHamiltonian:
                 vec.copy_(v0_vector)
         e = ctypes.c_double()
         info = LanczosInfo()
-        rc = lib().qsd_lanczos(self._h, ctypes.byref(o), ctypes.byref(e), _ptr(vec), ctypes.byref(info),
-                               _stream(stream))
+        if block == 1:
+            rc = lib().qsd_lanczos(self._h, ctypes.byref(o), ctypes.byref(e), _ptr(vec), ctypes.byref(info),
+                                   _stream(stream))
+        else:
+            rc = lib().qsd_block_lanczos(self._h, int(block), ctypes.byref(o), ctypes.byref(e), _ptr(vec),
+                                         ctypes.byref(info), _stream(stream))
         if rc != QSD_OK and not (rc == -6 and not raise_on_nonconv):
             _check(rc)
         return e.value, (vec if want_vector else None), info.as_dict()

@@ -50,9 +50,10 @@ __global__ void k_to_f32(const double *__restrict__ in, float *__restrict__ out,
 template <int Wp, int NV, class ET, bool CPLX>
 __global__ __launch_bounds__(kBlock) void k_matvec(SubView s, HamView h, const ET *__restrict__ dre,
                                                    const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
-                                                   ET *__restrict__ y, int64_t ldy, int nvec) {
+                                                   ET *__restrict__ y, int64_t ldy, int nvec, int remap) {
     __shared__ ChunkLds<Wp> lds;
-    matvec_block<Wp, NV, ET, CPLX>(s, h, dre, dim, x, ldx, y, ldy, nvec, (int64_t)blockIdx.x * kBlock, lds);
+    const int64_t row0 = tile_index(blockIdx.x, gridDim.x, remap != 0) * kBlock;
+    matvec_block<Wp, NV, ET, CPLX>(s, h, dre, dim, x, ldx, y, ldy, nvec, row0, lds);
 }
 
 // ---------------------------------------------------------------------------------- CSR
@@ -253,7 +254,8 @@ void launch_mv(const qsd_ham *h, const void *x, int64_t ldx, void *y, int64_t ld
     const ET *dre = f32 ? (const ET *)h->diag32 : (const ET *)h->diag;
     const ET *dim = CPLX ? (f32 ? (const ET *)h->diag32_im : (const ET *)h->diag_im) : nullptr;
     k_matvec<Wp, NV, ET, CPLX><<<grid_for(h->N, kBlock), kBlock, 0, st>>>(sview(h->s), view_of(h, f32), dre, dim,
-                                                                          (const ET *)x, ldx, (ET *)y, ldy, nvec);
+                                                                          (const ET *)x, ldx, (ET *)y, ldy, nvec,
+                                                                          (int)(h->schedule & QSD_SCHED_XCD_REMAP));
 }
 
 template <int Wp, class ET, bool CPLX>
@@ -493,5 +495,105 @@ extern "C" int qsd_ham_work_counts(const qsd_ham *h, int64_t *probes, int64_t *h
     if (rc != QSD_OK) return rc;
     if (probes) *probes = (int64_t)hv[0];
     if (hits) *hits = (int64_t)hv[1];
+    return QSD_OK;
+}
+
+extern "C" int qsd_ham_set_schedule(qsd_ham *h, uint32_t schedule) {
+    clear_error();
+    if (!h) return fail(QSD_ERR_INVALID_ARG, "NULL handle");
+    if (schedule & ~QSD_SCHED_XCD_REMAP) return fail(QSD_ERR_INVALID_ARG, "unknown schedule bits 0x%x", schedule);
+    h->schedule = schedule;
+    return QSD_OK;
+}
+
+extern "C" int qsd_ham_get_schedule(const qsd_ham *h, uint32_t *schedule) {
+    clear_error();
+    if (!h || !schedule) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+    *schedule = h->schedule;
+    return QSD_OK;
+}
+
+extern "C" int qsd_ham_autotune(qsd_ham *h, int32_t nvec, int32_t dtype, int32_t reps, uint32_t flags,
+                                qsd_tune_result *result, void *stream) {
+    clear_error();
+    if (!h) return fail(QSD_ERR_INVALID_ARG, "NULL handle");
+    if (nvec < 1 || nvec > 16) return fail(QSD_ERR_INVALID_ARG, "nvec must be in [1, 16]");
+    if (reps < 1) return fail(QSD_ERR_INVALID_ARG, "reps must be >= 1");
+    if (flags & ~(QSD_TUNE_SCHEDULE | QSD_TUNE_LOAD)) return fail(QSD_ERR_INVALID_ARG, "unknown tuning flags");
+    QSD_TRY(check_dtype(h, dtype));
+    hipStream_t st = (hipStream_t)stream;
+    qsd_subspace *sub = const_cast<qsd_subspace *>(h->s);
+    const size_t esz = dtype == QSD_F64 ? 8 : dtype == QSD_F32 ? 4 : dtype == QSD_C128 ? 16 : 8;
+    const size_t bytes = (size_t)h->N * nvec * esz;
+    uint8_t *x = nullptr, *y = nullptr;
+    QSD_TRY(dev_alloc(&x, bytes));
+    int rc = dev_alloc(&y, bytes);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == QSD_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = fail(QSD_ERR_HIP, "event create failed");
+    if (rc == QSD_OK && hipMemsetAsync(x, 0, bytes, st) != hipSuccess) rc = fail(QSD_ERR_HIP, "memset failed");
+    auto time_it = [&](float &ms_out) -> int {
+        QSD_TRY(qsd_matvec(h, nvec, x, nvec, y, nvec, dtype, st));  // warm-up
+        QSD_CHECK_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) QSD_TRY(qsd_matvec(h, nvec, x, nvec, y, nvec, dtype, st));
+        QSD_CHECK_HIP(hipEventRecord(e1, st));
+        QSD_CHECK_HIP(hipEventSynchronize(e1));
+        QSD_CHECK_HIP(hipEventElapsedTime(&ms_out, e0, e1));
+        ms_out /= reps;
+        return QSD_OK;
+    };
+    const uint32_t sched0 = h->schedule;
+    const int64_t C0 = sub->C;
+    std::vector<double> loads;
+    if (flags & QSD_TUNE_LOAD) {
+        for (double l : {0.0625, 0.125, 0.25, 0.5}) loads.push_back(l);
+    } else {
+        loads.push_back(0.0);  // keep the current table
+    }
+    std::vector<uint32_t> scheds;
+    if (flags & QSD_TUNE_SCHEDULE) {
+        scheds = {0u, QSD_SCHED_XCD_REMAP};
+    } else {
+        scheds = {sched0};
+    }
+    float ms_before = INFINITY, best_ms = INFINITY;
+    if (rc == QSD_OK) rc = time_it(ms_before);
+    uint32_t best_sched = sched0;
+    double best_load = (double)sub->N / (double)sub->C;
+    int64_t best_C = C0;
+    for (double l : loads) {
+        if (rc != QSD_OK) break;
+        if (l > 0.0 && (rc = qsd_subspace_rehash(sub, l, stream)) != QSD_OK) break;
+        for (uint32_t sc : scheds) {
+            h->schedule = sc;
+            float ms = 0.0f;
+            if ((rc = time_it(ms)) != QSD_OK) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_sched = sc;
+                best_C = sub->C;
+                best_load = l > 0.0 ? l : best_load;
+            }
+        }
+    }
+    // keep the best table and schedule (or restore the starting ones after an error)
+    if (rc == QSD_OK) {
+        if (sub->C != best_C) rc = qsd_subspace_rehash(sub, best_load, stream);
+        h->schedule = best_sched;
+    } else {
+        h->schedule = sched0;
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    dev_free(x);
+    dev_free(y);
+    if (rc != QSD_OK) return rc;
+    if (result) {
+        result->schedule = best_sched;
+        result->capacity = sub->C;
+        result->max_load = best_load;
+        result->ms = best_ms;
+        result->ms_before = ms_before;
+    }
     return QSD_OK;
 }

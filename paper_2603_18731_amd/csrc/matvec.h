@@ -6,6 +6,15 @@
 
 namespace qsd {
 
+// Row tile of workgroup b out of G.  Workgroups are dispatched round-robin over the 8 XCDs, so
+// with `remap` the tiles of one XCD are made contiguous (XCD x takes the x-th eighth of the rows,
+// in order): neighbouring rows, whose columns and hash probes overlap, then share one L2.
+__device__ __forceinline__ int64_t tile_index(unsigned b, unsigned G, bool remap) {
+    if (!remap) return b;
+    const unsigned x = b & 7u, r = b >> 3, per = G >> 3, rem = G & 7u;
+    return (int64_t)((x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + r);
+}
+
 // Loads the lane's row `row0 + lane` (clamped to a valid row for lanes past the end).
 template <int Wp>
 __device__ __forceinline__ int64_t load_row(const SubView &s, int64_t row0, uint64_t (&key)[Wp], uint64_t &hrow,

@@ -480,6 +480,59 @@ extern "C" int qsd_subspace_build(const uint64_t *d_bits, int64_t n_in, int32_t 
     return QSD_OK;
 }
 
+namespace qsd {
+namespace {
+
+template <int Wp>
+int rehash_impl(qsd_subspace *sub, int64_t C, hipStream_t st) {
+    uint64_t *slots = nullptr;
+    uint32_t *bitmap = nullptr;
+    QSD_TRY(dev_alloc(&slots, C));
+    int rc = dev_alloc(&bitmap, C / 32);
+    if (rc == QSD_OK) {
+        k_fill_u64<<<1024, kBlock, 0, st>>>(slots, C, ~0ull);
+        k_fill_u32<<<256, kBlock, 0, st>>>(bitmap, C / 32, 0u);
+        SubView v{sub->keys, sub->hkey, slots, bitmap, sub->N, (uint32_t)(C - 1)};
+        k_hash_insert<Wp><<<grid_for(sub->N, kBlock), kBlock, 0, st>>>(v, slots, bitmap, sub->hkey, sub->ztab);
+        if (hipStreamSynchronize(st) != hipSuccess)
+            rc = fail(QSD_ERR_HIP, "hash rebuild failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    if (rc != QSD_OK) {
+        dev_free(slots);
+        dev_free(bitmap);
+        return rc;
+    }
+    dev_free(sub->slots);
+    dev_free(sub->bitmap);
+    sub->slots = slots;
+    sub->bitmap = bitmap;
+    sub->C = C;
+    return QSD_OK;
+}
+
+}  // namespace
+}  // namespace qsd
+
+extern "C" int qsd_subspace_rehash(qsd_subspace *s, double max_load, void *stream) {
+    clear_error();
+    if (!s) return fail(QSD_ERR_INVALID_ARG, "subspace is NULL");
+    if (max_load == 0.0) max_load = 0.125;
+    if (!(max_load > 0.0 && max_load <= 0.5)) return fail(QSD_ERR_INVALID_ARG, "max_load must be in (0, 0.5]");
+    int64_t C = 64;
+    while ((double)s->N / (double)C > max_load) C <<= 1;
+    if (C > (1ll << 32)) return fail(QSD_ERR_CAPACITY, "hash table would exceed 2^32 slots");
+    if (C == s->C) return QSD_OK;
+    hipStream_t st = (hipStream_t)stream;
+    switch (s->Wp) {
+        case 1: return rehash_impl<1>(s, C, st);
+        case 2: return rehash_impl<2>(s, C, st);
+        case 4: return rehash_impl<4>(s, C, st);
+        case 8: return rehash_impl<8>(s, C, st);
+        case 16: return rehash_impl<16>(s, C, st);
+    }
+    return fail(QSD_ERR_UNSUPPORTED, "unsupported width");
+}
+
 extern "C" int qsd_subspace_info(const qsd_subspace *s, int64_t *N, int32_t *n_qubits, int32_t *W, int64_t *capacity) {
     clear_error();
     if (!s) return fail(QSD_ERR_INVALID_ARG, "subspace is NULL");
