@@ -2,21 +2,25 @@
 // the CSR passes and the work counter.
 //
 // Mapping.  One lane owns one row bit-string b_i (rows are consecutive in the canonical order).
-// The off-diagonal groups are processed in chunks of kChunk:
+// The off-diagonal groups are processed in chunks of kChunk = 64:
 //
-//   scan   all 64 lanes walk the chunk's groups in lockstep (group descriptors are wave-uniform
-//          scalar loads).  Each lane forms its ladder integer L from the row bits at the
-//          group's ladder qubits and keeps the group iff some term has that ladder integer
-//          (Methods, Fermionic Hamiltonians: an empty int_ptrs range needs no lookup).  The
-//          surviving groups are recorded as one bit per group in a per-lane mask.
+//   scan   bit-sliced over the wave's 64 rows.  The rows' keys are transposed once into bit
+//          planes (plane q = bit q of all 64 rows, one 64-bit word).  For the chunk, lane l
+//          takes group l: its ladder-integer live table (Methods, Fermionic Hamiltonians: an
+//          empty int_ptrs range needs no lookup) is evaluated as a boolean function of the four
+//          planes of the group's ladder qubits, giving one 64-bit word of live rows.  A 64 x 64
+//          bit transpose across the wave then hands every lane the live-group mask of its own
+//          row.  This costs a few hundred wave instructions per chunk instead of a ladder
+//          integer per (row, group).
 //   probe  each lane then pops its own set bits, lowest group first, kProbeBatch at a time, so
 //          every probe instruction runs with (nearly) all lanes busy instead of with only the
 //          lanes whose group happens to be live.  A probe forms hash(b_i ^ M_g) =
 //          hash(b_i) ^ hash(M_g) (the hash is linear over GF(2)), tests the occupancy bit,
 //          reads the {tag, index} slot and compares the key (Methods, Subspace data
 //          structure).
-//   hit    the terms of the group's ladder range are refined on their projector bits and
-//          summed with popcount-parity signs; the caller's functor consumes (j, value).
+//   hit    the row's ladder integer selects the group's term range; the terms are refined on
+//          their projector bits and summed with popcount-parity signs; the caller's functor
+//          consumes (j, value).
 //
 // Each lane consumes its hits in increasing group order, so a row's sum is formed in a fixed
 // order: results are bitwise reproducible and independent of how rows are batched.
@@ -101,14 +105,13 @@ __device__ __forceinline__ bool range_value(const HamView &h, const uint64_t (&k
     return any;
 }
 
-// 4-bit ladder integer of a row from a scan record: bit j = row bit at qubit (shift_j + j).
+// 4-bit ladder integer of a row from a scan record: bit j = row bit at qubit p_j = shift_j + j.
 // One-word keys are shifted in registers (one funnel shift per bit); wider keys read the
-// needed 32-bit half of the row from LDS (`keyh`, one word per lane per half), which avoids
-// indexing a register array with a run-time word number.  Unused positions are don't-cares
-// of the replicated live table.
+// wave's bit planes in LDS (plane p_j, bit = the lane), which avoids indexing a register array
+// with a run-time word number.  Unused positions are don't-cares of the replicated live table.
 template <int Wp>
-__device__ __forceinline__ uint32_t scan_lint(const uint64_t (&key)[Wp], uint64_t rec,
-                                              const uint32_t (*keyh)[kBlock]) {
+__device__ __forceinline__ uint32_t row_lint(const uint64_t (&key)[Wp], uint64_t rec, const uint64_t *planes,
+                                             int lane) {
     uint32_t L = 0;
     if (Wp == 1) {
         const uint32_t lo = (uint32_t)key[0], hi = (uint32_t)(key[0] >> 32);
@@ -122,23 +125,60 @@ __device__ __forceinline__ uint32_t scan_lint(const uint64_t (&key)[Wp], uint64_
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t p = ((uint32_t)(rec >> (16 + 12 * j)) & 0xFFFu) + (uint32_t)j;
-            L |= ((keyh[p >> 5][threadIdx.x] >> (p & 31u)) & 1u) << j;
+            L |= (uint32_t)((planes[p] >> lane) & 1ull) << j;
         }
     }
     return L;
 }
 
-// LDS staging of one chunk: what the probes and the hit ranges read.
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+    const uint32_t lo = __shfl_xor((unsigned)v, m, 64);
+    const uint32_t hi = __shfl_xor((unsigned)(v >> 32), m, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// 64 x 64 bit transpose across a wave: on return, bit j of lane i's word is bit i of lane j's
+// input word.  Six butterfly stages; every lane of the wave must take part.
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, int lane) {
+    const uint64_t M[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                           0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int sh = 32 >> k;
+        const uint64_t y = shfl_xor64(x, sh);
+        x = (lane & sh) ? ((x & ~M[k]) | ((y & ~M[k]) >> sh)) : ((x & M[k]) | ((y & M[k]) << sh));
+    }
+    return x;
+}
+
+// Bit-sliced live test: bit r of the result = T[L_r], L_r = (a_r, b_r, c_r, d_r) as bits 0..3,
+// for the 16-entry table T and the four planes a, b, c, d.
+__device__ __forceinline__ uint64_t sliced_table(uint32_t T, uint64_t a, uint64_t b, uint64_t c, uint64_t d) {
+    const uint64_t m[4] = {~a & ~b, a & ~b, ~a & b, a & b};
+    const uint64_t u[4] = {~c & ~d, c & ~d, ~c & d, c & d};
+    uint64_t f = 0;
+#pragma unroll
+    for (int hi = 0; hi < 4; ++hi) {
+        uint64_t g = 0;
+#pragma unroll
+        for (int lo = 0; lo < 4; ++lo) g |= m[lo] & (0ull - (uint64_t)((T >> (4 * hi + lo)) & 1u));
+        f |= g & u[hi];
+    }
+    return f;
+}
+
+// LDS staging of one chunk: what the probes and the hit ranges read, plus the bit planes of
+// every wave's rows.
 template <int Wp>
 struct ChunkLds {
     uint64_t hash[kChunk];
     uint64_t mask[kChunk][Wp];
+    uint64_t rec[kChunk];                // scan records (ladder positions for the hit ranges)
     uint32_t term0[kChunk];
     uint32_t nterm[kChunk];
     uint32_t lmask[kChunk];              // ladder-integer bits used for the range (0: all terms)
     uint16_t iptr[kChunk][kIptr];
-    uint32_t lint[kChunk / 8][kBlock];   // per-lane ladder integers, 8 nibbles per word
-    uint32_t keyh[Wp == 1 ? 1 : 2 * Wp][kBlock];  // row keys as 32-bit halves (wide keys)
+    uint64_t planes[kBlock / 64][64 * Wp];
 };
 
 // Pops the lowest set bit of a 64-bit mask held as two words; -1 when empty.
@@ -160,13 +200,11 @@ template <int Wp, class OnHit>
 __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, const uint64_t (&key)[Wp],
                                            uint64_t hrow, bool valid, ChunkLds<Wp> &lds, OnHit &&on_hit,
                                            unsigned long long *probes = nullptr) {
-    if (Wp > 1) {
+    const int lane = threadIdx.x & 63;
+    uint64_t *planes = lds.planes[threadIdx.x >> 6];
 #pragma unroll
-        for (int w = 0; w < Wp; ++w) {
-            lds.keyh[(2 * w) % (Wp == 1 ? 1 : 2 * Wp)][threadIdx.x] = (uint32_t)key[w];
-            lds.keyh[(2 * w + 1) % (Wp == 1 ? 1 : 2 * Wp)][threadIdx.x] = (uint32_t)(key[w] >> 32);
-        }
-    }
+    for (int w = 0; w < Wp; ++w) planes[64 * w + lane] = wave_transpose64(valid ? key[w] : 0ull, lane);
+    const uint64_t vrows = __ballot(valid);
     for (int64_t g0 = 0; g0 < h.G; g0 += kChunk) {
         const int nc = (int)((h.G - g0) < kChunk ? (h.G - g0) : kChunk);
         __syncthreads();
@@ -176,34 +214,25 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
 #pragma unroll
             for (int w = 0; w < Wp; ++w) lds.mask[c][w] = h.g_mask[g * Wp + w];
             const uint32_t info = h.g_info[g];
+            lds.rec[c] = h.g_scan[g];
             lds.term0[c] = h.g_term0[g];
             lds.nterm[c] = h.g_nterm[g];
             lds.lmask[c] = (info & kInfoLadder) ? ((1u << (info & kInfoKMask)) - 1u) : 0u;
 #pragma unroll
             for (int q = 0; q < kIptr; ++q) lds.iptr[c][q] = h.g_iptr[g * kIptr + q];
         }
-        // scan: a live bit and the ladder integer per group; records are read 8 at a time
-        uint32_t mw[2] = {0u, 0u};
+        // scan: lane l evaluates group g0 + l for the wave's 64 rows, then the masks are
+        // transposed to one live-group mask per row
+        uint64_t live = 0;
+        if (lane < nc) {
+            const uint64_t rec = h.g_scan[g0 + lane];
+            uint64_t P[4];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            uint32_t m = 0;
-            for (int c8 = 32 * q; c8 < 32 * q + 32 && c8 < nc; c8 += 8) {
-                uint64_t rec[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) rec[u] = h.g_scan[g0 + c8 + u];  // padded array
-                uint32_t lp = 0;
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const uint32_t L = scan_lint<Wp>(key, rec[u], lds.keyh);
-                    const uint32_t live = ((uint32_t)(rec[u] >> L) & 1u) & (c8 + u < nc ? 1u : 0u);
-                    m |= live << (c8 + u - 32 * q);
-                    lp |= L << (4 * u);
-                }
-                lds.lint[c8 / 8][threadIdx.x] = lp;
-            }
-            mw[q] = valid ? m : 0u;
+            for (int j = 0; j < 4; ++j) P[j] = planes[((uint32_t)(rec >> (16 + 12 * j)) & 0xFFFu) + (uint32_t)j];
+            live = sliced_table((uint32_t)rec & 0xFFFFu, P[0], P[1], P[2], P[3]) & vrows;
         }
-        uint32_t mlo = mw[0], mhi = mw[1];
+        live = wave_transpose64(live, lane);
+        uint32_t mlo = (uint32_t)live, mhi = (uint32_t)(live >> 32);
         if (probes) *probes += (unsigned long long)(__popc(mlo) + __popc(mhi));
         __syncthreads();
         // probe: each lane pops its own live groups, kProbeBatch at a time
@@ -255,7 +284,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                 if (j >= 0) {
                     const int cc = c[b];
                     const uint32_t lm = lds.lmask[cc];
-                    const uint32_t L = (lds.lint[cc >> 3][threadIdx.x] >> (4 * (cc & 7))) & lm;
+                    const uint32_t L = row_lint<Wp>(key, lds.rec[cc], planes, lane) & lm;
                     const uint32_t lo = lds.iptr[cc][L];
                     const uint32_t hi = lm ? (uint32_t)lds.iptr[cc][L + 1] : lds.nterm[cc];
                     on_hit(j, lds.term0[cc] + lo, hi - lo);
