@@ -237,6 +237,70 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def csr_compare(args):
+    """Matrix-free vs stored-CSR solve on one workload: CSR build time (two-pass and
+    lower-triangle), device memory, SpMV time of both operators, Lanczos time and energy."""
+    import numpy as np
+    import torch
+
+    import paper_2603_18731_amd as qsd
+
+    torch.cuda.set_device(0)
+    w = make_workload(args.workload)
+    sub = qsd.Subspace(w.keys, w.ops.n_qubits)
+    op = qsd.operator_from_termlist(w.ops)
+    H = qsd.SubspaceHamiltonian(sub, op)
+    tune = H.autotune(reps=2)
+    N = sub.N
+    print("# %s: N=%d, autotuned %s" % (w.name, N, json.dumps(tune)), file=sys.stderr, flush=True)
+    st = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record(st)
+            fn()
+            b.record(st)
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    x = torch.rand(N, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    mf_ms = timed(lambda: H.matvec(x, out=y), 5)
+    out = {"workload": w.name, "N": N, "matrix_free_spmv_ms": mf_ms}
+    for lower in (False, True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A = qsd.CsrMatrix(H, qsd.INDEX_I32 if N < 2**31 else qsd.INDEX_I64, lower_mirror=lower)
+        torch.cuda.synchronize()
+        key = "lower_mirror" if lower else "two_pass"
+        out["csr_build_s_" + key] = time.perf_counter() - t0
+        print("# CSR build (%s): %.3f s, nnz %d, %.2f GB" % (key, out["csr_build_s_" + key], A.nnz, A.bytes / 1e9),
+              file=sys.stderr, flush=True)
+        if not lower:
+            del A
+    y2 = torch.empty_like(x)
+    csr_ms = timed(lambda: A.matvec(x, out=y2), 10)
+    out.update({"nnz": A.nnz, "csr_bytes": A.bytes, "csr_spmv_ms": csr_ms,
+                "csr_spmv_gbs": (A.bytes + 3 * 8 * N) / (csr_ms / 1e3) / 1e9,
+                "spmv_max_rel_diff": float(((y2 - y).abs().max() / y.abs().max()).item())})
+    print("# SpMV: matrix-free %.3f ms, CSR %.3f ms (%.0f GB/s streamed)" % (mf_ms, csr_ms, out["csr_spmv_gbs"]),
+          file=sys.stderr, flush=True)
+    for mode, obj in (("csr", A), ("matrix_free", H)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e, _, info = obj.lanczos(tol=1e-10, max_iter=300, v0="uniform", raise_on_nonconv=False)
+        out["solve_s_" + mode] = time.perf_counter() - t0
+        out["energy_" + mode] = e
+        out["iterations_" + mode] = info["iterations"]
+        print("# Lanczos (%s): %.12f in %.3f s, %d iterations" % (mode, e, out["solve_s_" + mode],
+                                                                  info["iterations"]), file=sys.stderr, flush=True)
+    out["energy_rel_diff"] = abs(out["energy_csr"] - out["energy_matrix_free"]) / abs(out["energy_matrix_free"])
+    print(json.dumps({"csr_vs_matrix_free": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,11 +317,18 @@ def main():
                     "buffer sizes 256 KiB .. 1 GiB and exit")
     ap.add_argument("--calibrate-copy", action="store_true", help="run the plain-copy kernel used to scale "
                     "rocprofv3 FETCH_SIZE / WRITE_SIZE and exit")
+    ap.add_argument("--csr-compare", action="store_true", help="matrix-free vs stored-CSR solve on --workload")
     ap.add_argument("--serve", action="store_true", help="serving benchmark: batched Lanczos requests with "
                     "Poisson arrivals against the FIFO single-vector solver")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-smax", type=float, default=2e6)
     args = ap.parse_args()
+    if args.csr_compare:
+        if args.gpus != 1:
+            print("bench.py measures one GPU only (requested --gpus %d)" % args.gpus, file=sys.stderr)
+            sys.exit(2)
+        csr_compare(args)
+        return
     if args.serve:
         if args.gpus != 1:
             print("bench.py measures one GPU only (requested --gpus %d)" % args.gpus, file=sys.stderr)

@@ -333,6 +333,45 @@ int qsd_lanczos(const qsd_ham *h, const qsd_lanczos_opts *opts, double *eval_out
 int qsd_block_lanczos(const qsd_ham *h, int32_t block, const qsd_lanczos_opts *opts, double *eval_out, void *d_evec,
                       qsd_lanczos_info *info, void *stream);
 
+/* ============================================================ stored CSR operator
+ *
+ * qsd_csr_create - Methods, Matrix evaluation (CSR output) and Lower / upper triangle
+ *   evaluation.  Builds the CSR matrix of `h` (same entries as qsd_csr_build: structural
+ *   entries, columns ascending per row) and keeps it on the device for repeated SpMVs.
+ *   flags 0: two passes over all rows (structure, then values).
+ *   QSD_CSR_LOWER_MIRROR: each row evaluates only the groups whose column sorts below it (the
+ *   row bit at the group's most significant off-diagonal bit is set), so every element is
+ *   evaluated once; each entry is written into its row and, conjugated, into the column's row
+ *   (atomic cursors), then rows are sorted.  Requires a Hermitian operator (the upper triangle
+ *   is taken as the conjugate of the lower one).
+ *   index_type QSD_INDEX_I32 / I64 (CAPACITY if N >= 2^31 with I32); dtype as for
+ *   qsd_csr_build (F64 / F32 real, C128 / C64 complex; DTYPE if it does not match `h`).
+ *   Synchronizes.  Device memory: (N + 1) * 8 + nnz * (index + value size), plus the build's
+ *   scratch of nnz * (8 + 2 * value size) bytes while it runs.  `h` may be destroyed after.
+ * qsd_csr_info      N, nnz, device bytes held.
+ * qsd_csr_export    copies indptr [N+1] (int64), indices [nnz], data [nnz] to device buffers
+ *                   (any may be NULL); async on `stream`.
+ * qsd_csr_matvec    Y = A X, same layout and dtype rules as qsd_matvec except that the vector
+ *                   dtype must be the stored dtype (DTYPE otherwise).  LPR lanes per row with a
+ *                   fixed reduction tree: bitwise reproducible.  Async.
+ * qsd_csr_lanczos / qsd_csr_block_lanczos
+ *                   qsd_lanczos / qsd_block_lanczos on the stored matrix (opts->spmv_dtype must
+ *                   be the stored dtype).
+ * qsd_csr_destroy   frees the matrix.
+ */
+#define QSD_CSR_LOWER_MIRROR 1u
+typedef struct qsd_csr qsd_csr;
+int qsd_csr_create(const qsd_ham *h, int32_t index_type, int32_t dtype, uint32_t flags, void *stream, qsd_csr **out);
+int qsd_csr_info(const qsd_csr *c, int64_t *N, int64_t *nnz, int64_t *bytes);
+int qsd_csr_export(const qsd_csr *c, int64_t *d_indptr, void *d_indices, void *d_data, void *stream);
+int qsd_csr_matvec(const qsd_csr *c, int32_t nvec, const void *d_x, int64_t ldx, void *d_y, int64_t ldy, int32_t dtype,
+                   void *stream);
+int qsd_csr_lanczos(const qsd_csr *c, const qsd_lanczos_opts *opts, double *eval_out, void *d_evec,
+                    qsd_lanczos_info *info, void *stream);
+int qsd_csr_block_lanczos(const qsd_csr *c, int32_t block, const qsd_lanczos_opts *opts, double *eval_out,
+                          void *d_evec, qsd_lanczos_info *info, void *stream);
+int qsd_csr_destroy(qsd_csr *c);
+
 /* ========================================================= batched Lanczos (serving)
  *
  * Many ground-state solves advance together: qsd_batch_step takes one Lanczos iteration (the

@@ -29,6 +29,7 @@ SUB_ASSUME_SORTED_UNIQUE = 1
 V0_UNIFORM, V0_MIN_DIAG, V0_RANDOM, V0_USER = 0, 1, 2, 3
 SCHED_XCD_REMAP = 1
 TUNE_SCHEDULE, TUNE_LOAD = 1, 2
+CSR_LOWER_MIRROR = 1
 ERR_NAMES = {-1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "HIP", -4: "CAPACITY", -5: "NOT_HERMITIAN",
              -6: "NOT_CONVERGED", -7: "DTYPE", -8: "UNSUPPORTED"}
 
@@ -40,6 +41,8 @@ EXPORTED = [
     "qsd_device_gather_rate", "qsd_batch_create", "qsd_batch_footprint", "qsd_batch_add", "qsd_batch_step",
     "qsd_batch_poll", "qsd_batch_remove", "qsd_batch_destroy", "qsd_matvec_batched", "qsd_block_lanczos",
     "qsd_ham_set_schedule", "qsd_ham_get_schedule", "qsd_ham_autotune", "qsd_subspace_rehash",
+    "qsd_csr_create", "qsd_csr_info", "qsd_csr_export", "qsd_csr_matvec", "qsd_csr_lanczos", "qsd_csr_block_lanczos",
+    "qsd_csr_destroy",
 ]
 
 
@@ -117,6 +120,14 @@ def lib():
         "qsd_ham_get_schedule": ([P, P], ctypes.c_int),
         "qsd_ham_autotune": ([P, I32, I32, I32, U32, P, P], ctypes.c_int),
         "qsd_subspace_rehash": ([P, D, P], ctypes.c_int),
+        "qsd_csr_create": ([P, I32, I32, U32, P, PP], ctypes.c_int),
+        "qsd_csr_info": ([P, P, P, P], ctypes.c_int),
+        "qsd_csr_export": ([P, P, P, P, P], ctypes.c_int),
+        "qsd_csr_matvec": ([P, I32, P, I64, P, I64, I32, P], ctypes.c_int),
+        "qsd_csr_lanczos": ([P, ctypes.POINTER(LanczosOpts), P, P, ctypes.POINTER(LanczosInfo), P], ctypes.c_int),
+        "qsd_csr_block_lanczos": ([P, I32, ctypes.POINTER(LanczosOpts), P, P, ctypes.POINTER(LanczosInfo), P],
+                                  ctypes.c_int),
+        "qsd_csr_destroy": ([P], ctypes.c_int),
         "qsd_block_lanczos": ([P, I32, ctypes.POINTER(LanczosOpts), P, P, ctypes.POINTER(LanczosInfo), P],
                               ctypes.c_int),
         "qsd_batch_step": ([P, I32, P], ctypes.c_int),
@@ -407,36 +418,111 @@ class SubspaceHamiltonian:
         """Lowest eigenvalue by GPU Lanczos: ``(energy, vector or None, info dict)``.
 
         ``block`` 4 or 8 runs block Lanczos (``max_iter`` then counts block steps)."""
-        import torch
-
-        o = LanczosOpts()
-        lib().qsd_lanczos_default_opts(ctypes.byref(o))
-        o.max_iter, o.tol, o.seed, o.check_every = max_iter, tol, seed, check_every
-        o.v0_mode = {"uniform": V0_UNIFORM, "min_diag": V0_MIN_DIAG, "random": V0_RANDOM, "user": V0_USER}[v0]
-        o.spmv_dtype = {"f64": F64, "f32": F32}[spmv_dtype]
-        o.want_vector, o.use_graph = int(want_vector), int(use_graph)
-        vec = None
-        if want_vector or v0 == "user":
-            vec = torch.empty(self.N, dtype=torch.float64, device="cuda")
-            if v0 == "user":
-                vec.copy_(v0_vector)
-        e = ctypes.c_double()
-        info = LanczosInfo()
-        if block == 1:
-            rc = lib().qsd_lanczos(self._h, ctypes.byref(o), ctypes.byref(e), _ptr(vec), ctypes.byref(info),
-                                   _stream(stream))
-        else:
-            rc = lib().qsd_block_lanczos(self._h, int(block), ctypes.byref(o), ctypes.byref(e), _ptr(vec),
-                                         ctypes.byref(info), _stream(stream))
-        if rc != QSD_OK and not (rc == -6 and not raise_on_nonconv):
-            _check(rc)
-        return e.value, (vec if want_vector else None), info.as_dict()
+        return _lanczos(lib().qsd_lanczos, lib().qsd_block_lanczos, self._h, self.N, max_iter, tol, v0, seed,
+                        spmv_dtype, check_every, want_vector, use_graph, v0_vector, stream, raise_on_nonconv, block)
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h and _lib is not None:
             _lib.qsd_ham_destroy(h)
             self._h = None
+
+
+def _lanczos(single, blockfn, handle, N, max_iter, tol, v0, seed, spmv_dtype, check_every, want_vector, use_graph,
+             v0_vector, stream, raise_on_nonconv, block):
+    import torch
+
+    o = LanczosOpts()
+    lib().qsd_lanczos_default_opts(ctypes.byref(o))
+    o.max_iter, o.tol, o.seed, o.check_every = max_iter, tol, seed, check_every
+    o.v0_mode = {"uniform": V0_UNIFORM, "min_diag": V0_MIN_DIAG, "random": V0_RANDOM, "user": V0_USER}[v0]
+    o.spmv_dtype = {"f64": F64, "f32": F32}[spmv_dtype]
+    o.want_vector, o.use_graph = int(want_vector), int(use_graph)
+    vec = None
+    if want_vector or v0 == "user":
+        vec = torch.empty(N, dtype=torch.float64, device="cuda")
+        if v0 == "user":
+            vec.copy_(v0_vector)
+    e = ctypes.c_double()
+    info = LanczosInfo()
+    if block == 1:
+        rc = single(handle, ctypes.byref(o), ctypes.byref(e), _ptr(vec), ctypes.byref(info), _stream(stream))
+    else:
+        rc = blockfn(handle, int(block), ctypes.byref(o), ctypes.byref(e), _ptr(vec), ctypes.byref(info),
+                     _stream(stream))
+    if rc != QSD_OK and not (rc == -6 and not raise_on_nonconv):
+        _check(rc)
+    return e.value, (vec if want_vector else None), info.as_dict()
+
+
+class CsrMatrix:
+    """The operator's CSR matrix kept on the device (``qsd_csr_*``): SpMV and Lanczos on it."""
+
+    def __init__(self, ham: "SubspaceHamiltonian", index_type: int = INDEX_I32, dtype=None,
+                 lower_mirror: bool = False, stream=None):
+        import torch
+
+        if dtype is None:
+            dtype = torch.complex128 if ham.is_complex else torch.float64
+        self.dtype = dtype
+        code = {torch.float64: F64, torch.float32: F32, torch.complex128: C128, torch.complex64: C64}[dtype]
+        h = ctypes.c_void_p()
+        _check(lib().qsd_csr_create(ham.handle, index_type, code, CSR_LOWER_MIRROR if lower_mirror else 0,
+                                    _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.index_type = index_type
+        N, nnz, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().qsd_csr_info(h, ctypes.byref(N), ctypes.byref(nnz), ctypes.byref(b)))
+        self.N, self.nnz, self.bytes = N.value, nnz.value, b.value
+        self.is_complex = ham.is_complex
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self, stream=None):
+        """``(indptr int64, indices, data)`` device tensors (copies)."""
+        import torch
+
+        ip = torch.empty(self.N + 1, dtype=torch.int64, device="cuda")
+        ix = torch.empty(max(1, self.nnz), dtype=torch.int32 if self.index_type == INDEX_I32 else torch.int64,
+                         device="cuda")
+        dv = torch.empty(max(1, self.nnz), dtype=self.dtype, device="cuda")
+        _check(lib().qsd_csr_export(self._h, _ptr(ip), _ptr(ix), _ptr(dv), _stream(stream)))
+        return ip, ix[: self.nnz], dv[: self.nnz]
+
+    def matvec(self, x, out=None, stream=None):
+        vec = x.dim() == 1
+        X = x.reshape(self.N, -1)
+        if X.stride(1) != 1:
+            X = X.contiguous()
+        nvec = X.shape[1]
+        Y = torch_empty_like(X) if out is None else out.reshape(self.N, -1)
+        _check(lib().qsd_csr_matvec(self._h, nvec, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0),
+                                    SubspaceHamiltonian._dtype_code(X), _stream(stream)))
+        return Y.reshape(-1) if vec else Y
+
+    def lanczos(self, max_iter=300, tol=1e-10, v0="uniform", seed=0, spmv_dtype=None, check_every=5,
+                want_vector=False, use_graph=False, v0_vector=None, stream=None, raise_on_nonconv=True, block=1):
+        """Lanczos on the stored matrix (see ``SubspaceHamiltonian.lanczos``)."""
+        import torch
+
+        if spmv_dtype is None:
+            spmv_dtype = "f32" if self.dtype == torch.float32 else "f64"
+        return _lanczos(lib().qsd_csr_lanczos, lib().qsd_csr_block_lanczos, self._h, self.N, max_iter, tol, v0, seed,
+                        spmv_dtype, check_every, want_vector, use_graph, v0_vector, stream, raise_on_nonconv, block)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.qsd_csr_destroy(h)
+            self._h = None
+
+
+def torch_empty_like(x):
+    import torch
+
+    return torch.empty_like(x)
 
 
 def matvec_batched(hams, xs, ys=None, stream=None):

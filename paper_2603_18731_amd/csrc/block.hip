@@ -567,14 +567,14 @@ void enqueue_cholqr2(BlzState &S, double *dst, double *Vb, int off, int mode_bas
 }
 
 template <int B>
-int enqueue_step(const qsd_ham *h, BlzState &S, bool f32, hipStream_t st) {
+int enqueue_step(const SpmvOp &op, BlzState &S, bool f32, hipStream_t st) {
     const int64_t N = S.N;
     if (f32) {
         kbl_to_f32<<<1024, kThreads, 0, st>>>(S.X, S.X32, N * B);
-        QSD_TRY(qsd_matvec(h, B, S.X32, B, S.W32, B, QSD_F32, st));
+        QSD_TRY(op.matvec(B, S.X32, B, S.W32, B, QSD_F32, st));
         kbl_to_f64<<<1024, kThreads, 0, st>>>(S.W32, S.W, N * B);
     } else {
-        QSD_TRY(qsd_matvec(h, B, S.X, B, S.W, B, QSD_F64, st));
+        QSD_TRY(op.matvec(B, S.X, B, S.W, B, QSD_F64, st));
     }
     const unsigned jy = (unsigned)((S.m + 1 + (64 / B) - 1) / (64 / B));
     for (int pass = 0; pass < 2; ++pass) {
@@ -589,10 +589,10 @@ int enqueue_step(const qsd_ham *h, BlzState &S, bool f32, hipStream_t st) {
 }
 
 template <int B>
-int block_lanczos(const qsd_ham *h, const qsd_lanczos_opts &o, double *eval_out, void *d_evec, qsd_lanczos_info *info,
+int block_lanczos(const SpmvOp &op, const qsd_lanczos_opts &o, double *eval_out, void *d_evec, qsd_lanczos_info *info,
                   hipStream_t st) {
     auto t_start = std::chrono::steady_clock::now();
-    const int64_t N = h->N;
+    const int64_t N = op.N();
     BlzState S;
     S.N = N;
     S.B = B;
@@ -640,7 +640,7 @@ int block_lanczos(const qsd_ham *h, const qsd_lanczos_opts &o, double *eval_out,
         kbl_zero_i<<<1, 1, 0, st>>>(S.kdev);
         int64_t *spike = nullptr;
         if ((rc = dev_alloc(&spike, 1)) != QSD_OK) break;
-        if (o.v0_mode == QSD_V0_MIN_DIAG) kbl_argmin<<<1, kThreads, 0, st>>>(h->diag, N, spike);
+        if (o.v0_mode == QSD_V0_MIN_DIAG) kbl_argmin<<<1, kThreads, 0, st>>>(op.diag(), N, spike);
         kbl_init<B><<<1024, kThreads, 0, st>>>(S.W, N, o.v0_mode, o.seed, spike, (const double *)d_evec);
         enqueue_cholqr2<B>(S, S.X, S.V, 0, 0, st);
         std::vector<double> fl(4);
@@ -662,7 +662,7 @@ int block_lanczos(const qsd_ham *h, const qsd_lanczos_opts &o, double *eval_out,
                 rc = fail(QSD_ERR_HIP, "stream capture failed");
                 break;
             }
-            int erc = enqueue_step<B>(h, S, f32, st);
+            int erc = enqueue_step<B>(op, S, f32, st);
             hipError_t ce = hipStreamEndCapture(st, &graph);
             if (erc != QSD_OK || ce != hipSuccess) {
                 rc = erc != QSD_OK ? erc : fail(QSD_ERR_HIP, "end capture failed");
@@ -681,7 +681,7 @@ int block_lanczos(const qsd_ham *h, const qsd_lanczos_opts &o, double *eval_out,
                 if (gexec) {
                     if (hipGraphLaunch(gexec, st) != hipSuccess) rc = fail(QSD_ERR_HIP, "graph launch failed");
                 } else {
-                    rc = enqueue_step<B>(h, S, f32, st);
+                    rc = enqueue_step<B>(op, S, f32, st);
                 }
             }
             if (rc != QSD_OK) break;
@@ -713,9 +713,9 @@ int block_lanczos(const qsd_ham *h, const qsd_lanczos_opts &o, double *eval_out,
         if (rc != QSD_OK) break;
         hipEventRecord(e0, st);
         if (f32)
-            rc = qsd_matvec(h, B, S.X32, B, S.W32, B, QSD_F32, st);
+            rc = op.matvec(B, S.X32, B, S.W32, B, QSD_F32, st);
         else
-            rc = qsd_matvec(h, B, S.X, B, S.W, B, QSD_F64, st);
+            rc = op.matvec(B, S.X, B, S.W, B, QSD_F64, st);
         hipEventRecord(e1, st);
         if (rc != QSD_OK) break;
         hipEventSynchronize(e1);
@@ -726,7 +726,13 @@ int block_lanczos(const qsd_ham *h, const qsd_lanczos_opts &o, double *eval_out,
             kbl_ritzvec<B><<<g, kThreads, 0, st>>>(S.V, N * B, iters, S.ritz + 3, y, N);
             kbl_sq<<<kGramTiles, kThreads, 0, st>>>(y, nullptr, 0.0, N, S.red);
             kbl_scale_vec<<<g, kThreads, 0, st>>>(y, N, S.red, kGramTiles);
-            if ((rc = qsd_matvec(h, 1, y, 1, S.W, 1, QSD_F64, st)) != QSD_OK) break;
+            if (op.takes(QSD_F64)) {
+                if ((rc = op.matvec(1, y, 1, S.W, 1, QSD_F64, st)) != QSD_OK) break;
+            } else {  // a stored FP32 matrix: the residual of the FP32 operator
+                kbl_to_f32<<<1024, kThreads, 0, st>>>(y, S.X32, N);
+                if ((rc = op.matvec(1, S.X32, 1, S.W32, 1, QSD_F32, st)) != QSD_OK) break;
+                kbl_to_f64<<<1024, kThreads, 0, st>>>(S.W32, S.W, N);
+            }
             kbl_sq<<<kGramTiles, kThreads, 0, st>>>(S.W, y, theta, N, S.red);
             std::vector<double> parts(kGramTiles);
             if (hipMemcpyAsync(parts.data(), S.red, kGramTiles * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -766,24 +772,46 @@ int block_lanczos(const qsd_ham *h, const qsd_lanczos_opts &o, double *eval_out,
 
 using namespace qsd;
 
-extern "C" int qsd_block_lanczos(const qsd_ham *h, int32_t block, const qsd_lanczos_opts *opts, double *eval_out,
-                                 void *d_evec, qsd_lanczos_info *info, void *stream) {
-    clear_error();
-    if (!h || !eval_out) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+namespace {
+
+int block_entry(const SpmvOp &op, int32_t block, const qsd_lanczos_opts *opts, double *eval_out, void *d_evec,
+                qsd_lanczos_info *info, void *stream) {
+    if (!eval_out) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
     qsd_lanczos_opts o;
     qsd_lanczos_default_opts(&o);
     if (opts) o = *opts;
-    if (h->is_complex) return fail(QSD_ERR_UNSUPPORTED, "block Lanczos for complex operators is not implemented");
+    if (op.is_complex()) return fail(QSD_ERR_UNSUPPORTED, "block Lanczos for complex operators is not implemented");
     if (block != 4 && block != 8) return fail(QSD_ERR_INVALID_ARG, "block must be 4 or 8");
     if (o.max_iter < 1 || o.max_iter > kMaxSteps)
         return fail(QSD_ERR_INVALID_ARG, "max_iter (block steps) must be in [1, %d]", kMaxSteps);
     if (!(o.tol > 0)) return fail(QSD_ERR_INVALID_ARG, "tol must be > 0");
     if (o.spmv_dtype != QSD_F64 && o.spmv_dtype != QSD_F32) return fail(QSD_ERR_DTYPE, "spmv_dtype must be F64 or F32");
+    if (!op.takes(o.spmv_dtype)) return fail(QSD_ERR_DTYPE, "spmv_dtype must be the stored matrix's dtype");
     if (o.v0_mode < QSD_V0_UNIFORM || o.v0_mode > QSD_V0_USER) return fail(QSD_ERR_INVALID_ARG, "bad v0_mode");
     if ((o.v0_mode == QSD_V0_USER || o.want_vector) && !d_evec)
         return fail(QSD_ERR_INVALID_ARG, "d_evec is required for QSD_V0_USER / want_vector");
     if (o.check_every < 1) o.check_every = 1;
     hipStream_t st = (hipStream_t)stream;
-    return block == 8 ? block_lanczos<8>(h, o, eval_out, d_evec, info, st)
-                      : block_lanczos<4>(h, o, eval_out, d_evec, info, st);
+    return block == 8 ? block_lanczos<8>(op, o, eval_out, d_evec, info, st)
+                      : block_lanczos<4>(op, o, eval_out, d_evec, info, st);
+}
+
+}  // namespace
+
+extern "C" int qsd_block_lanczos(const qsd_ham *h, int32_t block, const qsd_lanczos_opts *opts, double *eval_out,
+                                 void *d_evec, qsd_lanczos_info *info, void *stream) {
+    clear_error();
+    if (!h) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+    SpmvOp op;
+    op.h = h;
+    return block_entry(op, block, opts, eval_out, d_evec, info, stream);
+}
+
+extern "C" int qsd_csr_block_lanczos(const qsd_csr *c, int32_t block, const qsd_lanczos_opts *opts, double *eval_out,
+                                     void *d_evec, qsd_lanczos_info *info, void *stream) {
+    clear_error();
+    if (!c) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+    SpmvOp op;
+    op.c = c;
+    return block_entry(op, block, opts, eval_out, d_evec, info, stream);
 }

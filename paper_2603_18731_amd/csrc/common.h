@@ -155,3 +155,31 @@ struct qsd_ham {
     float *diag32 = nullptr;      // [N]
     float *diag32_im = nullptr;
 };
+
+struct qsd_csr {
+    int64_t N = 0;
+    int64_t nnz = 0;
+    int32_t index_type = QSD_INDEX_I32;
+    int32_t dtype = QSD_F64;
+    bool cplx = false;
+    int64_t *indptr = nullptr;  // [N + 1]
+    void *indices = nullptr;    // [nnz] int32 or int64
+    void *data = nullptr;       // [nnz] (x2 for complex) FP64 or FP32
+    double *diag = nullptr;     // [N] real part of the diagonal (start vectors)
+    int lpr = 1;                // SpMV lanes per row
+};
+
+namespace qsd {
+// The operator an eigensolver applies: matrix-free (a bound Hamiltonian) or a stored CSR matrix.
+struct SpmvOp {
+    const qsd_ham *h = nullptr;
+    const qsd_csr *c = nullptr;
+    int64_t N() const { return c ? c->N : h->N; }
+    bool is_complex() const { return c ? c->cplx : h->is_complex; }
+    const double *diag() const { return c ? c->diag : h->diag; }
+    bool takes(int32_t dtype) const { return !c || c->dtype == dtype; }
+    int matvec(int nvec, const void *x, int64_t ldx, void *y, int64_t ldy, int32_t dtype, hipStream_t st) const {
+        return c ? qsd_csr_matvec(c, nvec, x, ldx, y, ldy, dtype, st) : qsd_matvec(h, nvec, x, ldx, y, ldy, dtype, st);
+    }
+};
+}  // namespace qsd

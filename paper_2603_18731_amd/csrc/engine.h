@@ -192,11 +192,32 @@ __device__ __forceinline__ int pop_group(uint32_t &mlo, uint32_t &mhi) {
     return c;
 }
 
+// Highest qubit of a group's flip mask (its most significant off-diagonal bit).
+template <int Wp>
+__device__ __forceinline__ uint32_t group_msob(const uint64_t *__restrict__ mask) {
+    uint32_t ms = 0;
+    bool found = false;
+#pragma unroll
+    for (int w = Wp - 1; w >= 0; --w) {
+        const uint64_t m = mask[w];
+        if (!found && m) {
+            ms = 64u * (uint32_t)w + 63u - (uint32_t)__clzll(m);
+            found = true;
+        }
+    }
+    return ms;
+}
+
 // Walks all groups for the lane's row and calls on_hit(j, t0, len) for every probe whose
 // column b_i ^ M_g is in the subspace (j = its index; [t0, t0 + len) = the group's terms for
 // the row's ladder integer), in increasing g.  All threads of the block must call it (chunks
 // are staged through LDS with barriers).  `valid` = the lane owns a row.
-template <int Wp, class OnHit>
+//
+// LOWER keeps only groups whose column sorts below the row (Methods, Lower / upper triangle
+// evaluation): the flip changes the row's bit at the group's most significant off-diagonal
+// bit, so the column is smaller exactly when that row bit is set, and in the ascending
+// canonical order its index is smaller too.  One more plane test per group in the scan.
+template <int Wp, bool LOWER = false, class OnHit>
 __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, const uint64_t (&key)[Wp],
                                            uint64_t hrow, bool valid, ChunkLds<Wp> &lds, OnHit &&on_hit,
                                            unsigned long long *probes = nullptr) {
@@ -230,6 +251,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
 #pragma unroll
             for (int j = 0; j < 4; ++j) P[j] = planes[((uint32_t)(rec >> (16 + 12 * j)) & 0xFFFu) + (uint32_t)j];
             live = sliced_table((uint32_t)rec & 0xFFFFu, P[0], P[1], P[2], P[3]) & vrows;
+            if (LOWER) live &= planes[group_msob<Wp>(h.g_mask + (g0 + lane) * Wp)];
         }
         live = wave_transpose64(live, lane);
         uint32_t mlo = (uint32_t)live, mhi = (uint32_t)(live >> 32);

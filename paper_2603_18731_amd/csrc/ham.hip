@@ -162,14 +162,8 @@ __global__ __launch_bounds__(kBlock) void k_csr_sort(const int64_t *__restrict__
 
 inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
-HamView view_of(const qsd_ham *h, bool f32) {
-    return HamView{h->g_mask, h->g_hash, h->g_pos,  h->g_scan, h->g_info, h->g_term0, h->g_nterm,
-                   h->g_iptr, h->t_cws,  f32 ? (const void *)h->t_coef32 : (const void *)h->t_coef, h->G};
-}
-
-SubView sview(const qsd_subspace *s) {
-    return SubView{s->keys, s->hkey, s->slots, s->bitmap, s->N, (uint32_t)(s->C - 1)};
-}
+inline HamView view_of(const qsd_ham *h, bool f32) { return ham_view(h, f32); }
+inline SubView sview(const qsd_subspace *s) { return sub_view(s); }
 
 template <class T>
 int upload(T **dst, const std::vector<T> &src, hipStream_t st) {

@@ -281,14 +281,14 @@ __global__ __launch_bounds__(kRed) void k_resid_part(const double *__restrict__ 
 
 inline unsigned gridN(int64_t n) { return (unsigned)((n + kRed - 1) / kRed); }
 
-int enqueue_iteration(const qsd_ham *h, LzState &S, bool f32, hipStream_t st) {
+int enqueue_iteration(const SpmvOp &op, LzState &S, bool f32, hipStream_t st) {
     const int64_t N = S.N;
     if (f32) {
         k_f64_to_f32<<<1024, kRed, 0, st>>>(S.x, S.x32, N);
-        QSD_TRY(qsd_matvec(h, 1, S.x32, 1, S.w32, 1, QSD_F32, st));
+        QSD_TRY(op.matvec(1, S.x32, 1, S.w32, 1, QSD_F32, st));
         k_f32_to_f64<<<1024, kRed, 0, st>>>(S.w32, S.w, N);
     } else {
-        QSD_TRY(qsd_matvec(h, 1, S.x, 1, S.w, 1, QSD_F64, st));
+        QSD_TRY(op.matvec(1, S.x, 1, S.w, 1, QSD_F64, st));
     }
     for (int pass = 0; pass < 2; ++pass) {
         k_gemv_t<<<kDotBlocks, kRed, 0, st>>>(S.V, S.w, N, S.kdev, 0, S.part);
@@ -326,24 +326,26 @@ extern "C" void qsd_lanczos_default_opts(qsd_lanczos_opts *o) {
     o->use_graph = 0;
 }
 
-extern "C" int qsd_lanczos(const qsd_ham *h, const qsd_lanczos_opts *opts, double *eval_out, void *d_evec,
-                           qsd_lanczos_info *info, void *stream) {
-    clear_error();
+namespace {
+
+int lanczos_impl(const SpmvOp &op, const qsd_lanczos_opts *opts, double *eval_out, void *d_evec,
+                 qsd_lanczos_info *info, void *stream) {
     auto t_start = std::chrono::steady_clock::now();
-    if (!h || !eval_out) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+    if (!eval_out) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
     qsd_lanczos_opts o;
     qsd_lanczos_default_opts(&o);
     if (opts) o = *opts;
-    if (h->is_complex) return fail(QSD_ERR_UNSUPPORTED, "Lanczos for complex operators is not implemented");
+    if (op.is_complex()) return fail(QSD_ERR_UNSUPPORTED, "Lanczos for complex operators is not implemented");
     if (o.max_iter < 1 || o.max_iter > 1000) return fail(QSD_ERR_INVALID_ARG, "max_iter must be in [1, 1000]");
     if (!(o.tol > 0)) return fail(QSD_ERR_INVALID_ARG, "tol must be > 0");
     if (o.spmv_dtype != QSD_F64 && o.spmv_dtype != QSD_F32) return fail(QSD_ERR_DTYPE, "spmv_dtype must be F64 or F32");
+    if (!op.takes(o.spmv_dtype)) return fail(QSD_ERR_DTYPE, "spmv_dtype must be the stored matrix's dtype");
     if (o.v0_mode < QSD_V0_UNIFORM || o.v0_mode > QSD_V0_USER) return fail(QSD_ERR_INVALID_ARG, "bad v0_mode");
     if ((o.v0_mode == QSD_V0_USER || o.want_vector) && !d_evec)
         return fail(QSD_ERR_INVALID_ARG, "d_evec is required for QSD_V0_USER / want_vector");
     if (o.check_every < 1) o.check_every = 1;
     hipStream_t st = (hipStream_t)stream;
-    const int64_t N = h->N;
+    const int64_t N = op.N();
     LzState S;
     S.N = N;
     S.m = (int)std::min<int64_t>(o.max_iter, N);
@@ -387,7 +389,7 @@ extern "C" int qsd_lanczos(const qsd_ham *h, const qsd_lanczos_opts *opts, doubl
         } else {
             int64_t *spike = nullptr;
             if ((rc = dev_alloc(&spike, 1)) != QSD_OK) break;
-            if (o.v0_mode == QSD_V0_MIN_DIAG) k_argmin<<<1, kRed, 0, st>>>(h->diag, N, spike);
+            if (o.v0_mode == QSD_V0_MIN_DIAG) k_argmin<<<1, kRed, 0, st>>>(op.diag(), N, spike);
             k_init_v0<<<1024, kRed, 0, st>>>(S.x, N, o.v0_mode, o.seed, spike);
             if (hipStreamSynchronize(st) != hipSuccess) rc = fail(QSD_ERR_HIP, "v0 failed");
             dev_free(spike);
@@ -409,7 +411,7 @@ extern "C" int qsd_lanczos(const qsd_ham *h, const qsd_lanczos_opts *opts, doubl
                 rc = fail(QSD_ERR_HIP, "stream capture failed");
                 break;
             }
-            int erc = enqueue_iteration(h, S, f32, st);
+            int erc = enqueue_iteration(op, S, f32, st);
             hipError_t ce = hipStreamEndCapture(st, &graph);
             if (erc != QSD_OK || ce != hipSuccess) {
                 rc = erc != QSD_OK ? erc : fail(QSD_ERR_HIP, "end capture failed");
@@ -428,7 +430,7 @@ extern "C" int qsd_lanczos(const qsd_ham *h, const qsd_lanczos_opts *opts, doubl
                 if (gexec) {
                     if (hipGraphLaunch(gexec, st) != hipSuccess) rc = fail(QSD_ERR_HIP, "graph launch failed");
                 } else {
-                    rc = enqueue_iteration(h, S, f32, st);
+                    rc = enqueue_iteration(op, S, f32, st);
                 }
             }
             if (rc != QSD_OK) break;
@@ -465,9 +467,9 @@ extern "C" int qsd_lanczos(const qsd_ham *h, const qsd_lanczos_opts *opts, doubl
         // matvec timing: one extra timed SpMV (the Lanczos loop itself is not instrumented)
         hipEventRecord(e0, st);
         if (f32)
-            rc = qsd_matvec(h, 1, S.x32, 1, S.w32, 1, QSD_F32, st);
+            rc = op.matvec(1, S.x32, 1, S.w32, 1, QSD_F32, st);
         else
-            rc = qsd_matvec(h, 1, S.x, 1, S.w, 1, QSD_F64, st);
+            rc = op.matvec(1, S.x, 1, S.w, 1, QSD_F64, st);
         hipEventRecord(e1, st);
         if (rc != QSD_OK) break;
         hipEventSynchronize(e1);
@@ -477,7 +479,13 @@ extern "C" int qsd_lanczos(const qsd_ham *h, const qsd_lanczos_opts *opts, doubl
             k_gemv_n<<<gridN(N), kRed, 0, st>>>(S.V, S.tri + 3, iters, N, y);
             k_sq_part<<<kDotBlocks, kRed, 0, st>>>(y, N, S.part);
             k_scale<<<1024, kRed, 0, st>>>(y, N, S.part, kDotBlocks);
-            if ((rc = qsd_matvec(h, 1, y, 1, S.w, 1, QSD_F64, st)) != QSD_OK) break;
+            if (op.takes(QSD_F64)) {
+                if ((rc = op.matvec(1, y, 1, S.w, 1, QSD_F64, st)) != QSD_OK) break;
+            } else {  // a stored FP32 matrix: the residual of the FP32 operator
+                k_f64_to_f32<<<1024, kRed, 0, st>>>(y, S.x32, N);
+                if ((rc = op.matvec(1, S.x32, 1, S.w32, 1, QSD_F32, st)) != QSD_OK) break;
+                k_f32_to_f64<<<1024, kRed, 0, st>>>(S.w32, S.w, N);
+            }
             k_resid_part<<<kDotBlocks, kRed, 0, st>>>(S.w, y, theta, N, S.part);
             std::vector<double> parts(kDotBlocks);
             if (hipMemcpyAsync(parts.data(), S.part, kDotBlocks * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -508,4 +516,24 @@ extern "C" int qsd_lanczos(const qsd_ham *h, const qsd_lanczos_opts *opts, doubl
     }
     if (!converged) return fail(QSD_ERR_NOT_CONVERGED, "Lanczos did not converge in %d iterations", iters);
     return QSD_OK;
+}
+
+}  // namespace
+
+extern "C" int qsd_lanczos(const qsd_ham *h, const qsd_lanczos_opts *opts, double *eval_out, void *d_evec,
+                           qsd_lanczos_info *info, void *stream) {
+    clear_error();
+    if (!h) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+    SpmvOp op;
+    op.h = h;
+    return lanczos_impl(op, opts, eval_out, d_evec, info, stream);
+}
+
+extern "C" int qsd_csr_lanczos(const qsd_csr *c, const qsd_lanczos_opts *opts, double *eval_out, void *d_evec,
+                               qsd_lanczos_info *info, void *stream) {
+    clear_error();
+    if (!c) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+    SpmvOp op;
+    op.c = c;
+    return lanczos_impl(op, opts, eval_out, d_evec, info, stream);
 }

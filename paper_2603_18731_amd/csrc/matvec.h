@@ -6,6 +6,15 @@
 
 namespace qsd {
 
+inline HamView ham_view(const qsd_ham *h, bool f32) {
+    return HamView{h->g_mask, h->g_hash, h->g_pos,  h->g_scan, h->g_info, h->g_term0, h->g_nterm,
+                   h->g_iptr, h->t_cws,  f32 ? (const void *)h->t_coef32 : (const void *)h->t_coef, h->G};
+}
+
+inline SubView sub_view(const qsd_subspace *s) {
+    return SubView{s->keys, s->hkey, s->slots, s->bitmap, s->N, (uint32_t)(s->C - 1)};
+}
+
 // Row tile of workgroup b out of G.  Workgroups are dispatched round-robin over the 8 XCDs, so
 // with `remap` the tiles of one XCD are made contiguous (XCD x takes the x-th eighth of the rows,
 // in order): neighbouring rows, whose columns and hash probes overlap, then share one L2.
