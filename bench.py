@@ -40,11 +40,11 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload, dtype, nvec):
+def stored_traffic(workload, dtype, nvec, capacity):
     """HBM bytes per SpMV launch from the committed counter profile of this workload, or None
-    when there is none or it was taken on other kernel sources.  The profile records
-    FETCH_SIZE and WRITE_SIZE per dispatch (KiB) and the factors that scale them to the bytes a
-    plain copy of known size moves."""
+    when there is none, it was taken on other kernel sources or with another hash-table size.
+    The profile records FETCH_SIZE and WRITE_SIZE per dispatch (KiB) and the factors that scale
+    them to the bytes a plain copy of known size moves."""
     path = os.path.join(ROOT, "profiles", "k_matvec_%s_%s_nvec%d.md" % (workload, dtype, nvec))
     if not os.path.exists(path):
         return None
@@ -55,7 +55,7 @@ def stored_traffic(workload, dtype, nvec):
                 for kv in line.split()[1:]:
                     k, v = kv.split("=")
                     vals[k] = v
-    if vals.get("source_digest") != kernel_digest():
+    if vals.get("source_digest") != kernel_digest() or int(vals.get("capacity", -1)) != capacity:
         return None
     return float(vals["hbm_bytes_per_launch"])
 
@@ -247,10 +247,14 @@ def csr_compare(args):
 
     torch.cuda.set_device(0)
     w = make_workload(args.workload)
-    sub = qsd.Subspace(w.keys, w.ops.n_qubits)
+    sub = qsd.Subspace(w.keys, w.ops.n_qubits, max_load=args.max_load)
     op = qsd.operator_from_termlist(w.ops)
     H = qsd.SubspaceHamiltonian(sub, op)
-    tune = H.autotune(reps=2)
+    tune = None
+    if args.schedule == "auto":
+        tune = H.autotune(reps=2, load=args.max_load == 0.0)
+    else:
+        H.schedule = int(args.schedule)
     N = sub.N
     print("# %s: N=%d, autotuned %s" % (w.name, N, json.dumps(tune)), file=sys.stderr, flush=True)
     st = torch.cuda.current_stream()
@@ -288,7 +292,7 @@ def csr_compare(args):
                 "spmv_max_rel_diff": float(((y2 - y).abs().max() / y.abs().max()).item())})
     print("# SpMV: matrix-free %.3f ms, CSR %.3f ms (%.0f GB/s streamed)" % (mf_ms, csr_ms, out["csr_spmv_gbs"]),
           file=sys.stderr, flush=True)
-    for mode, obj in (("csr", A), ("matrix_free", H)):
+    for mode, obj in (() if args.no_solve else (("csr", A), ("matrix_free", H))):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         e, _, info = obj.lanczos(tol=1e-10, max_iter=300, v0="uniform", raise_on_nonconv=False)
@@ -297,7 +301,8 @@ def csr_compare(args):
         out["iterations_" + mode] = info["iterations"]
         print("# Lanczos (%s): %.12f in %.3f s, %d iterations" % (mode, e, out["solve_s_" + mode],
                                                                   info["iterations"]), file=sys.stderr, flush=True)
-    out["energy_rel_diff"] = abs(out["energy_csr"] - out["energy_matrix_free"]) / abs(out["energy_matrix_free"])
+    if not args.no_solve:
+        out["energy_rel_diff"] = abs(out["energy_csr"] - out["energy_matrix_free"]) / abs(out["energy_matrix_free"])
     print(json.dumps({"csr_vs_matrix_free": out}), flush=True)
 
 
@@ -432,7 +437,7 @@ def main():
                    "schedule": sched, "hash_capacity": sub.capacity, "autotune": tune},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": stored_traffic(w.name, args.dtype, args.nvec), "bytes_per_launch": balg,
+                     "traffic": stored_traffic(w.name, args.dtype, args.nvec, sub.capacity), "bytes_per_launch": balg,
                      "kernel_ms": k_avg, "kernel_source_digest": kernel_digest()},
         "work": {"probes": probes, "hits": hits, "evaluations": N * op.n_groups,
                  "probes_per_s": probes / (k_avg / 1e3), "evaluations_per_s": N * op.n_groups / (k_avg / 1e3)},
