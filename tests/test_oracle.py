@@ -331,3 +331,67 @@ def test_workload_generators():
     np.testing.assert_array_equal(h, h.T)
     for perm in ((1, 0, 2, 3), (0, 1, 3, 2), (2, 3, 0, 1), (3, 2, 1, 0)):
         np.testing.assert_array_equal(eri, eri.transpose(perm))
+
+
+# ------------------------------------------------------------------ RAMPS (Supplement, Alg. S1)
+
+def _chain4(h01):
+    return np.array([[-5.0, h01, 0, 0], [np.conj(h01), -1.0, 0.2, 0], [0, 0.2, 0.5, 0.4], [0, 0, 0.4, 2.0]])
+
+
+@pytest.mark.parametrize("h01", [0.3, 0.3j])
+def test_ramps_chain_matches_eq_s1(h01):
+    """On the tridiagonal 4-state chain with S_0 = {0} and E = H_00, the forward path's
+    amplitudes at depths 1, 2, 3 are the three lines of the paper's recursive energy shift
+    (Supplement, Eq. S1); |H_01|^2 (not H_01^2) enters, so a purely imaginary H_01 gives the
+    same values."""
+    from oracle import ramps as ora
+
+    H = _chain4(h01)
+    H00, H11, H22, H33 = H[0, 0].real, H[1, 1].real, H[2, 2].real, H[3, 3].real
+    a01, a12, a23 = abs(H[0, 1]) ** 2, abs(H[1, 2]) ** 2, abs(H[2, 3]) ** 2
+    line1 = a01 / (H00 * (H00 - H11))
+    line2 = (1.0 / (H00 * (H00 - H11))) * (a01 / (H00 - H11)) * (a12 / (H00 - H22))
+    line3 = (1.0 / (H00 * (H00 - H11) * (H00 - H22))) * (a01 / (H00 - H11)) * (a12 / (H00 - H22)) * (a23 / (H00 - H33))
+    sel, levels = ora.ramps_restricted(sp.csr_matrix(H), [0], H00, 0.0, max_depth=3)
+    assert sel == [0, 1, 2, 3]
+    fwd = [dict(lv).get(k) for lv, k in zip(levels, (1, 2, 3))]
+    np.testing.assert_allclose(fwd, [line1, line2, line3], rtol=1e-14)
+    # back paths (2 -> 1) exist at depth 3; paths into S_0 are not followed
+    assert all(k != 0 for lv in levels for k, _ in lv)
+
+
+def _random_graph_h(n=60, seed=4):
+    rng = np.random.default_rng(seed)
+    M = sp.random(n, n, density=0.04, random_state=seed, data_rvs=lambda s: rng.normal(0, 0.3, s))
+    M = sp.triu(M, 1)
+    M = (M + M.T).tocsr()
+    M.setdiag(np.sort(rng.normal(0, 3, n)) + 10.0)
+    return M.tocsr()
+
+
+def test_ramps_limits_and_ball():
+    """tau = inf keeps S_0; tau = 0 keeps exactly the graph ball of radius max_depth around S_0
+    (shortest paths, a library routine); the output shrinks as tau grows."""
+    from scipy.sparse.csgraph import shortest_path
+
+    from oracle import ramps as ora
+
+    M = _random_graph_h()
+    s0 = [3, 17]
+    E = float(M[3, 3]) - 0.5
+    sel, _ = ora.ramps_restricted(M, s0, E, np.inf, max_depth=10)
+    assert sel == s0
+    P = M.copy()
+    P.setdiag(0)
+    P.eliminate_zeros()
+    dist = shortest_path((P != 0).astype(np.float64), unweighted=True, indices=s0).min(axis=0)
+    for d in (1, 2, 3):
+        sel, _ = ora.ramps_restricted(M, s0, E, 0.0, max_depth=d)
+        assert sel == sorted(np.nonzero(dist <= d)[0].tolist()), d
+    prev = None
+    for tau in (1e-9, 1e-6, 1e-4, 1e-2):
+        sel, _ = ora.ramps_restricted(M, s0, E, tau, max_depth=12)
+        if prev is not None:
+            assert set(sel) <= set(prev)
+        prev = sel
