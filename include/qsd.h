@@ -121,6 +121,12 @@ int qsd_subspace_info(const qsd_subspace *s, int64_t *N, int32_t *n_qubits, int3
  * next launch; serving requests hold the old one and must be removed first).  Synchronizes. */
 int qsd_subspace_rehash(qsd_subspace *s, double max_load, void *stream);
 
+/* New subspace of the strings whose byte in d_mask[N] (device) is nonzero, in the same order
+ * (indices renumbered consecutively), with a table for max_load (0 = default).  INVALID_ARG when
+ * the mask selects nothing.  Synchronizes. */
+int qsd_subspace_select(const qsd_subspace *s, const uint8_t *d_mask, double max_load, void *stream,
+                        qsd_subspace **out);
+
 /* Copies the canonical (sorted, unique) strings to device memory d_out, [N][W] row-major. */
 int qsd_subspace_keys(const qsd_subspace *s, uint64_t *d_out, void *stream);
 
@@ -371,6 +377,34 @@ int qsd_csr_lanczos(const qsd_csr *c, const qsd_lanczos_opts *opts, double *eval
 int qsd_csr_block_lanczos(const qsd_csr *c, int32_t block, const qsd_lanczos_opts *opts, double *eval_out,
                           void *d_evec, qsd_lanczos_info *info, void *stream);
 int qsd_csr_destroy(qsd_csr *c);
+
+/* ====================================================================== RAMPS
+ *
+ * qsd_ramps - Supplement, Recursive algorithm for a minimal perturbative subspace (Algorithm
+ *   S1), restricted to the operator's subspace S_full (columns outside S_full are not
+ *   followed), frontier-parallel on the device.  Every state of S_0 (host indices s0[n0] into
+ *   S_full) starts a walk with prefactor 1/E; a frontier entry (j, pre) visits each off-diagonal
+ *   element H_jk of its row with k in S_full and k not in S_0, forms
+ *   amp = (pre * |H_jk|^2) / (E - H_kk) (in this order, no fused operations), and when
+ *   |amp| > tau selects k and continues from it with prefactor amp / (E - H_kk).  A column
+ *   reached along several paths is carried once per path.  Levels stop when the frontier is
+ *   empty or after max_depth levels (then info->truncated = 1).
+ *   d_selected  device [N] bytes, out: 1 for S_0 and every selected column, else 0.
+ *   n_selected  host, out (may be NULL); info host, out (may be NULL).
+ *   max_frontier  paths one level may hold; CAPACITY when a level needs more (outputs then
+ *   undefined).  Real or complex H (|H_jk|^2).  Synchronizes once per level.
+ *   Device memory: N bytes + 32 * max_frontier bytes.
+ * Follow with qsd_subspace_select to build the trimmed subspace.
+ */
+typedef struct {
+    int32_t levels;       /* levels run */
+    int32_t truncated;    /* 1 if max_depth stopped a non-empty frontier */
+    int64_t paths;        /* frontier entries created over all levels */
+    int64_t max_frontier; /* largest level */
+    int64_t selected;     /* strings in the output subspace */
+} qsd_ramps_info;
+int qsd_ramps(const qsd_ham *h, const int64_t *s0, int64_t n0, double E, double tau, int32_t max_depth,
+              int64_t max_frontier, uint8_t *d_selected, int64_t *n_selected, qsd_ramps_info *info, void *stream);
 
 /* ========================================================= batched Lanczos (serving)
  *

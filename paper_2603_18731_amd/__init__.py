@@ -42,7 +42,7 @@ EXPORTED = [
     "qsd_batch_poll", "qsd_batch_remove", "qsd_batch_destroy", "qsd_matvec_batched", "qsd_block_lanczos",
     "qsd_ham_set_schedule", "qsd_ham_get_schedule", "qsd_ham_autotune", "qsd_subspace_rehash",
     "qsd_csr_create", "qsd_csr_info", "qsd_csr_export", "qsd_csr_matvec", "qsd_csr_lanczos", "qsd_csr_block_lanczos",
-    "qsd_csr_destroy",
+    "qsd_csr_destroy", "qsd_subspace_select", "qsd_ramps",
 ]
 
 
@@ -55,6 +55,14 @@ class QsdError(RuntimeError):
 class TuneResult(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_uint32), ("capacity", ctypes.c_int64), ("max_load", ctypes.c_double),
                 ("ms", ctypes.c_double), ("ms_before", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class RampsInfo(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("truncated", ctypes.c_int32), ("paths", ctypes.c_int64),
+                ("max_frontier", ctypes.c_int64), ("selected", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -128,6 +136,8 @@ def lib():
         "qsd_csr_block_lanczos": ([P, I32, ctypes.POINTER(LanczosOpts), P, P, ctypes.POINTER(LanczosInfo), P],
                                   ctypes.c_int),
         "qsd_csr_destroy": ([P], ctypes.c_int),
+        "qsd_subspace_select": ([P, P, D, P, PP], ctypes.c_int),
+        "qsd_ramps": ([P, P, I64, D, D, I32, I64, P, P, ctypes.POINTER(RampsInfo), P], ctypes.c_int),
         "qsd_block_lanczos": ([P, I32, ctypes.POINTER(LanczosOpts), P, P, ctypes.POINTER(LanczosInfo), P],
                               ctypes.c_int),
         "qsd_batch_step": ([P, I32, P], ctypes.c_int),
@@ -231,6 +241,22 @@ class Subspace:
         out = torch.empty(qt.shape[0], dtype=torch.int64, device="cuda")
         _check(lib().qsd_subspace_lookup(self._h, _ptr(qt), qt.shape[0], _ptr(out), _stream(stream)))
         return out
+
+    @classmethod
+    def _wrap(cls, handle, n_qubits: int):
+        self = cls.__new__(cls)
+        self._h = handle
+        self.n_qubits = int(n_qubits)
+        N, nq, Wo, C = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().qsd_subspace_info(handle, ctypes.byref(N), ctypes.byref(nq), ctypes.byref(Wo), ctypes.byref(C)))
+        self.N, self.W, self.capacity = N.value, Wo.value, C.value
+        return self
+
+    def select(self, mask, max_load: float = 0.0, stream=None) -> "Subspace":
+        """The strings whose byte in ``mask`` (device uint8 [N]) is nonzero, as a new subspace."""
+        h = ctypes.c_void_p()
+        _check(lib().qsd_subspace_select(self._h, _ptr(mask), max_load, _stream(stream), ctypes.byref(h)))
+        return Subspace._wrap(h, self.n_qubits)
 
     def _refresh(self):
         N, nq, Wo, C = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
@@ -390,6 +416,19 @@ class SubspaceHamiltonian:
         _check(lib().qsd_matvec(self._h, nvec, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0), self._dtype_code(X),
                                 _stream(stream)))
         return Y.reshape(-1) if vec else Y
+
+    def ramps(self, s0, E: float, tau: float, max_depth: int = 32, max_frontier: int = 1 << 22, stream=None):
+        """RAMPS restricted to this subspace (Supplement, Algorithm S1): ``(mask, info)`` with
+        ``mask`` a device uint8 [N] tensor marking S_0 and the selected strings."""
+        import torch
+
+        idx = np.ascontiguousarray(np.asarray(s0, dtype=np.int64).reshape(-1))
+        mask = torch.empty(self.N, dtype=torch.uint8, device="cuda")
+        info = RampsInfo()
+        n = ctypes.c_int64()
+        _check(lib().qsd_ramps(self._h, _ptr(idx), idx.size, float(E), float(tau), int(max_depth), int(max_frontier),
+                               _ptr(mask), ctypes.byref(n), ctypes.byref(info), _stream(stream)))
+        return mask, info.as_dict()
 
     def matvec_raw(self, nvec, x_ptr, ldx, y_ptr, ldy, dtype, stream=None):
         _check(lib().qsd_matvec(self._h, nvec, ctypes.c_void_p(x_ptr), ldx, ctypes.c_void_p(y_ptr), ldy, dtype,

@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqsd.so")
 
-SOURCES = ["api.cpp", "opcompile.cpp", "subspace.hip", "ham.hip", "lanczos.hip", "diag.hip", "serve.hip", "block.hip", "csr.hip"]
+SOURCES = ["api.cpp", "opcompile.cpp", "subspace.hip", "ham.hip", "lanczos.hip", "diag.hip", "serve.hip", "block.hip", "csr.hip", "ramps.hip"]
 ARCH = os.environ.get("QSD_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

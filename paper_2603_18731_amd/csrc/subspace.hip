@@ -552,6 +552,54 @@ __global__ __launch_bounds__(kBlock) void k_planes_to_rows(const uint64_t *__res
 }
 }  // namespace
 
+namespace {
+__global__ __launch_bounds__(kBlock) void k_mask_to_i64(const uint8_t *__restrict__ m, int64_t N, int64_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < N) out[i] = m[i] ? 1 : 0;
+    if (i == N) out[i] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_select_rows(const uint64_t *__restrict__ planes, int64_t N, int W,
+                                                        const uint8_t *__restrict__ m, const int64_t *__restrict__ pos,
+                                                        uint64_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= N || !m[i]) return;
+    for (int w = 0; w < W; ++w) out[pos[i] * W + w] = planes[(int64_t)w * N + i];
+}
+}  // namespace
+
+extern "C" int qsd_subspace_select(const qsd_subspace *s, const uint8_t *d_mask, double max_load, void *stream,
+                                   qsd_subspace **out) {
+    clear_error();
+    if (!s || !d_mask || !out) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = s->N;
+    int64_t *flag = nullptr, *pos = nullptr;
+    QSD_TRY(dev_alloc(&flag, N + 1));
+    int rc = dev_alloc(&pos, N + 1);
+    int64_t n = 0;
+    if (rc == QSD_OK) {
+        k_mask_to_i64<<<grid_for(N + 1, kBlock), kBlock, 0, st>>>(d_mask, N, flag);
+        rc = exclusive_scan_i64(flag, pos, N + 1, st);
+    }
+    if (rc == QSD_OK && (hipMemcpyAsync(&n, pos + N, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                         hipStreamSynchronize(st) != hipSuccess))
+        rc = fail(QSD_ERR_HIP, "selection count failed");
+    if (rc == QSD_OK && n == 0) rc = fail(QSD_ERR_INVALID_ARG, "the mask selects no string");
+    uint64_t *rows = nullptr;
+    if (rc == QSD_OK) rc = dev_alloc(&rows, (size_t)n * s->W);
+    if (rc == QSD_OK) {
+        k_select_rows<<<grid_for(N, kBlock), kBlock, 0, st>>>(s->keys, N, s->W, d_mask, pos, rows);
+        // the rows stay in ascending order and distinct
+        rc = qsd_subspace_build(rows, n, s->n_qubits, QSD_SUB_ASSUME_SORTED_UNIQUE, max_load, stream, out);
+    }
+    dev_free(flag);
+    dev_free(pos);
+    dev_free(rows);
+    return rc;
+}
+
 extern "C" int qsd_subspace_keys(const qsd_subspace *s, uint64_t *d_out, void *stream) {
     clear_error();
     if (!s || !d_out) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
