@@ -306,6 +306,58 @@ def csr_compare(args):
     print(json.dumps({"csr_vs_matrix_free": out}), flush=True)
 
 
+def ramps_bench(args):
+    """RAMPS on the full sampled subspace of --workload (Supplement, Algorithm S1, restricted to
+    it): S_0 = the 64 strings of lowest diagonal energy, E = the ground energy of H restricted
+    to S_0; then the ground energy on the trimmed subspace against the full one."""
+    import numpy as np
+    import torch
+
+    import paper_2603_18731_amd as qsd
+
+    torch.cuda.set_device(0)
+    w = make_workload(args.workload)
+    sub = qsd.Subspace(w.keys, w.ops.n_qubits)
+    op = qsd.operator_from_termlist(w.ops)
+    H = qsd.SubspaceHamiltonian(sub, op)
+    d = H.diagonal()
+    s0 = torch.argsort(d, stable=True)[:64].cpu().numpy()
+    m0 = torch.zeros(sub.N, dtype=torch.uint8, device="cuda")
+    m0[torch.from_numpy(s0).cuda()] = 1
+    H0 = qsd.SubspaceHamiltonian(sub.select(m0), op)
+    E, _, _ = H0.lanczos(tol=1e-12, max_iter=64)
+    A = qsd.CsrMatrix(H, lower_mirror=True)
+    e_full, _, info_full = A.lanczos(tol=1e-10, max_iter=300, raise_on_nonconv=False)
+    del A
+    out = {"workload": w.name, "N_full": sub.N, "S0": int(len(s0)), "E": E, "energy_full": e_full, "runs": []}
+    print("# S_0: 64 lowest-diagonal strings, E = %.10f; full-subspace energy %.10f" % (E, e_full), file=sys.stderr,
+          flush=True)
+    for tau in (1e-3, 1e-4, 1e-5, 1e-6):
+        try:
+            H.ramps(s0, E, tau, max_depth=args.ramps_depth, max_frontier=1 << 26)  # warm-up
+        except qsd.QsdError as exc:
+            out["runs"].append({"tau": tau, "error": str(exc)})
+            print("# RAMPS tau %.0e: %s" % (tau, exc), file=sys.stderr, flush=True)
+            continue
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mask, info = H.ramps(s0, E, tau, max_depth=args.ramps_depth, max_frontier=1 << 26)
+        torch.cuda.synchronize()
+        t_ramps = time.perf_counter() - t0
+        small = sub.select(mask)
+        Hs = qsd.SubspaceHamiltonian(small, op)
+        t0 = time.perf_counter()
+        e_small, _, _ = Hs.lanczos(tol=1e-10, max_iter=300, raise_on_nonconv=False)
+        t_solve = time.perf_counter() - t0
+        r = {"tau": tau, "ramps_s": t_ramps, "solve_trimmed_s": t_solve, "energy_trimmed": e_small,
+             "energy_rel_diff": abs(e_small - e_full) / abs(e_full), **info}
+        out["runs"].append(r)
+        print("# RAMPS tau %.0e: %d of %d strings, %d paths, %d levels, %.3f s; energy %.10f (full %.10f)" % (
+            tau, info["selected"], sub.N, info["paths"], info["levels"], t_ramps, e_small, e_full), file=sys.stderr,
+            flush=True)
+    print(json.dumps({"ramps": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -322,12 +374,21 @@ def main():
                     "buffer sizes 256 KiB .. 1 GiB and exit")
     ap.add_argument("--calibrate-copy", action="store_true", help="run the plain-copy kernel used to scale "
                     "rocprofv3 FETCH_SIZE / WRITE_SIZE and exit")
+    ap.add_argument("--ramps", action="store_true", help="RAMPS on --workload's subspace from its lowest "
+                    "diagonal string; trimmed vs full ground energy")
+    ap.add_argument("--ramps-depth", type=int, default=16)
     ap.add_argument("--csr-compare", action="store_true", help="matrix-free vs stored-CSR solve on --workload")
     ap.add_argument("--serve", action="store_true", help="serving benchmark: batched Lanczos requests with "
                     "Poisson arrivals against the FIFO single-vector solver")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-smax", type=float, default=2e6)
     args = ap.parse_args()
+    if args.ramps:
+        if args.gpus != 1:
+            print("bench.py measures one GPU only (requested --gpus %d)" % args.gpus, file=sys.stderr)
+            sys.exit(2)
+        ramps_bench(args)
+        return
     if args.csr_compare:
         if args.gpus != 1:
             print("bench.py measures one GPU only (requested --gpus %d)" % args.gpus, file=sys.stderr)
