@@ -395,3 +395,63 @@ def test_ramps_limits_and_ball():
         if prev is not None:
             assert set(sel) <= set(prev)
         prev = sel
+
+
+# ------------------------------------------------------------------ group trimming
+
+def test_trim_rules_qubit_and_fermion():
+    from oracle import trim as otr
+
+    tl = wl.TermList.from_terms(3, [(0.5, [(0, 3), (1, 3)]), (0.2, [(0, 4), (1, 4)]), (0.05, [(2, 3)]),
+                                    (0.3, [(0, 0)]), (0.1, [(1, 1), (2, 6)])])
+    B = otr.group_bounds(tl)
+    assert B == {0b011: pytest.approx(0.7), 0b100: pytest.approx(0.05 + 0.1)}
+    kept = otr.trim_terms(tl, 0.2)
+    assert len(kept.coef) == 3  # XX, YY and the diagonal Z
+    assert len(otr.trim_terms(tl, 0.0).coef) == 5
+    assert len(otr.trim_terms(tl, 0.8).coef) == 1
+    ft = wl.TermList.from_terms(4, [(0.4, [(0, 6), (1, 5)]), (0.4, [(1, 6), (0, 5)]), (1.0, [(0, 6), (0, 5)]),
+                                    (0.01, [(2, 6), (3, 5)])], fermionic=True)
+    Bf = otr.group_bounds(ft)
+    assert Bf == {0b0011: pytest.approx(0.8), 0b1100: pytest.approx(0.01)}
+    assert otr.smallest_splitting([3.0, 1.0, 1.0, 2.5]) == 1.5 and otr.smallest_splitting([2.0]) == 0.0
+
+
+@pytest.mark.parametrize("fermionic", [False, True])
+def test_trim_infinite_keeps_diagonal_and_weyl_bound(fermionic):
+    """Trimming everything leaves exactly the diagonal of the dense matrix; any trimming moves
+    the lowest eigenvalue by at most the norm of what was removed, which is at most the sum of
+    the removed groups' bounds (Weyl's inequality)."""
+    from oracle import trim as otr
+
+    rng = np.random.default_rng(31 + fermionic)
+    n = 6
+    terms = []
+    for _ in range(30):
+        k = int(rng.integers(1, 4))
+        qs = rng.choice(n, size=k, replace=not fermionic)
+        codes = rng.integers(5, 7, size=k) if fermionic else rng.integers(0, 7, size=k)
+        if not fermionic:
+            qs = rng.choice(n, size=k, replace=False)
+        word = [(int(q), int(c)) for q, c in zip(qs, codes)]
+        c = float(rng.normal(0, 0.5))
+        terms.append((c, word))
+        terms.append((c, [(q, {5: 6, 6: 5}.get(cc, cc)) for q, cc in reversed(word)] if fermionic
+                      else [(q, {5: 6, 6: 5}.get(cc, cc)) for q, cc in word]))
+    tl = wl.TermList.from_terms(n, terms, fermionic=fermionic)
+
+    def dense(t):
+        if fermionic:
+            return ofe.dense_hamiltonian(n, [(complex(t.coef[i]), list(zip(t.op_idx[t.term_ptr[i]:t.term_ptr[i + 1]].tolist(), t.op_code[t.term_ptr[i]:t.term_ptr[i + 1]].tolist()))) for i in range(len(t.coef))]).toarray()
+        return ode.qubit_hamiltonian(n, [(complex(t.coef[i]), list(zip(t.op_idx[t.term_ptr[i]:t.term_ptr[i + 1]].tolist(), t.op_code[t.term_ptr[i]:t.term_ptr[i + 1]].tolist()))) for i in range(len(t.coef))]).toarray()
+
+    Hf = dense(tl)
+    H0 = dense(otr.trim_terms(tl, np.inf))
+    np.testing.assert_allclose(H0, np.diag(np.diag(Hf)), atol=1e-12)
+    B = otr.group_bounds(tl)
+    for tol in sorted(B.values())[::5]:
+        Ht = dense(otr.trim_terms(tl, tol))
+        removed = sum(v for v in B.values() if v < tol)
+        dE = abs(np.linalg.eigvalsh(Hf)[0] - np.linalg.eigvalsh(Ht)[0])
+        nrm = np.linalg.norm(Hf - Ht, 2)
+        assert dE <= nrm + 1e-12 and nrm <= removed + 1e-12
