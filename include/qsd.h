@@ -159,7 +159,13 @@ int qsd_subspace_destroy(qsd_subspace *s);
  *   inside a group whose off-diagonal letters are all ladders on at most 4 qubits, sort terms
  *   by ladder integer ('-' -> 0, '+' -> 1, k-th lowest qubit -> bit k) with 2^k + 1 range
  *   pointers.
- *   trim_tol  must be 0 (group trimming is not implemented in this build: UNSUPPORTED).
+ *   trim_tol  group trimming (Results, CH4-dimer runs): a group is the set of input terms with
+ *             the same flip mask (X, Y, raise and lower letters of a qubit word; every ladder
+ *             operator of a fermionic word flips its mode); the modulus of its matrix elements
+ *             is bounded by the sum of |c| over its input terms, and groups whose bound is
+ *             below trim_tol are dropped before compilation (diagonal terms never are).
+ *             0 keeps everything; negative is INVALID_ARG.  The paper's relative tolerance is
+ *             trim_tol = tol * qsd_ham_diag_splitting of the subspace.
  *   All arrays are host memory and are not retained.
  *   Errors: INVALID_ARG (index out of range, bad code, repeated qubit in qubit mode, NaN);
  *   NOT_HERMITIAN with QSD_OP_CHECK_HERMITIAN when some word's adjoint does not carry the
@@ -207,6 +213,12 @@ int qsd_ham_info(const qsd_ham *h, int64_t *N, int64_t *G, int32_t *is_complex);
  * projector bits match), `hits` = those whose column is in the subspace (the off-diagonal
  * stored entries).  Host outputs; either may be NULL. */
 int qsd_ham_work_counts(const qsd_ham *h, int64_t *probes, int64_t *hits, void *stream);
+
+/* Lowest diagonal element of H over the subspace and the smallest diagonal energy splitting,
+ * read as the gap from it to the next larger distinct diagonal value (0 if all are equal): the
+ * scale of group trimming (Results, CH4-dimer runs).  Host outputs (either may be NULL);
+ * synchronizes. */
+int qsd_ham_diag_splitting(const qsd_ham *h, double *lowest, double *splitting, void *stream);
 
 /* SpMV schedule (launch shape only: every schedule gives bitwise the same results, since each
  * row is evaluated by one lane in the same group order whatever workgroup runs it).

@@ -43,6 +43,7 @@ EXPORTED = [
     "qsd_ham_set_schedule", "qsd_ham_get_schedule", "qsd_ham_autotune", "qsd_subspace_rehash",
     "qsd_csr_create", "qsd_csr_info", "qsd_csr_export", "qsd_csr_matvec", "qsd_csr_lanczos", "qsd_csr_block_lanczos",
     "qsd_csr_destroy", "qsd_subspace_select", "qsd_ramps",
+    "qsd_ham_diag_splitting",
 ]
 
 
@@ -137,6 +138,7 @@ def lib():
                                   ctypes.c_int),
         "qsd_csr_destroy": ([P], ctypes.c_int),
         "qsd_subspace_select": ([P, P, D, P, PP], ctypes.c_int),
+        "qsd_ham_diag_splitting": ([P, P, P, P], ctypes.c_int),
         "qsd_ramps": ([P, P, I64, D, D, I32, I64, P, P, ctypes.POINTER(RampsInfo), P], ctypes.c_int),
         "qsd_block_lanczos": ([P, I32, ctypes.POINTER(LanczosOpts), P, P, ctypes.POINTER(LanczosInfo), P],
                               ctypes.c_int),
@@ -284,7 +286,7 @@ class _Operator:
     fermionic = False
 
     def __init__(self, n_qubits: int, term_ptr, op_idx, op_code, coef, check_hermitian: bool = False,
-                 force_complex: bool = False, ladder_ints: bool = True):
+                 force_complex: bool = False, ladder_ints: bool = True, trim_tol: float = 0.0):
         tp = np.ascontiguousarray(term_ptr, dtype=np.int64)
         oi = np.ascontiguousarray(op_idx, dtype=np.int32)
         oc = np.ascontiguousarray(op_code, dtype=np.uint8)
@@ -293,8 +295,8 @@ class _Operator:
         flags = (OP_FERMIONIC if self.fermionic else 0) | (OP_CHECK_HERMITIAN if check_hermitian else 0) | \
                 (OP_FORCE_COMPLEX if force_complex else 0) | (0 if ladder_ints else OP_NO_LADDER_INT)
         h = ctypes.c_void_p()
-        _check(lib().qsd_op_compile(int(n_qubits), tp.shape[0] - 1, _ptr(tp), _ptr(oi), _ptr(oc), _ptr(cr), flags, 0.0,
-                                    ctypes.byref(h)))
+        _check(lib().qsd_op_compile(int(n_qubits), tp.shape[0] - 1, _ptr(tp), _ptr(oi), _ptr(oc), _ptr(cr), flags,
+                                    float(trim_tol), ctypes.byref(h)))
         self._h = h
         self.n_qubits = int(n_qubits)
         T, nl, G, cx, nq = (ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32())
@@ -372,6 +374,12 @@ class SubspaceHamiltonian:
         import torch
 
         return {torch.float64: F64, torch.float32: F32, torch.complex128: C128, torch.complex64: C64}[t.dtype]
+
+    def diag_splitting(self, stream=None):
+        """``(lowest diagonal element, smallest diagonal splitting)`` over the subspace."""
+        lo, sp_ = ctypes.c_double(), ctypes.c_double()
+        _check(lib().qsd_ham_diag_splitting(self._h, ctypes.byref(lo), ctypes.byref(sp_), _stream(stream)))
+        return lo.value, sp_.value
 
     def work_counts(self, stream=None):
         """``(probes, hits)`` of one SpMV."""
@@ -465,6 +473,15 @@ class SubspaceHamiltonian:
         if h and _lib is not None:
             _lib.qsd_ham_destroy(h)
             self._h = None
+
+
+def trimmed_hamiltonian(ham: "SubspaceHamiltonian", tl, tol: float, stream=None):
+    """The Hamiltonian of term list ``tl`` on ``ham``'s subspace with the groups whose bound is
+    below ``tol`` times the subspace's smallest diagonal splitting removed (Results, CH4-dimer
+    runs): ``(trimmed SubspaceHamiltonian, absolute threshold)``."""
+    _, split = ham.diag_splitting(stream)
+    op = operator_from_termlist(tl, trim_tol=tol * split)
+    return SubspaceHamiltonian(ham.subspace, op, stream), tol * split
 
 
 def _lanczos(single, blockfn, handle, N, max_iter, tol, v0, seed, spmv_dtype, check_every, want_vector, use_graph,

@@ -492,6 +492,50 @@ extern "C" int qsd_ham_work_counts(const qsd_ham *h, int64_t *probes, int64_t *h
     return QSD_OK;
 }
 
+namespace {
+// part[block] = min over the block's chunk of d[i] among values > floor (INFINITY if none)
+__global__ __launch_bounds__(256) void k_min_above(const double *__restrict__ d, int64_t N, double floor,
+                                                   double *__restrict__ part) {
+    __shared__ double ws[4];
+    double m = INFINITY;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256)
+        if (d[i] > floor) m = fmin(m, d[i]);
+#pragma unroll
+    for (int k = 32; k >= 1; k >>= 1) m = fmin(m, __shfl_xor(m, k, 64));
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = fmin(fmin(ws[0], ws[1]), fmin(ws[2], ws[3]));
+}
+}  // namespace
+
+extern "C" int qsd_ham_diag_splitting(const qsd_ham *h, double *lowest, double *splitting, void *stream) {
+    clear_error();
+    if (!h) return fail(QSD_ERR_INVALID_ARG, "NULL handle");
+    hipStream_t st = (hipStream_t)stream;
+    constexpr int kParts = 1024;
+    double *part = nullptr;
+    QSD_TRY(dev_alloc(&part, kParts));
+    std::vector<double> hp(kParts);
+    double lo = INFINITY, next = INFINITY;
+    int rc = QSD_OK;
+    for (int pass = 0; pass < 2 && rc == QSD_OK; ++pass) {
+        k_min_above<<<kParts, 256, 0, st>>>(h->diag, h->N, pass == 0 ? -INFINITY : lo, part);
+        if (hipMemcpyAsync(hp.data(), part, kParts * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            rc = fail(QSD_ERR_HIP, "diagonal reduction failed");
+            break;
+        }
+        double m = INFINITY;
+        for (double v : hp) m = std::fmin(m, v);
+        (pass == 0 ? lo : next) = m;
+    }
+    dev_free(part);
+    if (rc != QSD_OK) return rc;
+    if (lowest) *lowest = lo;
+    if (splitting) *splitting = std::isinf(next) ? 0.0 : next - lo;
+    return QSD_OK;
+}
+
 extern "C" int qsd_ham_set_schedule(qsd_ham *h, uint32_t schedule) {
     clear_error();
     if (!h) return fail(QSD_ERR_INVALID_ARG, "NULL handle");

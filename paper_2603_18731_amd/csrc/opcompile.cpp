@@ -188,10 +188,41 @@ extern "C" int qsd_op_compile(int32_t n_qubits, int64_t n_terms, const int64_t *
     if (n_qubits > kMaxWords * 64) return fail(QSD_ERR_UNSUPPORTED, "n_qubits > %d", kMaxWords * 64);
     if (n_terms < 0 || (n_terms > 0 && (!term_ptr || !coef_reim)))
         return fail(QSD_ERR_INVALID_ARG, "bad term arrays");
-    if (trim_tol != 0.0) return fail(QSD_ERR_UNSUPPORTED, "group trimming (trim_tol != 0) is not implemented");
+    if (!(trim_tol >= 0.0)) return fail(QSD_ERR_INVALID_ARG, "trim_tol must be >= 0");
     const bool fermionic = flags & QSD_OP_FERMIONIC;
     const int Wp = padded_words(n_qubits);
     if (n_terms > 0 && term_ptr[0] != 0) return fail(QSD_ERR_INVALID_ARG, "term_ptr[0] must be 0");
+
+    // 0. group trimming (Results, CH4-dimer runs): a group is the set of input terms with the
+    //    same flip mask (X, Y and ladder letters of a qubit word; every ladder operator of a
+    //    fermionic word flips its mode).  Its matrix elements are bounded by the sum of |c|
+    //    over its input terms; groups whose bound is below trim_tol are dropped.
+    std::vector<char> keep_term((size_t)std::max<int64_t>(n_terms, 0), 1);
+    if (trim_tol > 0.0) {
+        std::map<std::vector<uint64_t>, double> bound;
+        std::vector<std::vector<uint64_t>> tmask((size_t)n_terms);
+        for (int64_t t = 0; t < n_terms; ++t) {
+            std::vector<uint64_t> m((size_t)Wp, 0ull);
+            for (int64_t k = term_ptr[t]; k < term_ptr[t + 1]; ++k) {
+                const int q = op_idx[k], code = op_code[k];
+                if (q < 0 || q >= n_qubits) continue;  // rejected below
+                const uint64_t bit = 1ull << (q & 63);
+                if (fermionic)
+                    m[(size_t)(q >> 6)] ^= bit;
+                else if (code == QSD_X || code == QSD_Y || code == QSD_LOWER || code == QSD_RAISE)
+                    m[(size_t)(q >> 6)] |= bit;
+            }
+            const double a = std::abs(cplx(coef_reim[2 * t], coef_reim[2 * t + 1]));
+            bool any = false;
+            for (uint64_t w : m) any |= w != 0;
+            if (any) bound[m] += a;
+            tmask[(size_t)t] = std::move(m);
+        }
+        for (int64_t t = 0; t < n_terms; ++t) {
+            auto it = bound.find(tmask[(size_t)t]);
+            if (it != bound.end() && it->second < trim_tol) keep_term[(size_t)t] = 0;
+        }
+    }
 
     // 1. per-term normalization --------------------------------------------------------
     std::vector<CompiledTerm> raw;
@@ -213,7 +244,7 @@ extern "C" int qsd_op_compile(int32_t n_qubits, int64_t n_terms, const int64_t *
                 return fail(QSD_ERR_INVALID_ARG, "term %lld: invalid letter code %d", (long long)t, code);
             ops.push_back({q, (uint8_t)code});
         }
-        if (c == cplx(0, 0)) continue;
+        if (c == cplx(0, 0) || !keep_term[(size_t)t]) continue;
         double sign = 1.0;
         if (fermionic) {
             if (!fermion_to_word(ops, word, sign)) continue;

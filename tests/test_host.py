@@ -183,3 +183,34 @@ def test_molecular_compile_sizes():
     assert gl[1:].all()
     assert not op.is_complex
     assert sizes.max() == 62
+
+
+@pytest.mark.parametrize("which", ["fermi", "xxz", "random_qubit"])
+def test_trimming_selects_the_oracle_groups(which):
+    """Compiling with trim_tol drops exactly the groups the oracle drops: the compiled operator
+    equals the compile of the oracle-trimmed term list, at several thresholds."""
+    from oracle import trim as otr
+
+    if which == "fermi":
+        h, eri = wl.molecular_integrals(6, 7)
+        tl = wl.molecular_terms(h, eri)
+    elif which == "xxz":
+        tl = wl.xxz_grid_6x6()
+    else:
+        rng = np.random.default_rng(9)
+        terms = []
+        for _ in range(60):
+            k = int(rng.integers(1, 4))
+            qs = rng.choice(8, size=k, replace=False)
+            terms.append((complex(rng.normal(0, 0.3), rng.normal(0, 0.3) * (k % 2)),
+                          [(int(q), int(c)) for q, c in zip(qs, rng.integers(0, 7, size=k))]))
+        tl = wl.TermList.from_terms(8, terms)
+    B = sorted(otr.group_bounds(tl).values())
+    for tol in (0.0, B[len(B) // 4], B[len(B) // 2], B[-1] * 1.0001):
+        a = qsd.operator_from_termlist(tl, trim_tol=tol).export()
+        b = qsd.operator_from_termlist(otr.trim_terms(tl, tol)).export()
+        assert len(a[0]) == len(b[0])
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+    with pytest.raises(qsd.QsdError, match="INVALID_ARG"):
+        qsd.operator_from_termlist(tl, trim_tol=-1.0)
