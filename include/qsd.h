@@ -76,6 +76,7 @@ extern "C" {
 #define QSD_OP_CHECK_HERMITIAN 2u /* fail with QSD_ERR_NOT_HERMITIAN unless H = H^dagger */
 #define QSD_OP_FORCE_COMPLEX 4u   /* treat the matrix as complex even if every element is real */
 #define QSD_OP_NO_LADDER_INT 8u   /* evaluate every group without ladder-integer ranges (ablation) */
+#define QSD_OP_ORDER_BY_MASK 16u  /* order groups by flip mask only (default: weight, then mask) */
 
 typedef struct qsd_subspace qsd_subspace;
 typedef struct qsd_op qsd_op;

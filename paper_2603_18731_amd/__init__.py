@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libqsd.so")
 QSD_OK = 0
 F64, F32, C128, C64 = 0, 1, 2, 3
 INDEX_I32, INDEX_I64 = 0, 1
-OP_FERMIONIC, OP_CHECK_HERMITIAN, OP_FORCE_COMPLEX, OP_NO_LADDER_INT = 1, 2, 4, 8
+OP_FERMIONIC, OP_CHECK_HERMITIAN, OP_FORCE_COMPLEX, OP_NO_LADDER_INT, OP_ORDER_BY_MASK = 1, 2, 4, 8, 16
 SUB_ASSUME_SORTED_UNIQUE = 1
 V0_UNIFORM, V0_MIN_DIAG, V0_RANDOM, V0_USER = 0, 1, 2, 3
 SCHED_XCD_REMAP = 1
@@ -286,14 +286,16 @@ class _Operator:
     fermionic = False
 
     def __init__(self, n_qubits: int, term_ptr, op_idx, op_code, coef, check_hermitian: bool = False,
-                 force_complex: bool = False, ladder_ints: bool = True, trim_tol: float = 0.0):
+                 force_complex: bool = False, ladder_ints: bool = True, trim_tol: float = 0.0,
+                 order_by_mask: bool = False):
         tp = np.ascontiguousarray(term_ptr, dtype=np.int64)
         oi = np.ascontiguousarray(op_idx, dtype=np.int32)
         oc = np.ascontiguousarray(op_code, dtype=np.uint8)
         c = np.asarray(coef, dtype=np.complex128)
         cr = np.ascontiguousarray(np.stack([c.real, c.imag], axis=1)).astype(np.float64)
         flags = (OP_FERMIONIC if self.fermionic else 0) | (OP_CHECK_HERMITIAN if check_hermitian else 0) | \
-                (OP_FORCE_COMPLEX if force_complex else 0) | (0 if ladder_ints else OP_NO_LADDER_INT)
+                (OP_FORCE_COMPLEX if force_complex else 0) | (0 if ladder_ints else OP_NO_LADDER_INT) | \
+                (OP_ORDER_BY_MASK if order_by_mask else 0)
         h = ctypes.c_void_p()
         _check(lib().qsd_op_compile(int(n_qubits), tp.shape[0] - 1, _ptr(tp), _ptr(oi), _ptr(oc), _ptr(cr), flags,
                                     float(trim_tol), ctypes.byref(h)))

@@ -312,8 +312,9 @@ extern "C" int qsd_op_compile(int32_t n_qubits, int64_t n_terms, const int64_t *
         else
             offd.push_back({i, std::move(m), wgt});
     }
-    std::stable_sort(offd.begin(), offd.end(), [](const Item &x, const Item &y) {
-        if (x.weight != y.weight) return x.weight < y.weight;
+    const bool by_mask = (flags & QSD_OP_ORDER_BY_MASK) != 0;
+    std::stable_sort(offd.begin(), offd.end(), [by_mask](const Item &x, const Item &y) {
+        if (!by_mask && x.weight != y.weight) return x.weight < y.weight;
         return mask_less(x.m.off, y.m.off);
     });
 

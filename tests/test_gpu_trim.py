@@ -50,3 +50,15 @@ def test_trimmed_fermionic_matrix():
         say("trim rel %.0e: threshold %.3e, groups %d of %d, energy %.10f (full %.10f), removed bound %.3e" % (
             rel, thr, groups, H.op.n_groups, e_t, e_full, removed))
         assert abs(e_t - e_full) <= removed + 1e-9
+
+
+def test_group_order_same_matrix():
+    """Ordering groups by flip mask only (instead of weight, then mask) changes the evaluation
+    order, not the matrix."""
+    ops, keys = c3_parts(40, 40)
+    tl = dyadic(ops)
+    sub = qsd.Subspace(keys, tl.n_qubits)
+    a = qsd.SubspaceHamiltonian(sub, qsd.operator_from_termlist(tl)).to_csr()
+    b = qsd.SubspaceHamiltonian(sub, qsd.operator_from_termlist(tl, order_by_mask=True)).to_csr()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
