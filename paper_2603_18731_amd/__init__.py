@@ -94,6 +94,11 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libqsd.so is missing: build it with `python -m paper_2603_18731_amd.build` "
                            "(no CPU fallback exists)")
+    # PyTorch's HIP runtime is loaded first so that the library binds to the same runtime (its
+    # streams and memory are the ones passed in); loading the library first would bring in a
+    # second runtime instance.
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(LIB_PATH)
     P, I32, I64, U32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
     PP = ctypes.POINTER(ctypes.c_void_p)
