@@ -58,21 +58,42 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// partial[j][b] = sum over rows of block b of V[j][i] * w[i], j = 0..k (k = *kdev); one wave
-// per basis vector at a time.
+// partial[j][b] = sum over the rows of chunk b of V[j][i] * w[i], j = 0..k (k = *kdev).
+// blockIdx.y selects kGemvJ basis vectors: each thread reads w[i] once and kGemvJ basis values,
+// so the basis streams at full occupancy; block sums by a fixed tree (deterministic).
+constexpr int kGemvJ = 8;
+
 __global__ __launch_bounds__(kRed) void k_gemv_t(const double *__restrict__ V, const double *__restrict__ w, int64_t N,
                                                  const int *__restrict__ kdev, int extra, double *__restrict__ part) {
+    __shared__ double red[kGemvJ][kRed / 64];
     const int cnt = *kdev + 1 + extra;
+    const int j0 = blockIdx.y * kGemvJ;
+    if (j0 >= cnt) return;
+    const int nj = min(kGemvJ, cnt - j0);
     const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
     const int64_t a = (int64_t)blockIdx.x * chunk;
     const int64_t b = min(N, a + chunk);
+    double acc[kGemvJ];
+#pragma unroll
+    for (int q = 0; q < kGemvJ; ++q) acc[q] = 0.0;
+    const double *v0 = V + (int64_t)j0 * N;
+    for (int64_t i = a + threadIdx.x; i < b; i += kRed) {
+        const double wi = w[i];
+#pragma unroll
+        for (int q = 0; q < kGemvJ; ++q)
+            if (q < nj) acc[q] += v0[(int64_t)q * N + i] * wi;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int j = wave; j < cnt; j += kRed / 64) {
-        const double *vj = V + (int64_t)j * N;
-        double s = 0.0;
-        for (int64_t i = a + lane; i < b; i += 64) s += vj[i] * w[i];
-        s = wave_sum(s);
-        if (lane == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = s;
+#pragma unroll
+    for (int q = 0; q < kGemvJ; ++q) {
+        const double s = wave_sum(acc[q]);
+        if (lane == 0) red[q][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < nj) {
+        double t = 0.0;
+        for (int q = 0; q < kRed / 64; ++q) t += red[threadIdx.x][q];
+        part[(int64_t)(j0 + threadIdx.x) * gridDim.x + blockIdx.x] = t;
     }
 }
 
@@ -291,7 +312,7 @@ int enqueue_iteration(const SpmvOp &op, LzState &S, bool f32, hipStream_t st) {
         QSD_TRY(op.matvec(1, S.x, 1, S.w, 1, QSD_F64, st));
     }
     for (int pass = 0; pass < 2; ++pass) {
-        k_gemv_t<<<kDotBlocks, kRed, 0, st>>>(S.V, S.w, N, S.kdev, 0, S.part);
+        k_gemv_t<<<dim3(kDotBlocks, (S.m + 1 + kGemvJ - 1) / kGemvJ), kRed, 0, st>>>(S.V, S.w, N, S.kdev, 0, S.part);
         k_reduce_parts<<<S.m + 1, kRed, 0, st>>>(S.part, kDotBlocks, S.kdev, 0, S.hv, S.alpha);
         k_gemv_n_sub<<<gridN(N), kRed, 0, st>>>(S.V, S.hv, N, S.kdev, S.w);
     }

@@ -76,21 +76,40 @@ __global__ __launch_bounds__(256) void kb_convert(const ReqDev *__restrict__ req
     }
 }
 
-// part[j][tile] = sum over the tile's rows of V[j][i] w[i], j = 0..k
+// part[j][tile] = sum over the tile's rows of V[j][i] w[i], j = 0..k; blockIdx.y selects
+// kBJ basis vectors (w read once per row for all of them), block sums by a fixed tree.
+constexpr int kBJ = 8;
+
 __global__ __launch_bounds__(256) void kb_gemv_t(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles) {
+    __shared__ double red[kBJ][4];
     const Tile t = tiles[blockIdx.x];
     const ReqDev &R = reqs[t.slot];
     if (*R.kdev >= R.m) return;
     const int cnt = *R.kdev + 1;
+    const int j0 = blockIdx.y * kBJ;
+    if (j0 >= cnt) return;  // uniform for the block
+    const int nj = min(kBJ, cnt - j0);
     const int64_t a = (int64_t)t.idx * kBT, b = min(R.N, a + kBT);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int j = wave; j < cnt; j += 4) {
-        const double *vj = R.V + (int64_t)j * R.N;
-        double s = 0.0;
-        for (int64_t i = a + lane; i < b; i += 64) s += vj[i] * R.w[i];
-        s = wsum(s);
-        if (lane == 0) R.part[(int64_t)j * R.nbt + t.idx] = s;
+    double acc[kBJ];
+#pragma unroll
+    for (int q = 0; q < kBJ; ++q) acc[q] = 0.0;
+    const double *v0 = R.V + (int64_t)j0 * R.N;
+    for (int64_t i = a + threadIdx.x; i < b; i += 256) {
+        const double wi = R.w[i];
+#pragma unroll
+        for (int q = 0; q < kBJ; ++q)
+            if (q < nj) acc[q] += v0[(int64_t)q * R.N + i] * wi;
     }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kBJ; ++q) {
+        const double s = wsum(acc[q]);
+        if (lane == 0) red[q][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < nj)
+        R.part[(int64_t)(j0 + threadIdx.x) * R.nbt + t.idx] =
+            (red[threadIdx.x][0] + red[threadIdx.x][1]) + (red[threadIdx.x][2] + red[threadIdx.x][3]);
 }
 
 // hv[j] = sum of part[j][*] in tile order; alpha[k] += hv[k].  One wave per j, four per block.
@@ -555,7 +574,7 @@ extern "C" int qsd_batch_step(qsd_batch *b, int32_t iterations, void *stream) {
         }
         if (b->f32) kb_convert<<<b->n_bl, 256, 0, st>>>(b->d_reqs, b->d_bl, 0);
         for (int pass = 0; pass < 2; ++pass) {
-            kb_gemv_t<<<b->n_bl, 256, 0, st>>>(b->d_reqs, b->d_bl);
+            kb_gemv_t<<<dim3(b->n_bl, (b->max_iter + kBJ) / kBJ), 256, 0, st>>>(b->d_reqs, b->d_bl);
             kb_reduce<<<dim3((b->max_iter + 4) / 4, ns), 256, 0, st>>>(b->d_reqs, ns);
             kb_gemv_n_sub<<<b->n_mv, kBlock, 0, st>>>(b->d_reqs, b->d_mv);
         }
