@@ -87,7 +87,15 @@ struct qsd_subspace {
     uint64_t *slots = nullptr;   // [C] (tag << 32) | index, empty = ~0
     uint32_t *bitmap = nullptr;  // [C / 32] slot occupancy
     uint64_t *ztab = nullptr;    // [Wp * 8][256] byte tabulation of the hash
+    bool exact = false;          // slots carry displacements (see device.h)
 };
+
+// Whether slots of a table with C slots may use the exact layout: one-word keys, indices below
+// 2^26, and the n qubit hash words, restricted to the bits that the home slot and the tag keep,
+// linearly independent over GF(2) (then the map key -> (home slot, tag) is injective).
+namespace qsd {
+bool exact_tags_ok(int n_qubits, int W, int64_t N, int64_t C);
+}
 
 struct Letter {
     int32_t q;

@@ -15,7 +15,39 @@ struct SubView {
     const uint32_t *__restrict__ bitmap;  // [C/32]
     int64_t N;
     uint32_t cmask;  // C - 1
+    uint32_t exact;  // slots carry the displacement: a tag match at the right displacement is the key
 };
+
+// Slot layout.  Default: tag (high 32 bits of the hash) | index (32 bits).  Exact mode (one-word
+// keys, N < 2^26, and the map key -> (home slot, tag) proven injective when the table is built):
+// tag | displacement from the home slot (6 bits, 63 = 63 or more) | index (26 bits).  Then a slot
+// whose tag and displacement match the probe's holds the probed string itself, and the key
+// compare is needed only for displacements of 63 or more.
+constexpr int kExactIdxBits = 26;
+constexpr uint32_t kExactIdxMask = (1u << kExactIdxBits) - 1u;
+
+__device__ __forceinline__ uint32_t slot_index(const SubView &s, uint64_t slot) {
+    return s.exact ? ((uint32_t)slot & kExactIdxMask) : (uint32_t)slot;
+}
+
+// Index of `col` if the occupied `slot` (tag already equal) holds it, probed at distance `dist`
+// from col's home slot; -1 otherwise.
+template <int Wp>
+__device__ __forceinline__ int64_t slot_match(const SubView &s, uint64_t slot, uint32_t dist,
+                                              const uint64_t (&col)[Wp]) {
+    if (s.exact) {
+        const uint32_t d = (uint32_t)(slot >> kExactIdxBits) & 63u;
+        const uint32_t r = (uint32_t)slot & kExactIdxMask;
+        if (d < 63u) return d == dist ? (int64_t)r : -1;
+        if (dist < 63u) return -1;
+        return s.keys[r] == col[0] ? (int64_t)r : -1;
+    }
+    const uint32_t r = (uint32_t)slot;
+    bool eq = true;
+#pragma unroll
+    for (int w = 0; w < Wp; ++w) eq &= (s.keys[(int64_t)w * s.N + r] == col[w]);
+    return eq ? (int64_t)r : -1;
+}
 
 // Hash probe: index of the string `col` (Wp words, known to hash to `h`) or -1.
 // Linear probing; the occupancy bit of each slot is tested before the slot is read, so a
@@ -25,34 +57,30 @@ template <int Wp>
 __device__ __forceinline__ int64_t probe(const SubView &s, uint64_t h, const uint64_t (&col)[Wp]) {
     uint32_t pos = (uint32_t)h & s.cmask;
     const uint32_t tag = (uint32_t)(h >> 32);
-    while (true) {
+    for (uint32_t dist = 0;; ++dist) {
         const uint32_t word = s.bitmap[pos >> 5];
         if (!((word >> (pos & 31)) & 1u)) return -1;
         const uint64_t slot = s.slots[pos];
         if ((uint32_t)(slot >> 32) == tag) {
-            const uint32_t r = (uint32_t)slot;
-            bool eq = true;
-#pragma unroll
-            for (int w = 0; w < Wp; ++w) eq &= (s.keys[(int64_t)w * s.N + r] == col[w]);
-            if (eq) return (int64_t)r;
+            const int64_t r = slot_match<Wp>(s, slot, dist, col);
+            if (r >= 0) return r;
         }
         pos = (pos + 1) & s.cmask;
     }
 }
 
-// Continues a probe at slot `pos` (known occupied or not) for a string with tag `tag`.
+// Continues a probe at slot `pos`, `dist` slots after the string's home slot (known occupied or
+// not), for a string with tag `tag`.
 template <int Wp>
-__device__ __forceinline__ int64_t probe_from(const SubView &s, uint32_t pos, uint32_t tag, const uint64_t (&col)[Wp]) {
-    while (true) {
+__device__ __forceinline__ int64_t probe_from(const SubView &s, uint32_t pos, uint32_t dist, uint32_t tag,
+                                              const uint64_t (&col)[Wp]) {
+    for (;; ++dist) {
         const uint32_t word = s.bitmap[pos >> 5];
         if (!((word >> (pos & 31)) & 1u)) return -1;
         const uint64_t slot = s.slots[pos];
         if ((uint32_t)(slot >> 32) == tag) {
-            const uint32_t r = (uint32_t)slot;
-            bool eq = true;
-#pragma unroll
-            for (int w = 0; w < Wp; ++w) eq &= (s.keys[(int64_t)w * s.N + r] == col[w]);
-            if (eq) return (int64_t)r;
+            const int64_t r = slot_match<Wp>(s, slot, dist, col);
+            if (r >= 0) return r;
         }
         pos = (pos + 1) & s.cmask;
     }

@@ -290,18 +290,12 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
 #pragma unroll
                 for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ lds.mask[c[b]][w];
                 int64_t j = -1;
-                if ((uint32_t)(slot[b] >> 32) == tag) {
-                    const uint32_t r = (uint32_t)slot[b];
-                    bool eq = true;
-#pragma unroll
-                    for (int w = 0; w < Wp; ++w) eq &= s.keys[(int64_t)w * s.N + r] == col[w];
-                    if (eq) j = r;
-                }
+                if ((uint32_t)(slot[b] >> 32) == tag) j = slot_match<Wp>(s, slot[b], 0u, col);
                 if (j < 0) {
-                    // first slot held another key: follow the run while slots stay occupied
+                    // the home slot held another string: follow the run while slots stay occupied
                     const uint32_t nxt = (pos[b] + 1) & s.cmask;
                     const uint32_t nw = ((nxt >> 5) == (pos[b] >> 5)) ? word[b] : s.bitmap[nxt >> 5];
-                    if ((nw >> (nxt & 31u)) & 1u) j = probe_from<Wp>(s, nxt, tag, col);
+                    if ((nw >> (nxt & 31u)) & 1u) j = probe_from<Wp>(s, nxt, 1u, tag, col);
                 }
                 if (j >= 0) {
                     const int cc = c[b];

@@ -12,7 +12,7 @@ inline HamView ham_view(const qsd_ham *h, bool f32) {
 }
 
 inline SubView sub_view(const qsd_subspace *s) {
-    return SubView{s->keys, s->hkey, s->slots, s->bitmap, s->N, (uint32_t)(s->C - 1)};
+    return SubView{s->keys, s->hkey, s->slots, s->bitmap, s->N, (uint32_t)(s->C - 1), s->exact ? 1u : 0u};
 }
 
 // Row tile of workgroup b out of G.  Workgroups are dispatched round-robin over the 8 XCDs, so

@@ -16,6 +16,26 @@
 
 namespace qsd {
 
+bool exact_tags_ok(int n_qubits, int W, int64_t N, int64_t C) {
+    if (W != 1 || N >= (1ll << 26) || n_qubits > 64) return false;
+    const uint64_t P = (uint64_t)(C - 1) | 0xFFFFFFFF00000000ull;  // home-slot bits and tag bits
+    uint64_t piv[64] = {0};  // piv[b]: the basis vector whose leading bit is b
+    for (int q = 0; q < n_qubits; ++q) {
+        uint64_t v = qubit_hash_value(q) & P;
+        int b = 63;
+        while (v) {
+            while (!((v >> b) & 1ull)) --b;  // leading bit of v
+            if (!piv[b]) {
+                piv[b] = v;
+                break;
+            }
+            v ^= piv[b];  // clears bit b and leaves only lower bits
+        }
+        if (!v) return false;  // reduced to zero: dependent on earlier qubits
+    }
+    return true;
+}
+
 uint64_t qubit_hash_value(int q) {
     // splitmix64 output for counter q (Steele, Lea, Flood 2014): fixed pseudo-random words
     uint64_t z = 0x243F6A8885A308D3ull + (uint64_t)(q + 1) * 0x9E3779B97F4A7C15ull;

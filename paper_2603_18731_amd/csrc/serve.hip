@@ -490,7 +490,7 @@ extern "C" int qsd_batch_add(qsd_batch *b, const qsd_ham *h, int32_t v0_mode, ui
     d.N = N;
     d.m = (int)std::min<int64_t>(b->max_iter, N);
     d.nbt = (int)((N + kBT - 1) / kBT);
-    d.s = SubView{h->s->keys, h->s->hkey, h->s->slots, h->s->bitmap, h->s->N, (uint32_t)(h->s->C - 1)};
+    d.s = sub_view(h->s);
     d.h = HamView{h->g_mask, h->g_hash, h->g_pos, h->g_scan, h->g_info, h->g_term0, h->g_nterm, h->g_iptr, h->t_cws,
                   b->f32 ? (const void *)h->t_coef32 : (const void *)h->t_coef, h->G};
     d.diag = h->diag;
@@ -705,7 +705,7 @@ extern "C" int qsd_matvec_batched(int32_t n, const qsd_ham *const *hams, const v
                 const qsd_ham *h = hams[i];
                 if (h->Wp != Wp || nvecs[i] <= c0 || h->N == 0) continue;
                 MvReq R{};
-                R.s = SubView{h->s->keys, h->s->hkey, h->s->slots, h->s->bitmap, h->s->N, (uint32_t)(h->s->C - 1)};
+                R.s = sub_view(h->s);
                 R.h = HamView{h->g_mask, h->g_hash, h->g_pos, h->g_scan, h->g_info, h->g_term0, h->g_nterm, h->g_iptr,
                               h->t_cws, f32 ? (const void *)h->t_coef32 : (const void *)h->t_coef, h->G};
                 R.dre = f32 ? (const void *)h->diag32 : (const void *)h->diag;

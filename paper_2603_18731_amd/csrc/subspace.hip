@@ -232,9 +232,11 @@ __global__ __launch_bounds__(kBlock) void k_hash_insert(SubView s, uint64_t *__r
     for (int w = 0; w < Wp; ++w) k[w] = s.keys[(int64_t)w * s.N + i];
     const uint64_t h = tab_hash<Wp>(k, ztab);
     hkey[i] = h;
-    const unsigned long long val = ((unsigned long long)(h >> 32) << 32) | (unsigned long long)(uint32_t)i;
+    const unsigned long long base = ((unsigned long long)(h >> 32) << 32) | (unsigned long long)(uint32_t)i;
     uint32_t pos = (uint32_t)h & s.cmask;
     for (uint32_t step = 0; step <= s.cmask; ++step) {
+        const unsigned long long val =
+            s.exact ? (base | ((unsigned long long)(step < 63u ? step : 63u) << kExactIdxBits)) : base;
         unsigned long long prev = atomicCAS((unsigned long long *)&slots[pos], ~0ull, val);
         if (prev == ~0ull) {
             atomicOr(&bitmap[pos >> 5], 1u << (pos & 31));
@@ -268,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_probe_len(SubView s, unsigned long l
         uint32_t pos = (uint32_t)h & s.cmask;
         while (true) {
             ++len;
-            if ((uint32_t)s.slots[pos] == (uint32_t)i) break;
+            if (slot_index(s, s.slots[pos]) == (uint32_t)i) break;
             pos = (pos + 1) & s.cmask;
         }
     }
@@ -386,6 +388,7 @@ int build_impl(qsd_subspace *sub, const uint64_t *d_bits, int64_t n_in, uint32_t
             break;
         }
         sub->C = C;
+        sub->exact = exact_tags_ok(sub->n_qubits, sub->W, N, C);
         std::vector<uint64_t> tab;
         hash_byte_tables(Wp, tab);
         if ((rc = dev_alloc(&sub->ztab, tab.size())) != QSD_OK) break;
@@ -398,7 +401,7 @@ int build_impl(qsd_subspace *sub, const uint64_t *d_bits, int64_t n_in, uint32_t
         }
         k_fill_u64<<<1024, kBlock, 0, st>>>(sub->slots, C, ~0ull);
         k_fill_u32<<<256, kBlock, 0, st>>>(sub->bitmap, C / 32, 0u);
-        SubView v{sub->keys, sub->hkey, sub->slots, sub->bitmap, N, (uint32_t)(C - 1)};
+        SubView v{sub->keys, sub->hkey, sub->slots, sub->bitmap, N, (uint32_t)(C - 1), sub->exact ? 1u : 0u};
         k_hash_insert<Wp><<<grid_for(N, kBlock), kBlock, 0, st>>>(v, sub->slots, sub->bitmap, sub->hkey, sub->ztab);
         if (hipStreamSynchronize(st) != hipSuccess) {
             rc = fail(QSD_ERR_HIP, "hash build failed: %s", hipGetErrorString(hipGetLastError()));
@@ -420,7 +423,7 @@ void free_sub(qsd_subspace *s) {
 }
 
 SubView view_of(const qsd_subspace *s) {
-    return SubView{s->keys, s->hkey, s->slots, s->bitmap, s->N, (uint32_t)(s->C - 1)};
+    return SubView{s->keys, s->hkey, s->slots, s->bitmap, s->N, (uint32_t)(s->C - 1), s->exact ? 1u : 0u};
 }
 
 }  // namespace
@@ -489,10 +492,11 @@ int rehash_impl(qsd_subspace *sub, int64_t C, hipStream_t st) {
     uint32_t *bitmap = nullptr;
     QSD_TRY(dev_alloc(&slots, C));
     int rc = dev_alloc(&bitmap, C / 32);
+    const bool exact = exact_tags_ok(sub->n_qubits, sub->W, sub->N, C);
     if (rc == QSD_OK) {
         k_fill_u64<<<1024, kBlock, 0, st>>>(slots, C, ~0ull);
         k_fill_u32<<<256, kBlock, 0, st>>>(bitmap, C / 32, 0u);
-        SubView v{sub->keys, sub->hkey, slots, bitmap, sub->N, (uint32_t)(C - 1)};
+        SubView v{sub->keys, sub->hkey, slots, bitmap, sub->N, (uint32_t)(C - 1), exact ? 1u : 0u};
         k_hash_insert<Wp><<<grid_for(sub->N, kBlock), kBlock, 0, st>>>(v, slots, bitmap, sub->hkey, sub->ztab);
         if (hipStreamSynchronize(st) != hipSuccess)
             rc = fail(QSD_ERR_HIP, "hash rebuild failed: %s", hipGetErrorString(hipGetLastError()));
@@ -507,6 +511,7 @@ int rehash_impl(qsd_subspace *sub, int64_t C, hipStream_t st) {
     sub->slots = slots;
     sub->bitmap = bitmap;
     sub->C = C;
+    sub->exact = exact;
     return QSD_OK;
 }
 
