@@ -163,9 +163,14 @@ def serve_bench(args):
                "fermi16": wl.molecular_terms(h, eri)}
     ops = {k: qsd.operator_from_termlist(v) for k, v in fam_ops.items()}
     hams = []
+    nnzs = []
+    csr_min = (1 << 15) if args.serve_csr else None
     for i, (fam, size, sub_seed) in enumerate(specs):
         keys = wl.serving_subspace(fam, size, sub_seed)
-        hams.append(qsd.SubspaceHamiltonian(qsd.Subspace(keys, fam_ops[fam].n_qubits), ops[fam]))
+        H = qsd.SubspaceHamiltonian(qsd.Subspace(keys, fam_ops[fam].n_qubits), ops[fam])
+        hams.append(H)
+        # stored-matrix size, for the CSR memory budget (a pass over the rows at setup)
+        nnzs.append(H.N + H.work_counts()[1] if csr_min is not None and H.N >= csr_min else 0)
         if (i + 1) % 32 == 0:
             print("# built %d/%d request operators (%.0f s)" % (i + 1, len(specs), time.perf_counter() - t_setup),
                   file=sys.stderr, flush=True)
@@ -196,8 +201,8 @@ def serve_bench(args):
     budget = int(0.85 * free)
 
     def run(arrivals, label):
-        srv = serve.Server(budget, max_iter=max_iter, spmv_dtype=args.dtype)
-        reqs = [serve.Request(i, hams[i], arrival=float(arrivals[i]), tol=tol) for i in range(n)]
+        srv = serve.Server(budget, max_iter=max_iter, spmv_dtype=args.dtype, csr_min_rows=csr_min)
+        reqs = [serve.Request(i, hams[i], arrival=float(arrivals[i]), tol=tol, nnz=nnzs[i]) for i in range(n)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         done = srv.run(reqs, progress=lambda k: k % 32 == 0 and print(
@@ -209,7 +214,7 @@ def serve_bench(args):
         res = dict(serve.percentiles(lat), solves_per_s=n / span, makespan_s=span,
                    converged=int(sum(r.status == 2 for r in done)),
                    energy_max_rel_err_vs_fp64=float(err.max()), peak_hbm_gb=srv.peak_used / 1e9,
-                   peak_active=srv.peak_active)
+                   peak_active=srv.peak_active, csr_requests=int(sum(r.used_csr for r in done)))
         print("# %s: %s" % (label, json.dumps(res)), file=sys.stderr, flush=True)
         return res
 
@@ -235,7 +240,8 @@ def serve_bench(args):
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": "serve_%d_requests_1e3_%.0e" % (n, args.serve_smax), "rows_total": int(sizes.sum()),
+        "config": {"workload": "serve_%d_requests_1e3_%.0e%s" % (n, args.serve_smax, "_csr" if csr_min else ""),
+                   "rows_total": int(sizes.sum()), "csr_min_rows": csr_min,
                    "tol": tol, "max_iter": max_iter, "hbm_budget_gb": budget / 1e9},
         "serve": {"closed_loop": closed, **out_open},
         "fifo_fp64_single_vector": {"solves_per_s": mu_fifo, "service_s_total": float(service.sum()),
@@ -390,6 +396,8 @@ def main():
                     "Poisson arrivals against the FIFO single-vector solver")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-smax", type=float, default=2e6)
+    ap.add_argument("--serve-csr", action="store_true", help="serve requests of >= 2^15 rows from stored CSR "
+                    "matrices built at admission")
     args = ap.parse_args()
     if args.ramps:
         if args.gpus != 1:

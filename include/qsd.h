@@ -443,6 +443,11 @@ int qsd_ramps(const qsd_ham *h, const int64_t *s0, int64_t n0, double E, double 
  *                      the same key width.  Errors: CAPACITY (no free slot), OUT_OF_MEMORY,
  *                      UNSUPPORTED (complex operator or other key width), INVALID_ARG (empty
  *                      subspace, short or misaligned workspace).  Synchronizes `stream`.
+ * qsd_batch_add_csr    the same for a stored CSR operator (int32 columns, dtype = the batch's
+ *                      SpMV dtype): its rows are evaluated from the matrix by the same lanes-per-row
+ *                      reduction as qsd_csr_matvec, inside the same batched launch; requests of
+ *                      both kinds and any key width mix freely.  The matrix must outlive the request.
+ * qsd_batch_footprint_rows  workspace bytes for a request of N rows.
  * qsd_batch_step       `iterations` iterations for every active request (requests at their
  *                      limit idle).  Enqueued on `stream`.
  * qsd_batch_poll       solves every active request's tridiagonal problem and reports, per
@@ -457,6 +462,9 @@ int qsd_batch_create(int32_t max_requests, int32_t max_iter, int32_t spmv_dtype,
 int qsd_batch_footprint(const qsd_ham *h, int32_t max_iter, int32_t spmv_dtype, int64_t *bytes);
 int qsd_batch_add(qsd_batch *b, const qsd_ham *h, int32_t v0_mode, uint64_t seed, double tol, void *workspace,
                   int64_t workspace_bytes, int32_t *slot_out, void *stream);
+int qsd_batch_add_csr(qsd_batch *b, const qsd_csr *c, int32_t v0_mode, uint64_t seed, double tol, void *workspace,
+                      int64_t workspace_bytes, int32_t *slot_out, void *stream);
+int qsd_batch_footprint_rows(int64_t N, int32_t max_iter, int32_t spmv_dtype, int64_t *bytes);
 int qsd_batch_step(qsd_batch *b, int32_t iterations, void *stream);
 int qsd_batch_poll(qsd_batch *b, int32_t *status, double *energy, int32_t *iterations, double *ritz_residual,
                    void *stream);

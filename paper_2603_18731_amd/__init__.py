@@ -43,7 +43,7 @@ EXPORTED = [
     "qsd_ham_set_schedule", "qsd_ham_get_schedule", "qsd_ham_autotune", "qsd_subspace_rehash",
     "qsd_csr_create", "qsd_csr_info", "qsd_csr_export", "qsd_csr_matvec", "qsd_csr_lanczos", "qsd_csr_block_lanczos",
     "qsd_csr_destroy", "qsd_subspace_select", "qsd_ramps",
-    "qsd_ham_diag_splitting",
+    "qsd_ham_diag_splitting", "qsd_batch_add_csr", "qsd_batch_footprint_rows",
 ]
 
 
@@ -148,6 +148,8 @@ def lib():
         "qsd_block_lanczos": ([P, I32, ctypes.POINTER(LanczosOpts), P, P, ctypes.POINTER(LanczosInfo), P],
                               ctypes.c_int),
         "qsd_batch_step": ([P, I32, P], ctypes.c_int),
+        "qsd_batch_add_csr": ([P, P, I32, ctypes.c_uint64, D, P, I64, P, P], ctypes.c_int),
+        "qsd_batch_footprint_rows": ([I64, I32, I32, P], ctypes.c_int),
         "qsd_batch_poll": ([P, P, P, P, P, P], ctypes.c_int),
         "qsd_batch_remove": ([P, I32], ctypes.c_int),
         "qsd_batch_destroy": ([P], ctypes.c_int),
@@ -626,9 +628,10 @@ class LanczosBatch:
         self._h = h
         self._hams = {}
 
-    def footprint(self, ham: "SubspaceHamiltonian") -> int:
+    def footprint(self, ham) -> int:
+        """Workspace bytes of a request on ``ham`` (a SubspaceHamiltonian or a CsrMatrix)."""
         b = ctypes.c_int64()
-        _check(lib().qsd_batch_footprint(ham.handle, self.max_iter, self.dtype, ctypes.byref(b)))
+        _check(lib().qsd_batch_footprint_rows(int(ham.N), self.max_iter, self.dtype, ctypes.byref(b)))
         return b.value
 
     def add(self, ham: "SubspaceHamiltonian", v0: str = "uniform", seed: int = 0, tol: float = 1e-10,
@@ -638,8 +641,8 @@ class LanczosBatch:
         mode = {"uniform": V0_UNIFORM, "min_diag": V0_MIN_DIAG, "random": V0_RANDOM}[v0]
         slot = ctypes.c_int32()
         nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
-        _check(lib().qsd_batch_add(self._h, ham.handle, mode, seed, tol, _ptr(workspace), nbytes, ctypes.byref(slot),
-                                   _stream(stream)))
+        add = lib().qsd_batch_add_csr if isinstance(ham, CsrMatrix) else lib().qsd_batch_add
+        _check(add(self._h, ham.handle, mode, seed, tol, _ptr(workspace), nbytes, ctypes.byref(slot), _stream(stream)))
         self._hams[slot.value] = (ham, workspace)  # both stay alive while the request runs
         return slot.value
 

@@ -35,6 +35,11 @@ struct ReqDev {
     double *tri;  // [m+4]
     int m;
     int nbt;
+    // stored CSR operator (int32 columns) instead of the row engine, when cptr is set
+    const int64_t *cptr;
+    const int32_t *cidx;
+    const void *cval;
+    int lpr;
 };
 
 struct Tile {
@@ -58,6 +63,24 @@ __global__ __launch_bounds__(kBlock) void kb_matvec(const ReqDev *__restrict__ r
     const ET *dre = f32 ? (const ET *)R.diag32 : (const ET *)R.diag;
     const ET *x = f32 ? (const ET *)R.x32 : (const ET *)R.x;
     ET *y = f32 ? (ET *)R.w32 : (ET *)R.w;
+    if (R.cptr) {
+        // stored CSR: groups of lpr consecutive lanes take the tile's rows in turn; entries are
+        // strided over a group's lanes and summed by the same shuffle tree as qsd_csr_matvec
+        const int lpr = R.lpr;
+        const int sub = threadIdx.x & (lpr - 1);
+        const int64_t row0 = (int64_t)t.idx * kBlock, rend = min(R.N, row0 + kBlock);
+        const ET *val = (const ET *)R.cval;
+        for (int64_t r = row0 + threadIdx.x / lpr; r < row0 + kBlock; r += kBlock / lpr) {
+            double acc = 0.0;
+            if (r < rend) {
+                const int64_t a = R.cptr[r], b = R.cptr[r + 1];
+                for (int64_t e = a + sub; e < b; e += lpr) acc += (double)val[e] * (double)x[R.cidx[e]];
+            }
+            for (int d = lpr / 2; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+            if (sub == 0 && r < rend) y[r] = (ET)acc;
+        }
+        return;
+    }
     matvec_block<Wp, 1, ET, false>(R.s, R.h, dre, nullptr, x, 1, y, 1, 1, (int64_t)t.idx * kBlock, lds);
 }
 
@@ -455,6 +478,14 @@ extern "C" int qsd_batch_create(int32_t max_requests, int32_t max_iter, int32_t 
     return QSD_OK;
 }
 
+extern "C" int qsd_batch_footprint_rows(int64_t N, int32_t max_iter, int32_t spmv_dtype, int64_t *bytes) {
+    clear_error();
+    if (!bytes || N < 1) return fail(QSD_ERR_INVALID_ARG, "bad arguments");
+    if (max_iter < 2 || max_iter > 1000) return fail(QSD_ERR_INVALID_ARG, "max_iter must be in [2, 1000]");
+    *bytes = layout_of(N, (int)std::min<int64_t>(max_iter, N), spmv_dtype == QSD_F32).total;
+    return QSD_OK;
+}
+
 extern "C" int qsd_batch_footprint(const qsd_ham *h, int32_t max_iter, int32_t spmv_dtype, int64_t *bytes) {
     clear_error();
     if (!h || !bytes) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
@@ -463,18 +494,26 @@ extern "C" int qsd_batch_footprint(const qsd_ham *h, int32_t max_iter, int32_t s
     return QSD_OK;
 }
 
-extern "C" int qsd_batch_add(qsd_batch *b, const qsd_ham *h, int32_t v0_mode, uint64_t seed, double tol,
-                             void *workspace, int64_t workspace_bytes, int32_t *slot_out, void *stream) {
-    clear_error();
-    if (!b || !h || !slot_out) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
-    if (h->is_complex) return fail(QSD_ERR_UNSUPPORTED, "batched Lanczos is real only");
+namespace {
+
+int add_impl(qsd_batch *b, const qsd_ham *h, const qsd_csr *c, int32_t v0_mode, uint64_t seed, double tol,
+             void *workspace, int64_t workspace_bytes, int32_t *slot_out, void *stream) {
+    if (!b || (!h && !c) || !slot_out) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+    if (h ? h->is_complex : c->cplx) return fail(QSD_ERR_UNSUPPORTED, "batched Lanczos is real only");
+    if (c && c->index_type != QSD_INDEX_I32) return fail(QSD_ERR_UNSUPPORTED, "serving needs int32 CSR columns");
+    if (c && c->dtype != (b->f32 ? QSD_F32 : QSD_F64))
+        return fail(QSD_ERR_DTYPE, "the stored matrix must have the batch's SpMV dtype");
     if (v0_mode != QSD_V0_UNIFORM && v0_mode != QSD_V0_MIN_DIAG && v0_mode != QSD_V0_RANDOM)
         return fail(QSD_ERR_INVALID_ARG, "v0_mode must be UNIFORM, MIN_DIAG or RANDOM");
     if (!(tol > 0)) return fail(QSD_ERR_INVALID_ARG, "tol must be > 0");
-    if (h->N < 1) return fail(QSD_ERR_INVALID_ARG, "empty subspace");
-    bool any = false;
-    for (auto &S : b->slots) any |= S.used;
-    if (any && h->Wp != b->Wp) return fail(QSD_ERR_UNSUPPORTED, "all requests of a batch must have the same key width");
+    const int64_t N = h ? h->N : c->N;
+    if (N < 1) return fail(QSD_ERR_INVALID_ARG, "empty subspace");
+    if (h) {
+        bool any = false;
+        for (auto &S : b->slots) any |= S.used && S.h;
+        if (any && h->Wp != b->Wp)
+            return fail(QSD_ERR_UNSUPPORTED, "all matrix-free requests of a batch must have the same key width");
+    }
     int slot = -1;
     for (int i = 0; i < b->max_slots; ++i)
         if (!b->slots[i].used) {
@@ -486,15 +525,21 @@ extern "C" int qsd_batch_add(qsd_batch *b, const qsd_ham *h, int32_t v0_mode, ui
     auto &S = b->slots[slot];
     S = qsd_batch::Slot();
     ReqDev &d = S.d;
-    const int64_t N = h->N;
     d.N = N;
     d.m = (int)std::min<int64_t>(b->max_iter, N);
     d.nbt = (int)((N + kBT - 1) / kBT);
-    d.s = sub_view(h->s);
-    d.h = HamView{h->g_mask, h->g_hash, h->g_pos, h->g_scan, h->g_info, h->g_term0, h->g_nterm, h->g_iptr, h->t_cws,
-                  b->f32 ? (const void *)h->t_coef32 : (const void *)h->t_coef, h->G};
-    d.diag = h->diag;
-    d.diag32 = h->diag32;
+    if (h) {
+        d.s = sub_view(h->s);
+        d.h = ham_view(h, b->f32);
+        d.diag = h->diag;
+        d.diag32 = h->diag32;
+    } else {
+        d.diag = c->diag;
+        d.cptr = c->indptr;
+        d.cidx = (const int32_t *)c->indices;
+        d.cval = c->data;
+        d.lpr = c->lpr;
+    }
     const Layout L = layout_of(N, d.m, b->f32);
     int rc = QSD_OK;
     if (workspace) {
@@ -528,7 +573,7 @@ extern "C" int qsd_batch_add(qsd_batch *b, const qsd_ham *h, int32_t v0_mode, ui
     S.used = true;
     S.h = h;
     S.tol = tol;
-    b->Wp = h->Wp;
+    if (h) b->Wp = h->Wp;
     b->dirty = true;
     if ((rc = sync_tables(b, st)) != QSD_OK) {
         free_slot(S);
@@ -537,7 +582,7 @@ extern "C" int qsd_batch_add(qsd_batch *b, const qsd_ham *h, int32_t v0_mode, ui
     }
     int64_t spike = 0;
     if (v0_mode == QSD_V0_MIN_DIAG) {
-        kb_argmin<<<1, 256, 0, st>>>(h->diag, N, b->d_spike);
+        kb_argmin<<<1, 256, 0, st>>>(d.diag, N, b->d_spike);
         if (hipMemcpyAsync(&spike, b->d_spike, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             rc = fail(QSD_ERR_HIP, "argmin failed");
@@ -556,6 +601,22 @@ extern "C" int qsd_batch_add(qsd_batch *b, const qsd_ham *h, int32_t v0_mode, ui
     return QSD_OK;
 }
 
+}  // namespace
+
+extern "C" int qsd_batch_add(qsd_batch *b, const qsd_ham *h, int32_t v0_mode, uint64_t seed, double tol,
+                             void *workspace, int64_t workspace_bytes, int32_t *slot_out, void *stream) {
+    clear_error();
+    if (!h) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+    return add_impl(b, h, nullptr, v0_mode, seed, tol, workspace, workspace_bytes, slot_out, stream);
+}
+
+extern "C" int qsd_batch_add_csr(qsd_batch *b, const qsd_csr *c, int32_t v0_mode, uint64_t seed, double tol,
+                                 void *workspace, int64_t workspace_bytes, int32_t *slot_out, void *stream) {
+    clear_error();
+    if (!c) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
+    return add_impl(b, nullptr, c, v0_mode, seed, tol, workspace, workspace_bytes, slot_out, stream);
+}
+
 extern "C" int qsd_batch_step(qsd_batch *b, int32_t iterations, void *stream) {
     clear_error();
     if (!b || iterations < 0) return fail(QSD_ERR_INVALID_ARG, "bad arguments");
@@ -571,6 +632,7 @@ extern "C" int qsd_batch_step(qsd_batch *b, int32_t iterations, void *stream) {
             case 4: launch_bmv<4>(b, st); break;
             case 8: launch_bmv<8>(b, st); break;
             case 16: launch_bmv<16>(b, st); break;
+            default: launch_bmv<1>(b, st); break;  // stored-CSR requests only
         }
         if (b->f32) kb_convert<<<b->n_bl, 256, 0, st>>>(b->d_reqs, b->d_bl, 0);
         for (int pass = 0; pass < 2; ++pass) {

@@ -11,6 +11,11 @@ request finishes.
 
 The host loop never blocks on a running lane: each lane's steps end with an event, and a lane
 is polled (convergence test, retire, admit) only once its event has completed.
+
+Optionally (``csr_min_rows``) a request of at least that many rows whose stored-matrix size is
+known (``Request.nnz``) is served from its CSR matrix, built when it is admitted (lower
+triangle, mirrored) and freed when it finishes: the matrix and the build's transient scratch
+count against the HBM budget, and its SpMV then streams the matrix instead of re-evaluating it.
 """
 import math
 import time
@@ -19,7 +24,7 @@ from typing import List, Optional
 
 import numpy as np
 
-from . import LanczosBatch, SubspaceHamiltonian
+from . import INDEX_I32, CsrMatrix, LanczosBatch, SubspaceHamiltonian
 
 
 @dataclass
@@ -38,6 +43,9 @@ class Request:
     status: int = 0  # 2 converged, 3 iteration limit
     footprint: int = 0
     lane: int = -1
+    nnz: int = 0  # stored entries of H on the subspace, when known (enables CSR serving)
+    csr: Optional[object] = None
+    used_csr: bool = False
 
     @property
     def latency(self) -> float:
@@ -58,11 +66,18 @@ class Server:
     ``lane_bounds`` are the subspace-size boundaries between lanes; ``steps_per_poll`` Lanczos
     iterations are enqueued per lane between two convergence checks."""
 
+    # bytes per stored entry while the lower-triangle build runs (int64 column + value pair
+    # scratch, plus the int32 column and value of the result)
+    BUILD_BYTES_PER_NNZ = 8 + 16 + 4 + 8
+
     def __init__(self, hbm_budget: int, max_iter: int = 300, spmv_dtype: str = "f64",
-                 lane_bounds=(1 << 15, 1 << 18), lane_slots=(128, 16, 2), steps_per_poll: int = 4):
+                 lane_bounds=(1 << 15, 1 << 18), lane_slots=(128, 16, 2), steps_per_poll: int = 4,
+                 csr_min_rows: Optional[int] = None):
         import torch
 
         self.budget = int(hbm_budget)
+        self.spmv_dtype = spmv_dtype
+        self.csr_min_rows = csr_min_rows
         self.max_iter = max_iter
         self.steps_per_poll = steps_per_poll
         self.bounds = tuple(lane_bounds)
@@ -81,15 +96,30 @@ class Server:
     def footprint(self, req: Request) -> int:
         return self.lanes[self.lane_of(req)].batch.footprint(req.ham)
 
+    def _wants_csr(self, req: Request) -> bool:
+        return (self.csr_min_rows is not None and req.nnz > 0 and req.ham.N >= self.csr_min_rows
+                and not req.ham.is_complex)
+
     def _admit(self, lane: _Lane, li: int, req: Request, now: float) -> bool:
         import torch
 
         fp = lane.batch.footprint(req.ham)
-        if self.used + fp > self.budget or len(lane.active) >= lane.batch.max_requests:
+        if len(lane.active) >= lane.batch.max_requests:
             return False
+        use_csr = self._wants_csr(req)
+        need = fp + (self.BUILD_BYTES_PER_NNZ * req.nnz + 8 * (req.ham.N + 1) if use_csr else 0)
+        if self.used + need > self.budget:
+            return False
+        op = req.ham
+        if use_csr:
+            dt = torch.float32 if self.spmv_dtype == "f32" else torch.float64
+            req.csr = CsrMatrix(req.ham, INDEX_I32, dtype=dt, lower_mirror=True, stream=lane.stream)
+            fp += req.csr.bytes
+            op = req.csr
+            req.used_csr = True
         with torch.cuda.stream(lane.stream):
-            ws = torch.empty(fp, dtype=torch.uint8, device="cuda")
-        slot = lane.batch.add(req.ham, v0=req.v0, seed=req.seed, tol=req.tol, workspace=ws, stream=lane.stream)
+            ws = torch.empty(lane.batch.footprint(req.ham), dtype=torch.uint8, device="cuda")
+        slot = lane.batch.add(op, v0=req.v0, seed=req.seed, tol=req.tol, workspace=ws, stream=lane.stream)
         req.admitted, req.footprint, req.lane = now, fp, li
         lane.active[slot] = req
         self.used += fp
@@ -104,6 +134,8 @@ class Server:
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         for r in pending:
             fp = self.footprint(r)
+            if self._wants_csr(r):
+                fp += self.BUILD_BYTES_PER_NNZ * r.nnz + 8 * (r.ham.N + 1)
             if fp > self.budget:
                 raise ValueError("request %d needs %d bytes, more than the budget" % (r.rid, fp))
         waiting: List[Request] = []
@@ -128,6 +160,7 @@ class Server:
                             r = lane.active.pop(slot)
                             r.finished, r.energy, r.iterations, r.status = now, float(en[slot]), int(it[slot]), int(st[slot])
                             lane.batch.remove(slot)
+                            r.csr = None  # the stored matrix is released with the request
                             self.used -= r.footprint
                             done.append(r)
                             progressed = True

@@ -213,3 +213,63 @@ def test_server_admission(hams):
         assert r.status == 2
         assert r.finished >= r.admitted >= r.arrival
         assert abs(r.energy - singles[names[r.rid]]) / abs(singles[names[r.rid]]) < 1e-10
+
+
+def test_batch_csr_requests(hams, oracle_energies):
+    """Stored-CSR requests in the same batch as matrix-free ones: energies within 1e-10 of the
+    oracle, and a CSR request's results are bitwise the same alone and in the mix."""
+    A3 = qsd.CsrMatrix(hams["fermi1600"], lower_mirror=True)
+    A1 = qsd.CsrMatrix(hams["tfim12"])
+    b = qsd.LanczosBatch(8, max_iter=300)
+    slots = {"fermi1600": b.add(A3, tol=1e-10), "xxz20k": b.add(hams["xxz20k"], tol=1e-10),
+             "tfim12": b.add(A1, tol=1e-10)}
+    st, e, it, rr = _run_to_end(b)
+    for name, s in slots.items():
+        assert st[s] == 2, (name, st[s])
+        e_o = oracle_energies[name]
+        say("csr batch", name, e[s], e_o, it[s])
+        assert abs(e[s] - e_o) / abs(e_o) < 1e-10
+    alone = qsd.LanczosBatch(4, max_iter=200)
+    sa = alone.add(A3, v0="random", seed=4)
+    alone.step(25)
+    ra = alone.poll()
+    mix = qsd.LanczosBatch(4, max_iter=200)
+    mix.add(hams["xxz20k"])
+    mix.add(A1)
+    sm = mix.add(A3, v0="random", seed=4)
+    mix.step(25)
+    rm = mix.poll()
+    assert ra[1][sa] == rm[1][sm] and ra[3][sa] == rm[3][sm] and ra[2][sa] == rm[2][sm] == 25
+
+
+def test_batch_csr_f32_and_errors(hams, oracle_energies):
+    A32 = qsd.CsrMatrix(hams["xxz20k"], dtype=torch.float32)
+    b = qsd.LanczosBatch(2, max_iter=300, spmv_dtype="f32")
+    s = b.add(A32, tol=1e-7, v0="min_diag")
+    st, e, it, rr = _run_to_end(b)
+    err = abs(e[s] - oracle_energies["xxz20k"]) / abs(oracle_energies["xxz20k"])
+    assert st[s] == 2 and err < 1e-5
+    b64 = qsd.LanczosBatch(2, max_iter=50)
+    with pytest.raises(qsd.QsdError, match="DTYPE"):
+        b64.add(A32)
+    with pytest.raises(qsd.QsdError, match="UNSUPPORTED"):
+        b64.add(qsd.CsrMatrix(hams["xxz20k"], qsd.INDEX_I64))
+
+
+def test_server_csr_mode(hams):
+    from paper_2603_18731_amd import serve
+
+    names = ["fermi1600", "xxz20k", "tfim12", "fermi1600", "xxz3k"]
+    reqs = []
+    for i, n in enumerate(names):
+        p, hcount = hams[n].work_counts()
+        reqs.append(serve.Request(i, hams[n], arrival=0.001 * i, nnz=hams[n].N + hcount))
+    srv = serve.Server(hbm_budget=4 << 30, max_iter=300, lane_bounds=(2000,), lane_slots=(4, 4), csr_min_rows=3500)
+    done = srv.run(reqs)
+    singles = {n: hams[n].lanczos(tol=1e-10)[0] for n in set(names)}
+    for r in done:
+        n = names[r.rid]
+        assert r.status == 2
+        assert r.used_csr == (hams[n].N >= 3500)
+        assert abs(r.energy - singles[n]) / abs(singles[n]) < 1e-10
+    assert srv.used == 0 and srv.peak_used <= 4 << 30
