@@ -326,6 +326,8 @@ void qsd_lanczos_default_opts(qsd_lanczos_opts *opts);
  *   eval_out  host, receives theta.
  *   d_evec    device [N] (FP64, or complex FP64 for a complex H): Ritz vector if want_vector,
  *             start vector if v0_mode == QSD_V0_USER; may be NULL otherwise.
+ *   A complex Hermitian H runs the same recurrence on interleaved complex vectors (projections
+ *   conj(v)^T w, alpha the real part); spmv_dtype F64 / F32 then means C128 / C64 SpMV.
  *   info      host, may be NULL.
  * Synchronizes.  Returns NOT_CONVERGED (with outputs filled) if max_iter is reached.
  * The basis needs (max_iter + 1) * N * 8 bytes (x2 for complex) of device memory.

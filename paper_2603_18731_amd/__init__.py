@@ -475,7 +475,8 @@ class SubspaceHamiltonian:
 
         ``block`` 4 or 8 runs block Lanczos (``max_iter`` then counts block steps)."""
         return _lanczos(lib().qsd_lanczos, lib().qsd_block_lanczos, self._h, self.N, max_iter, tol, v0, seed,
-                        spmv_dtype, check_every, want_vector, use_graph, v0_vector, stream, raise_on_nonconv, block)
+                        spmv_dtype, check_every, want_vector, use_graph, v0_vector, stream, raise_on_nonconv, block,
+                        self.is_complex)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -494,7 +495,7 @@ def trimmed_hamiltonian(ham: "SubspaceHamiltonian", tl, tol: float, stream=None)
 
 
 def _lanczos(single, blockfn, handle, N, max_iter, tol, v0, seed, spmv_dtype, check_every, want_vector, use_graph,
-             v0_vector, stream, raise_on_nonconv, block):
+             v0_vector, stream, raise_on_nonconv, block, is_complex=False):
     import torch
 
     o = LanczosOpts()
@@ -505,7 +506,7 @@ def _lanczos(single, blockfn, handle, N, max_iter, tol, v0, seed, spmv_dtype, ch
     o.want_vector, o.use_graph = int(want_vector), int(use_graph)
     vec = None
     if want_vector or v0 == "user":
-        vec = torch.empty(N, dtype=torch.float64, device="cuda")
+        vec = torch.empty(N, dtype=torch.complex128 if is_complex else torch.float64, device="cuda")
         if v0 == "user":
             vec.copy_(v0_vector)
     e = ctypes.c_double()
@@ -573,9 +574,10 @@ class CsrMatrix:
         import torch
 
         if spmv_dtype is None:
-            spmv_dtype = "f32" if self.dtype == torch.float32 else "f64"
+            spmv_dtype = "f32" if self.dtype in (torch.float32, torch.complex64) else "f64"
         return _lanczos(lib().qsd_csr_lanczos, lib().qsd_csr_block_lanczos, self._h, self.N, max_iter, tol, v0, seed,
-                        spmv_dtype, check_every, want_vector, use_graph, v0_vector, stream, raise_on_nonconv, block)
+                        spmv_dtype, check_every, want_vector, use_graph, v0_vector, stream, raise_on_nonconv, block,
+                        self.is_complex)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -24,7 +24,9 @@ constexpr int kRed = 256;       // threads of reduction kernels
 constexpr int kDotBlocks = 512; // partial-sum blocks (fixed => deterministic sums)
 
 struct LzState {
-    int64_t N = 0;
+    int64_t N = 0;           // rows
+    int64_t NR = 0;          // doubles per vector: N (real) or 2N (complex, interleaved)
+    bool cplx = false;
     int m = 0;               // max iterations
     double *V = nullptr;     // [m+1][N]
     double *x = nullptr;     // [N] current basis vector
@@ -97,24 +99,102 @@ __global__ __launch_bounds__(kRed) void k_gemv_t(const double *__restrict__ V, c
     }
 }
 
+// Complex (Hermitian) variant: part[j][b] and part[P + j][b] (P = plane stride) are the real
+// and imaginary parts of sum over chunk b of conj(V[j][i]) w[i], vectors interleaved (re, im).
+__global__ __launch_bounds__(kRed) void k_gemv_t_c(const double2 *__restrict__ V, const double2 *__restrict__ w,
+                                                   int64_t N, const int *__restrict__ kdev, int64_t plane,
+                                                   double *__restrict__ part) {
+    __shared__ double red[2 * kGemvJ][kRed / 64];
+    const int cnt = *kdev + 1;
+    const int j0 = blockIdx.y * kGemvJ;
+    if (j0 >= cnt) return;
+    const int nj = min(kGemvJ, cnt - j0);
+    const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
+    const int64_t a = (int64_t)blockIdx.x * chunk;
+    const int64_t b = min(N, a + chunk);
+    double are[kGemvJ], aim[kGemvJ];
+#pragma unroll
+    for (int q = 0; q < kGemvJ; ++q) are[q] = aim[q] = 0.0;
+    const double2 *v0 = V + (int64_t)j0 * N;
+    for (int64_t i = a + threadIdx.x; i < b; i += kRed) {
+        const double2 wi = w[i];
+#pragma unroll
+        for (int q = 0; q < kGemvJ; ++q)
+            if (q < nj) {
+                const double2 v = v0[(int64_t)q * N + i];
+                are[q] += v.x * wi.x + v.y * wi.y;
+                aim[q] += v.x * wi.y - v.y * wi.x;
+            }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kGemvJ; ++q) {
+        const double sr = wave_sum(are[q]), si = wave_sum(aim[q]);
+        if (lane == 0) {
+            red[2 * q][wave] = sr;
+            red[2 * q + 1][wave] = si;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * nj) {
+        double t = 0.0;
+        for (int q = 0; q < kRed / 64; ++q) t += red[threadIdx.x][q];
+        const int jj = threadIdx.x >> 1;
+        part[(threadIdx.x & 1) * plane + (int64_t)(j0 + jj) * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// w[i] -= sum_{j<=k} V[j][i] h[j] for complex vectors and coefficients (h interleaved)
+__global__ __launch_bounds__(kRed) void k_gemv_n_sub_c(const double2 *__restrict__ V, const double *__restrict__ hv,
+                                                       int64_t N, const int *__restrict__ kdev,
+                                                       double2 *__restrict__ w) {
+    __shared__ double sh[2 * 512];
+    const int cnt = *kdev + 1;
+    const int64_t i = (int64_t)blockIdx.x * kRed + threadIdx.x;
+    double ar = 0.0, ai = 0.0;
+    for (int j0 = 0; j0 < cnt; j0 += 512) {
+        const int nj = min(512, cnt - j0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < 2 * nj; q += kRed) sh[q] = hv[2 * j0 + q];
+        __syncthreads();
+        if (i < N)
+            for (int q = 0; q < nj; ++q) {
+                const double2 v = V[(int64_t)(j0 + q) * N + i];
+                const double hr = sh[2 * q], hi = sh[2 * q + 1];
+                ar += v.x * hr - v.y * hi;
+                ai += v.x * hi + v.y * hr;
+            }
+    }
+    if (i < N) {
+        double2 t = w[i];
+        t.x -= ar;
+        t.y -= ai;
+        w[i] = t;
+    }
+}
+
 // hv[j] = sum_b part[j][b] (one block per j, fixed tree); optionally alpha[k] += hv[k].
+// With planes = 2 (complex), blockIdx.y selects the real / imaginary plane at offset `plane`
+// and hv holds interleaved pairs; alpha takes the real part.
 __global__ __launch_bounds__(kRed) void k_reduce_parts(const double *__restrict__ part, int nparts,
                                                        const int *__restrict__ kdev, int extra, double *__restrict__ hv,
-                                                       double *__restrict__ alpha) {
+                                                       double *__restrict__ alpha, int planes = 1,
+                                                       int64_t plane = 0) {
     __shared__ double ws[kRed / 64];
     const int cnt = *kdev + 1 + extra;
-    const int j = blockIdx.x;
+    const int j = blockIdx.x, im = blockIdx.y;
     if (j >= cnt) return;
     double s = 0.0;
-    for (int p = threadIdx.x; p < nparts; p += kRed) s += part[(int64_t)j * nparts + p];
+    const double *pp = part + im * plane;
+    for (int p = threadIdx.x; p < nparts; p += kRed) s += pp[(int64_t)j * nparts + p];
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int q = 0; q < kRed / 64; ++q) t += ws[q];
-        hv[j] = t;
-        if (alpha && j == *kdev) alpha[j] += t;
+        hv[planes * j + im] = t;
+        if (alpha && im == 0 && j == *kdev) alpha[j] += t;
     }
 }
 
@@ -244,13 +324,14 @@ __global__ __launch_bounds__(kRed) void k_argmin(const double *__restrict__ d, i
     }
 }
 
-__global__ void k_init_v0(double *__restrict__ x, int64_t N, int mode, uint64_t seed, const int64_t *__restrict__ spike) {
+__global__ void k_init_v0(double *__restrict__ x, int64_t N, int mode, uint64_t seed, const int64_t *__restrict__ spike,
+                          int stride = 1) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
         double v;
         if (mode == QSD_V0_UNIFORM) {
             v = 1.0;
         } else if (mode == QSD_V0_MIN_DIAG) {
-            v = (i == *spike) ? 1.0 : 0.0;
+            v = (i == stride * *spike) ? 1.0 : 0.0;
         } else {
             // splitmix64 of (seed, i): uniform in [-1, 1)
             uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
@@ -303,22 +384,31 @@ __global__ __launch_bounds__(kRed) void k_resid_part(const double *__restrict__ 
 inline unsigned gridN(int64_t n) { return (unsigned)((n + kRed - 1) / kRed); }
 
 int enqueue_iteration(const SpmvOp &op, LzState &S, bool f32, hipStream_t st) {
-    const int64_t N = S.N;
+    const int64_t N = S.N, NR = S.NR;
+    const int32_t dt64 = S.cplx ? QSD_C128 : QSD_F64, dt32 = S.cplx ? QSD_C64 : QSD_F32;
     if (f32) {
-        k_f64_to_f32<<<1024, kRed, 0, st>>>(S.x, S.x32, N);
-        QSD_TRY(op.matvec(1, S.x32, 1, S.w32, 1, QSD_F32, st));
-        k_f32_to_f64<<<1024, kRed, 0, st>>>(S.w32, S.w, N);
+        k_f64_to_f32<<<1024, kRed, 0, st>>>(S.x, S.x32, NR);
+        QSD_TRY(op.matvec(1, S.x32, 1, S.w32, 1, dt32, st));
+        k_f32_to_f64<<<1024, kRed, 0, st>>>(S.w32, S.w, NR);
     } else {
-        QSD_TRY(op.matvec(1, S.x, 1, S.w, 1, QSD_F64, st));
+        QSD_TRY(op.matvec(1, S.x, 1, S.w, 1, dt64, st));
     }
+    const dim3 gt(kDotBlocks, (S.m + 1 + kGemvJ - 1) / kGemvJ);
+    const int64_t plane = (int64_t)(S.m + 1) * kDotBlocks;
     for (int pass = 0; pass < 2; ++pass) {
-        k_gemv_t<<<dim3(kDotBlocks, (S.m + 1 + kGemvJ - 1) / kGemvJ), kRed, 0, st>>>(S.V, S.w, N, S.kdev, 0, S.part);
-        k_reduce_parts<<<S.m + 1, kRed, 0, st>>>(S.part, kDotBlocks, S.kdev, 0, S.hv, S.alpha);
-        k_gemv_n_sub<<<gridN(N), kRed, 0, st>>>(S.V, S.hv, N, S.kdev, S.w);
+        if (S.cplx) {
+            k_gemv_t_c<<<gt, kRed, 0, st>>>((const double2 *)S.V, (const double2 *)S.w, N, S.kdev, plane, S.part);
+            k_reduce_parts<<<dim3(S.m + 1, 2), kRed, 0, st>>>(S.part, kDotBlocks, S.kdev, 0, S.hv, S.alpha, 2, plane);
+            k_gemv_n_sub_c<<<gridN(N), kRed, 0, st>>>((const double2 *)S.V, S.hv, N, S.kdev, (double2 *)S.w);
+        } else {
+            k_gemv_t<<<gt, kRed, 0, st>>>(S.V, S.w, N, S.kdev, 0, S.part);
+            k_reduce_parts<<<S.m + 1, kRed, 0, st>>>(S.part, kDotBlocks, S.kdev, 0, S.hv, S.alpha);
+            k_gemv_n_sub<<<gridN(N), kRed, 0, st>>>(S.V, S.hv, N, S.kdev, S.w);
+        }
     }
-    k_sq_part<<<kDotBlocks, kRed, 0, st>>>(S.w, N, S.part);
+    k_sq_part<<<kDotBlocks, kRed, 0, st>>>(S.w, NR, S.part);
     k_beta<<<1, kRed, 0, st>>>(S.part, kDotBlocks, S.kdev, S.beta, S.tri);
-    k_next<<<gridN(N), kRed, 0, st>>>(S.V, S.x, S.w, N, S.kdev, S.alpha, S.beta, S.m, S.tri);
+    k_next<<<gridN(NR), kRed, 0, st>>>(S.V, S.x, S.w, NR, S.kdev, S.alpha, S.beta, S.m, S.tri);
     k_bump<<<1, 1, 0, st>>>(S.kdev);
     QSD_CHECK_HIP(hipGetLastError());
     return QSD_OK;
@@ -356,32 +446,37 @@ int lanczos_impl(const SpmvOp &op, const qsd_lanczos_opts *opts, double *eval_ou
     qsd_lanczos_opts o;
     qsd_lanczos_default_opts(&o);
     if (opts) o = *opts;
-    if (op.is_complex()) return fail(QSD_ERR_UNSUPPORTED, "Lanczos for complex operators is not implemented");
+    const bool cplx = op.is_complex();
     if (o.max_iter < 1 || o.max_iter > 1000) return fail(QSD_ERR_INVALID_ARG, "max_iter must be in [1, 1000]");
     if (!(o.tol > 0)) return fail(QSD_ERR_INVALID_ARG, "tol must be > 0");
     if (o.spmv_dtype != QSD_F64 && o.spmv_dtype != QSD_F32) return fail(QSD_ERR_DTYPE, "spmv_dtype must be F64 or F32");
-    if (!op.takes(o.spmv_dtype)) return fail(QSD_ERR_DTYPE, "spmv_dtype must be the stored matrix's dtype");
+    const int32_t mv64 = cplx ? QSD_C128 : QSD_F64, mv32 = cplx ? QSD_C64 : QSD_F32;
+    if (!op.takes(o.spmv_dtype == QSD_F32 ? mv32 : mv64))
+        return fail(QSD_ERR_DTYPE, "spmv_dtype must be the stored matrix's dtype");
     if (o.v0_mode < QSD_V0_UNIFORM || o.v0_mode > QSD_V0_USER) return fail(QSD_ERR_INVALID_ARG, "bad v0_mode");
     if ((o.v0_mode == QSD_V0_USER || o.want_vector) && !d_evec)
         return fail(QSD_ERR_INVALID_ARG, "d_evec is required for QSD_V0_USER / want_vector");
     if (o.check_every < 1) o.check_every = 1;
     hipStream_t st = (hipStream_t)stream;
     const int64_t N = op.N();
+    const int64_t NR = cplx ? 2 * N : N;  // doubles per vector
     LzState S;
     S.N = N;
+    S.NR = NR;
+    S.cplx = cplx;
     S.m = (int)std::min<int64_t>(o.max_iter, N);
     const bool f32 = o.spmv_dtype == QSD_F32;
     int rc = QSD_OK;
     auto alloc_all = [&]() -> int {
-        QSD_TRY(dev_alloc(&S.V, (size_t)(S.m + 1) * N));
-        QSD_TRY(dev_alloc(&S.x, N));
-        QSD_TRY(dev_alloc(&S.w, N));
+        QSD_TRY(dev_alloc(&S.V, (size_t)(S.m + 1) * NR));
+        QSD_TRY(dev_alloc(&S.x, NR));
+        QSD_TRY(dev_alloc(&S.w, NR));
         if (f32) {
-            QSD_TRY(dev_alloc(&S.x32, N));
-            QSD_TRY(dev_alloc(&S.w32, N));
+            QSD_TRY(dev_alloc(&S.x32, NR));
+            QSD_TRY(dev_alloc(&S.w32, NR));
         }
-        QSD_TRY(dev_alloc(&S.part, (size_t)(S.m + 1) * kDotBlocks));
-        QSD_TRY(dev_alloc(&S.hv, S.m + 1));
+        QSD_TRY(dev_alloc(&S.part, (size_t)(S.m + 1) * kDotBlocks * (cplx ? 2 : 1)));
+        QSD_TRY(dev_alloc(&S.hv, (size_t)(S.m + 1) * (cplx ? 2 : 1)));
         QSD_TRY(dev_alloc(&S.alpha, S.m));
         QSD_TRY(dev_alloc(&S.beta, S.m));
         QSD_TRY(dev_alloc(&S.kdev, 1));
@@ -403,7 +498,7 @@ int lanczos_impl(const SpmvOp &op, const qsd_lanczos_opts *opts, double *eval_ou
     do {
         // start vector
         if (o.v0_mode == QSD_V0_USER) {
-            if (hipMemcpyAsync(S.x, d_evec, N * 8, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+            if (hipMemcpyAsync(S.x, d_evec, NR * 8, hipMemcpyDeviceToDevice, st) != hipSuccess) {
                 rc = fail(QSD_ERR_HIP, "copy failed");
                 break;
             }
@@ -411,14 +506,14 @@ int lanczos_impl(const SpmvOp &op, const qsd_lanczos_opts *opts, double *eval_ou
             int64_t *spike = nullptr;
             if ((rc = dev_alloc(&spike, 1)) != QSD_OK) break;
             if (o.v0_mode == QSD_V0_MIN_DIAG) k_argmin<<<1, kRed, 0, st>>>(op.diag(), N, spike);
-            k_init_v0<<<1024, kRed, 0, st>>>(S.x, N, o.v0_mode, o.seed, spike);
+            k_init_v0<<<1024, kRed, 0, st>>>(S.x, NR, o.v0_mode, o.seed, spike, cplx ? 2 : 1);
             if (hipStreamSynchronize(st) != hipSuccess) rc = fail(QSD_ERR_HIP, "v0 failed");
             dev_free(spike);
             if (rc != QSD_OK) break;
         }
-        k_sq_part<<<kDotBlocks, kRed, 0, st>>>(S.x, N, S.part);
-        k_scale<<<1024, kRed, 0, st>>>(S.x, N, S.part, kDotBlocks);
-        k_copy_row<<<1024, kRed, 0, st>>>(S.x, S.V, N);
+        k_sq_part<<<kDotBlocks, kRed, 0, st>>>(S.x, NR, S.part);
+        k_scale<<<1024, kRed, 0, st>>>(S.x, NR, S.part, kDotBlocks);
+        k_copy_row<<<1024, kRed, 0, st>>>(S.x, S.V, NR);
         k_zero<<<64, kRed, 0, st>>>(S.alpha, S.m);
         k_zero<<<64, kRed, 0, st>>>(S.beta, S.m);
         k_zero<<<1, 64, 0, st>>>(S.tri, 4);
@@ -488,26 +583,26 @@ int lanczos_impl(const SpmvOp &op, const qsd_lanczos_opts *opts, double *eval_ou
         // matvec timing: one extra timed SpMV (the Lanczos loop itself is not instrumented)
         hipEventRecord(e0, st);
         if (f32)
-            rc = op.matvec(1, S.x32, 1, S.w32, 1, QSD_F32, st);
+            rc = op.matvec(1, S.x32, 1, S.w32, 1, mv32, st);
         else
-            rc = op.matvec(1, S.x, 1, S.w, 1, QSD_F64, st);
+            rc = op.matvec(1, S.x, 1, S.w, 1, mv64, st);
         hipEventRecord(e1, st);
         if (rc != QSD_OK) break;
         hipEventSynchronize(e1);
         hipEventElapsedTime(&mv_ms, e0, e1);
         if (o.want_vector) {
             double *y = (double *)d_evec;
-            k_gemv_n<<<gridN(N), kRed, 0, st>>>(S.V, S.tri + 3, iters, N, y);
-            k_sq_part<<<kDotBlocks, kRed, 0, st>>>(y, N, S.part);
-            k_scale<<<1024, kRed, 0, st>>>(y, N, S.part, kDotBlocks);
-            if (op.takes(QSD_F64)) {
-                if ((rc = op.matvec(1, y, 1, S.w, 1, QSD_F64, st)) != QSD_OK) break;
+            k_gemv_n<<<gridN(NR), kRed, 0, st>>>(S.V, S.tri + 3, iters, NR, y);
+            k_sq_part<<<kDotBlocks, kRed, 0, st>>>(y, NR, S.part);
+            k_scale<<<1024, kRed, 0, st>>>(y, NR, S.part, kDotBlocks);
+            if (op.takes(mv64)) {
+                if ((rc = op.matvec(1, y, 1, S.w, 1, mv64, st)) != QSD_OK) break;
             } else {  // a stored FP32 matrix: the residual of the FP32 operator
-                k_f64_to_f32<<<1024, kRed, 0, st>>>(y, S.x32, N);
-                if ((rc = op.matvec(1, S.x32, 1, S.w32, 1, QSD_F32, st)) != QSD_OK) break;
-                k_f32_to_f64<<<1024, kRed, 0, st>>>(S.w32, S.w, N);
+                k_f64_to_f32<<<1024, kRed, 0, st>>>(y, S.x32, NR);
+                if ((rc = op.matvec(1, S.x32, 1, S.w32, 1, mv32, st)) != QSD_OK) break;
+                k_f32_to_f64<<<1024, kRed, 0, st>>>(S.w32, S.w, NR);
             }
-            k_resid_part<<<kDotBlocks, kRed, 0, st>>>(S.w, y, theta, N, S.part);
+            k_resid_part<<<kDotBlocks, kRed, 0, st>>>(S.w, y, theta, NR, S.part);
             std::vector<double> parts(kDotBlocks);
             if (hipMemcpyAsync(parts.data(), S.part, kDotBlocks * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
                 hipStreamSynchronize(st) != hipSuccess) {

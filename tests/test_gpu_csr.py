@@ -166,4 +166,4 @@ def test_csr_errors():
         qsd.CsrMatrix(H, dtype=torch.float64)
     A = qsd.CsrMatrix(H)
     with pytest.raises(qsd.QsdError, match="UNSUPPORTED"):
-        A.lanczos()
+        A.lanczos(block=4)  # block Lanczos is real only
