@@ -223,17 +223,32 @@ int qsd_ham_diag_splitting(const qsd_ham *h, double *lowest, double *splitting, 
 
 /* SpMV schedule (launch shape only: every schedule gives bitwise the same results, since each
  * row is evaluated by one lane in the same group order whatever workgroup runs it).
- *   QSD_SCHED_XCD_REMAP  workgroups dispatched to one XCD take contiguous row tiles, so rows
- *                        whose columns and probes overlap share that XCD's L2.
+ *   QSD_SCHED_XCD_REMAP   workgroups dispatched to one XCD take contiguous row tiles, so rows
+ *                         whose columns and probes overlap share that XCD's L2.
+ *   QSD_SCHED_SLOT_ORDER  a workgroup takes 256 consecutive rows of the slot order (the rows
+ *                         listed by the position of their slot in the hash table, kept with the
+ *                         table) instead of the canonical order.  The hash is linear, so the
+ *                         columns b ^ M_g of rows whose slots are neighbours are neighbours too.
+ *   QSD_SCHED_LOCKSTEP    the 64 lanes of a wave probe the same group in the same instruction
+ *                         (lanes whose row does not have it live sit idle) instead of each lane
+ *                         walking its own live groups; with SLOT_ORDER the wave's occupancy-bit
+ *                         loads for one group then fall in one or two cache lines.
+ *   QSD_SCHED_FILTER_FIRST  a lane first reads the occupancy bits of all its live groups'
+ *                         home slots (8 loads in flight), then the slots of the occupied ones
+ *                         (4 in flight), instead of reading bit and slot group by group.
  * qsd_ham_set_schedule sets the bits (INVALID_ARG for unknown bits). */
 #define QSD_SCHED_XCD_REMAP 1u
+#define QSD_SCHED_SLOT_ORDER 2u
+#define QSD_SCHED_LOCKSTEP 4u
+#define QSD_SCHED_FILTER_FIRST 8u
 int qsd_ham_set_schedule(qsd_ham *h, uint32_t schedule);
 int qsd_ham_get_schedule(const qsd_ham *h, uint32_t *schedule);
 
 /* Autotuner (not in the paper).  Times `reps` SpMVs (nvec vectors of `dtype`, internal buffers)
  * with HIP events for every candidate and keeps the fastest:
- *   QSD_TUNE_SCHEDULE  every schedule above;
- *   QSD_TUNE_LOAD      hash-table loads 1/16, 1/8, 1/4, 1/2: the subspace's table is rebuilt
+ *   QSD_TUNE_SCHEDULE  every schedule above (on the current table);
+ *   QSD_TUNE_LOAD      hash-table loads 1/32, 1/16, 1/8, 1/4, 1/2 (with the three fastest
+ *                      schedules when both flags are set): the subspace's table is rebuilt
  *                      (qsd_subspace_rehash), so the subspace must not be used meanwhile by
  *                      any other handle, batch or stream.  The best table depends on how the
  *                      occupancy bitmap and the slots fit the caches.

@@ -27,7 +27,8 @@ INDEX_I32, INDEX_I64 = 0, 1
 OP_FERMIONIC, OP_CHECK_HERMITIAN, OP_FORCE_COMPLEX, OP_NO_LADDER_INT, OP_ORDER_BY_MASK = 1, 2, 4, 8, 16
 SUB_ASSUME_SORTED_UNIQUE = 1
 V0_UNIFORM, V0_MIN_DIAG, V0_RANDOM, V0_USER = 0, 1, 2, 3
-SCHED_XCD_REMAP = 1
+SCHED_XCD_REMAP, SCHED_SLOT_ORDER, SCHED_LOCKSTEP, SCHED_FILTER_FIRST = 1, 2, 4, 8
+SCHED_ALL = 15
 TUNE_SCHEDULE, TUNE_LOAD = 1, 2
 CSR_LOWER_MIRROR = 1
 ERR_NAMES = {-1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "HIP", -4: "CAPACITY", -5: "NOT_HERMITIAN",

@@ -34,6 +34,7 @@ void clear_error();
 constexpr int kMaxLadder = 4;   // ladder-integer ranges for groups of up to 4 ladder letters
 constexpr int kMaxWords = 16;   // widest compiled key: 16 x 64 = 1024 qubits
 constexpr int kBlock = 256;     // threads per workgroup for row kernels
+constexpr uint32_t kSchedAll = QSD_SCHED_XCD_REMAP | QSD_SCHED_SLOT_ORDER | QSD_SCHED_LOCKSTEP | QSD_SCHED_FILTER_FIRST;
 
 // Padded word count used by the kernels: 1, 2, 4, 8 or 16.
 inline int padded_words(int n_qubits) {
@@ -76,6 +77,21 @@ int exclusive_scan_i64(const int64_t *d_in, int64_t *d_out, int64_t n, hipStream
 
 // ------------------------------------------------------------------- handle contents
 
+// The rows of a subspace in slot order (the order of their slots in the hash table), with their
+// keys and hashes in that order; rebuilt with the table.
+struct SlotRows {
+    uint32_t *order = nullptr;  // [N] row index of each position
+    uint64_t *keys = nullptr;   // [Wp][N]
+    uint64_t *hkey = nullptr;   // [N]
+};
+namespace qsd {
+inline void free_rows(SlotRows &r) {
+    dev_free(r.order);
+    dev_free(r.keys);
+    dev_free(r.hkey);
+}
+}  // namespace qsd
+
 struct qsd_subspace {
     int32_t n_qubits = 0;
     int32_t W = 0;   // words per string
@@ -87,6 +103,7 @@ struct qsd_subspace {
     uint64_t *slots = nullptr;   // [C] (tag << 32) | index, empty = ~0
     uint32_t *bitmap = nullptr;  // [C / 32] slot occupancy
     uint64_t *ztab = nullptr;    // [Wp * 8][256] byte tabulation of the hash
+    SlotRows rows;               // the rows in slot order
     bool exact = false;          // slots carry displacements (see device.h)
 };
 

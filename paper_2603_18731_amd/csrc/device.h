@@ -16,6 +16,9 @@ struct SubView {
     int64_t N;
     uint32_t cmask;  // C - 1
     uint32_t exact;  // slots carry the displacement: a tag match at the right displacement is the key
+    const uint32_t *__restrict__ order;  // [N] row indices in the order of their slots in the table
+    const uint64_t *__restrict__ okeys;  // [Wp][N] keys in that order
+    const uint64_t *__restrict__ ohkey;  // [N] hashes in that order
 };
 
 // Slot layout.  Default: tag (high 32 bits of the hash) | index (32 bits).  Exact mode (one-word

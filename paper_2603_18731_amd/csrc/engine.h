@@ -37,6 +37,9 @@ namespace qsd {
 
 constexpr int kChunk = 64;      // groups per chunk (one 64-bit live mask per lane)
 constexpr int kProbeBatch = 2;  // probes in flight per lane
+constexpr int kLockBatch = 4;   // groups in flight per wave in lockstep mode
+constexpr int kOccBatch = 8;    // occupancy-bit loads in flight per lane (filter-first mode)
+constexpr int kSlotBatch = 4;   // slot loads in flight per lane (filter-first mode)
 
 struct HamView {
     const uint64_t *__restrict__ g_mask;   // [G][Wp]
@@ -208,6 +211,115 @@ __device__ __forceinline__ uint32_t group_msob(const uint64_t *__restrict__ mask
     return ms;
 }
 
+// Probes NB groups for the lane's row: c[b] = chunk-local group, act[b] = whether the lane
+// probes it.  All occupancy-bit loads are issued before the slot loads, and the slots before any
+// hit is consumed; hits go to on_hit in increasing b (the caller passes increasing groups).
+template <int Wp, int NB, class OnHit>
+__device__ __forceinline__ void probe_groups(const SubView &s, const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp],
+                                             uint64_t hrow, const uint64_t *planes, int lane, const int (&c)[NB],
+                                             const bool (&act)[NB], OnHit &on_hit) {
+    // unconditional loads: idle lanes read word 0 / slot 0 and ignore them
+    uint64_t hh[NB];
+    uint32_t pos[NB], word[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        hh[b] = hrow ^ lds.hash[c[b] & (kChunk - 1)];
+        pos[b] = (uint32_t)hh[b] & s.cmask;
+        word[b] = s.bitmap[act[b] ? (pos[b] >> 5) : 0u];
+    }
+    uint64_t slot[NB];
+    bool occ[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        occ[b] = act[b] && ((word[b] >> (pos[b] & 31u)) & 1u);
+        slot[b] = s.slots[occ[b] ? pos[b] : 0u];
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (!occ[b]) continue;
+        const uint32_t tag = (uint32_t)(hh[b] >> 32);
+        uint64_t col[Wp];
+#pragma unroll
+        for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ lds.mask[c[b]][w];
+        int64_t j = -1;
+        if ((uint32_t)(slot[b] >> 32) == tag) j = slot_match<Wp>(s, slot[b], 0u, col);
+        if (j < 0) {
+            // the home slot held another string: follow the run while slots stay occupied
+            const uint32_t nxt = (pos[b] + 1) & s.cmask;
+            const uint32_t nw = ((nxt >> 5) == (pos[b] >> 5)) ? word[b] : s.bitmap[nxt >> 5];
+            if ((nw >> (nxt & 31u)) & 1u) j = probe_from<Wp>(s, nxt, 1u, tag, col);
+        }
+        if (j >= 0) {
+            const int cc = c[b];
+            const uint32_t lm = lds.lmask[cc];
+            const uint32_t L = row_lint<Wp>(key, lds.rec[cc], planes, lane) & lm;
+            const uint32_t lo = lds.iptr[cc][L];
+            const uint32_t hi = lm ? (uint32_t)lds.iptr[cc][L + 1] : lds.nterm[cc];
+            on_hit(j, lds.term0[cc] + lo, hi - lo);
+        }
+    }
+}
+
+// Filter-first mode, phase 1: for the NB groups c[b] the lane probes (act[b]), sets bit c[b] of
+// `occ` when the group's home slot is occupied, and of `occn` when the slot after it is occupied
+// too (or lies in the next bitmap word, so is not known here).  All NB loads are in flight at once.
+template <int NB>
+__device__ __forceinline__ void occupancy(const SubView &s, const uint64_t *lhash, uint64_t hrow, const int (&c)[NB],
+                                          const bool (&act)[NB], uint64_t &occ, uint64_t &occn) {
+    // the loads are unconditional (idle lanes all read word 0 and ignore it), so they are issued
+    // back to back without a branch per load
+    uint32_t pos[NB], word[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        pos[b] = (uint32_t)(hrow ^ lhash[c[b] & (kChunk - 1)]) & s.cmask;
+        word[b] = s.bitmap[act[b] ? (pos[b] >> 5) : 0u];
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const uint32_t sh = pos[b] & 31u;
+        const uint32_t o = act[b] ? ((word[b] >> sh) & 1u) : 0u;
+        const uint32_t n = sh == 31u ? 1u : ((word[b] >> (sh + 1u)) & 1u);
+        occ |= (uint64_t)o << (c[b] & (kChunk - 1));
+        occn |= (uint64_t)(o & n) << (c[b] & (kChunk - 1));
+    }
+}
+
+// Filter-first mode, phase 2: resolves NB groups whose home slot is occupied: reads the slots,
+// follows the run when the home slot holds another string and the next slot may be occupied,
+// and hands hits to on_hit in increasing b.
+template <int Wp, int NB, class OnHit>
+__device__ __forceinline__ void resolve_groups(const SubView &s, const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp],
+                                               uint64_t hrow, const uint64_t *planes, int lane, const int (&c)[NB],
+                                               const bool (&act)[NB], uint64_t occn, OnHit &on_hit) {
+    uint64_t hh[NB], slot[NB];
+    uint32_t pos[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        hh[b] = hrow ^ lds.hash[c[b] & (kChunk - 1)];
+        pos[b] = (uint32_t)hh[b] & s.cmask;
+        slot[b] = s.slots[act[b] ? pos[b] : 0u];  // unconditional, as above
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (!act[b]) continue;
+        const uint32_t tag = (uint32_t)(hh[b] >> 32);
+        uint64_t col[Wp];
+#pragma unroll
+        for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ lds.mask[c[b]][w];
+        int64_t j = -1;
+        if ((uint32_t)(slot[b] >> 32) == tag) j = slot_match<Wp>(s, slot[b], 0u, col);
+        if (j < 0 && ((occn >> c[b]) & 1ull)) j = probe_from<Wp>(s, (pos[b] + 1) & s.cmask, 1u, tag, col);
+        if (j >= 0) {
+            const int cc = c[b];
+            const uint32_t lm = lds.lmask[cc];
+            const uint32_t L = row_lint<Wp>(key, lds.rec[cc], planes, lane) & lm;
+            const uint32_t lo = lds.iptr[cc][L];
+            const uint32_t hi = lm ? (uint32_t)lds.iptr[cc][L + 1] : lds.nterm[cc];
+            on_hit(j, lds.term0[cc] + lo, hi - lo);
+        }
+    }
+}
+
 // Walks all groups for the lane's row and calls on_hit(j, t0, len) for every probe whose
 // column b_i ^ M_g is in the subspace (j = its index; [t0, t0 + len) = the group's terms for
 // the row's ladder integer), in increasing g.  All threads of the block must call it (chunks
@@ -217,10 +329,19 @@ __device__ __forceinline__ uint32_t group_msob(const uint64_t *__restrict__ mask
 // evaluation): the flip changes the row's bit at the group's most significant off-diagonal
 // bit, so the column is smaller exactly when that row bit is set, and in the ascending
 // canonical order its index is smaller too.  One more plane test per group in the scan.
+//
+// `lockstep` changes only which probes share an instruction: the wave walks the groups that are
+// live for any of its rows in increasing order, kLockBatch at a time, and every lane whose row
+// has the group live probes it in the same instruction.  When the wave's rows sit in one
+// stretch of the hash table (rows taken in slot order), the columns of one group, with hashes
+// h(b_i) ^ h(M_g), land in one stretch as well, and the wave's occupancy-bit loads for the group
+// touch one or two cache lines instead of one line per lane.  Each lane still meets its hits in
+// increasing group order, so both modes give bitwise the same sums.
 template <int Wp, bool LOWER = false, class OnHit>
 __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, const uint64_t (&key)[Wp],
                                            uint64_t hrow, bool valid, ChunkLds<Wp> &lds, OnHit &&on_hit,
-                                           unsigned long long *probes = nullptr) {
+                                           unsigned long long *probes = nullptr, bool lockstep = false,
+                                           bool filter_first = false) {
     const int lane = threadIdx.x & 63;
     uint64_t *planes = lds.planes[threadIdx.x >> 6];
 #pragma unroll
@@ -253,10 +374,68 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
             live = sliced_table((uint32_t)rec & 0xFFFFu, P[0], P[1], P[2], P[3]) & vrows;
             if (LOWER) live &= planes[group_msob<Wp>(h.g_mask + (g0 + lane) * Wp)];
         }
+        uint64_t todo = __ballot(live != 0ull);  // groups live for some row of the wave
         live = wave_transpose64(live, lane);
         uint32_t mlo = (uint32_t)live, mhi = (uint32_t)(live >> 32);
         if (probes) *probes += (unsigned long long)(__popc(mlo) + __popc(mhi));
         __syncthreads();
+        if (filter_first) {
+            // phase 1: occupancy bits of the live groups' home slots (and of the slot after)
+            uint64_t occ = 0, occn = 0;
+            if (lockstep) {
+                while (todo) {
+                    int c[kOccBatch];
+                    bool act[kOccBatch];
+#pragma unroll
+                    for (int b = 0; b < kOccBatch; ++b) {
+                        c[b] = todo ? (int)__builtin_ctzll(todo) : -1;
+                        todo &= todo - 1ull;
+                        act[b] = c[b] >= 0 && ((live >> c[b]) & 1ull);
+                    }
+                    occupancy<kOccBatch>(s, lds.hash, hrow, c, act, occ, occn);
+                }
+            } else {
+                uint64_t rem = live;
+                while (__any(rem != 0ull)) {
+                    int c[kOccBatch];
+                    bool act[kOccBatch];
+#pragma unroll
+                    for (int b = 0; b < kOccBatch; ++b) {
+                        c[b] = rem ? (int)__builtin_ctzll(rem) : -1;
+                        rem &= rem - 1ull;
+                        act[b] = c[b] >= 0;
+                    }
+                    occupancy<kOccBatch>(s, lds.hash, hrow, c, act, occ, occn);
+                }
+            }
+            // phase 2: the slots of the occupied home slots, lowest group first
+            while (__any(occ != 0ull)) {
+                int c[kSlotBatch];
+                bool act[kSlotBatch];
+#pragma unroll
+                for (int b = 0; b < kSlotBatch; ++b) {
+                    c[b] = occ ? (int)__builtin_ctzll(occ) : -1;
+                    occ &= occ - 1ull;
+                    act[b] = c[b] >= 0;
+                }
+                resolve_groups<Wp, kSlotBatch>(s, lds, key, hrow, planes, lane, c, act, occn, on_hit);
+            }
+            continue;
+        }
+        if (lockstep) {
+            while (todo) {
+                int c[kLockBatch];
+                bool act[kLockBatch];
+#pragma unroll
+                for (int b = 0; b < kLockBatch; ++b) {
+                    c[b] = todo ? (int)__builtin_ctzll(todo) : -1;
+                    todo &= todo - 1ull;
+                    act[b] = c[b] >= 0 && ((live >> c[b]) & 1ull);
+                }
+                probe_groups<Wp, kLockBatch>(s, lds, key, hrow, planes, lane, c, act, on_hit);
+            }
+            continue;
+        }
         // probe: each lane pops its own live groups, kProbeBatch at a time
         while (true) {
             int c[kProbeBatch];
@@ -267,45 +446,10 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                 anyc |= c[b] >= 0;
             }
             if (!__any(anyc)) break;
-            uint64_t hh[kProbeBatch];
-            uint32_t pos[kProbeBatch], word[kProbeBatch];
+            bool act[kProbeBatch];
 #pragma unroll
-            for (int b = 0; b < kProbeBatch; ++b) {
-                hh[b] = c[b] >= 0 ? (hrow ^ lds.hash[c[b]]) : 0ull;
-                pos[b] = (uint32_t)hh[b] & s.cmask;
-                word[b] = c[b] >= 0 ? s.bitmap[pos[b] >> 5] : 0u;
-            }
-            uint64_t slot[kProbeBatch];
-            bool occ[kProbeBatch];
-#pragma unroll
-            for (int b = 0; b < kProbeBatch; ++b) {
-                occ[b] = (word[b] >> (pos[b] & 31u)) & 1u;
-                slot[b] = occ[b] ? s.slots[pos[b]] : ~0ull;
-            }
-#pragma unroll
-            for (int b = 0; b < kProbeBatch; ++b) {
-                if (!occ[b]) continue;
-                const uint32_t tag = (uint32_t)(hh[b] >> 32);
-                uint64_t col[Wp];
-#pragma unroll
-                for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ lds.mask[c[b]][w];
-                int64_t j = -1;
-                if ((uint32_t)(slot[b] >> 32) == tag) j = slot_match<Wp>(s, slot[b], 0u, col);
-                if (j < 0) {
-                    // the home slot held another string: follow the run while slots stay occupied
-                    const uint32_t nxt = (pos[b] + 1) & s.cmask;
-                    const uint32_t nw = ((nxt >> 5) == (pos[b] >> 5)) ? word[b] : s.bitmap[nxt >> 5];
-                    if ((nw >> (nxt & 31u)) & 1u) j = probe_from<Wp>(s, nxt, 1u, tag, col);
-                }
-                if (j >= 0) {
-                    const int cc = c[b];
-                    const uint32_t lm = lds.lmask[cc];
-                    const uint32_t L = row_lint<Wp>(key, lds.rec[cc], planes, lane) & lm;
-                    const uint32_t lo = lds.iptr[cc][L];
-                    const uint32_t hi = lm ? (uint32_t)lds.iptr[cc][L + 1] : lds.nterm[cc];
-                    on_hit(j, lds.term0[cc] + lo, hi - lo);
-                }
-            }
+            for (int b = 0; b < kProbeBatch; ++b) act[b] = c[b] >= 0;
+            probe_groups<Wp, kProbeBatch>(s, lds, key, hrow, planes, lane, c, act, on_hit);
         }
     }
 }

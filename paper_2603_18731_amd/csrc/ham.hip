@@ -50,10 +50,11 @@ __global__ void k_to_f32(const double *__restrict__ in, float *__restrict__ out,
 template <int Wp, int NV, class ET, bool CPLX>
 __global__ __launch_bounds__(kBlock) void k_matvec(SubView s, HamView h, const ET *__restrict__ dre,
                                                    const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
-                                                   ET *__restrict__ y, int64_t ldy, int nvec, int remap) {
+                                                   ET *__restrict__ y, int64_t ldy, int nvec, uint32_t sched) {
     __shared__ ChunkLds<Wp> lds;
-    const int64_t row0 = tile_index(blockIdx.x, gridDim.x, remap != 0) * kBlock;
-    matvec_block<Wp, NV, ET, CPLX>(s, h, dre, dim, x, ldx, y, ldy, nvec, row0, lds);
+    const int64_t row0 = tile_index(blockIdx.x, gridDim.x, (sched & QSD_SCHED_XCD_REMAP) != 0) * kBlock;
+    matvec_block<Wp, NV, ET, CPLX>(s, h, dre, dim, x, ldx, y, ldy, nvec, row0, lds, (sched & QSD_SCHED_SLOT_ORDER) != 0,
+                                   (sched & QSD_SCHED_LOCKSTEP) != 0, (sched & QSD_SCHED_FILTER_FIRST) != 0);
 }
 
 // ---------------------------------------------------------------------------------- CSR
@@ -249,7 +250,7 @@ void launch_mv(const qsd_ham *h, const void *x, int64_t ldx, void *y, int64_t ld
     const ET *dim = CPLX ? (f32 ? (const ET *)h->diag32_im : (const ET *)h->diag_im) : nullptr;
     k_matvec<Wp, NV, ET, CPLX><<<grid_for(h->N, kBlock), kBlock, 0, st>>>(sview(h->s), view_of(h, f32), dre, dim,
                                                                           (const ET *)x, ldx, (ET *)y, ldy, nvec,
-                                                                          (int)(h->schedule & QSD_SCHED_XCD_REMAP));
+                                                                          h->schedule);
 }
 
 template <int Wp, class ET, bool CPLX>
@@ -539,7 +540,7 @@ extern "C" int qsd_ham_diag_splitting(const qsd_ham *h, double *lowest, double *
 extern "C" int qsd_ham_set_schedule(qsd_ham *h, uint32_t schedule) {
     clear_error();
     if (!h) return fail(QSD_ERR_INVALID_ARG, "NULL handle");
-    if (schedule & ~QSD_SCHED_XCD_REMAP) return fail(QSD_ERR_INVALID_ARG, "unknown schedule bits 0x%x", schedule);
+    if (schedule & ~kSchedAll) return fail(QSD_ERR_INVALID_ARG, "unknown schedule bits 0x%x", schedule);
     h->schedule = schedule;
     return QSD_OK;
 }
@@ -582,35 +583,46 @@ extern "C" int qsd_ham_autotune(qsd_ham *h, int32_t nvec, int32_t dtype, int32_t
     };
     const uint32_t sched0 = h->schedule;
     const int64_t C0 = sub->C;
-    std::vector<double> loads;
-    if (flags & QSD_TUNE_LOAD) {
-        for (double l : {0.0625, 0.125, 0.25, 0.5}) loads.push_back(l);
-    } else {
-        loads.push_back(0.0);  // keep the current table
-    }
-    std::vector<uint32_t> scheds;
-    if (flags & QSD_TUNE_SCHEDULE) {
-        scheds = {0u, QSD_SCHED_XCD_REMAP};
-    } else {
-        scheds = {sched0};
-    }
     float ms_before = INFINITY, best_ms = INFINITY;
     if (rc == QSD_OK) rc = time_it(ms_before);
     uint32_t best_sched = sched0;
     double best_load = (double)sub->N / (double)sub->C;
     int64_t best_C = C0;
-    for (double l : loads) {
-        if (rc != QSD_OK) break;
-        if (l > 0.0 && (rc = qsd_subspace_rehash(sub, l, stream)) != QSD_OK) break;
-        for (uint32_t sc : scheds) {
-            h->schedule = sc;
+    auto consider = [&](uint32_t sc, double l, float &ms) -> int {
+        h->schedule = sc;
+        QSD_TRY(time_it(ms));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_sched = sc;
+            best_C = sub->C;
+            best_load = l > 0.0 ? l : best_load;
+        }
+        return QSD_OK;
+    };
+    // every schedule on the current table, then the three fastest on every other table
+    std::vector<std::pair<float, uint32_t>> ranked;
+    if (flags & QSD_TUNE_SCHEDULE) {
+        for (uint32_t sc = 0; sc <= kSchedAll && rc == QSD_OK; ++sc) {
             float ms = 0.0f;
-            if ((rc = time_it(ms)) != QSD_OK) break;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best_sched = sc;
-                best_C = sub->C;
-                best_load = l > 0.0 ? l : best_load;
+            rc = consider(sc, 0.0, ms);
+            ranked.push_back({ms, sc});
+        }
+        std::sort(ranked.begin(), ranked.end());
+        if (ranked.size() > 3) ranked.resize(3);
+    } else {
+        ranked.push_back({0.0f, sched0});
+    }
+    if (flags & QSD_TUNE_LOAD) {
+        for (double l : {0.03125, 0.0625, 0.125, 0.25, 0.5}) {
+            if (rc != QSD_OK) break;
+            if ((rc = qsd_subspace_rehash(sub, l, stream)) != QSD_OK) break;
+            if (sub->C == C0 && (flags & QSD_TUNE_SCHEDULE)) {  // already timed
+                if (best_C == C0 && best_load == (double)sub->N / (double)C0) best_load = l;
+                continue;
+            }
+            for (auto &p : ranked) {
+                float ms = 0.0f;
+                if ((rc = consider(p.second, l, ms)) != QSD_OK) break;
             }
         }
     }

@@ -12,7 +12,8 @@ inline HamView ham_view(const qsd_ham *h, bool f32) {
 }
 
 inline SubView sub_view(const qsd_subspace *s) {
-    return SubView{s->keys, s->hkey, s->slots, s->bitmap, s->N, (uint32_t)(s->C - 1), s->exact ? 1u : 0u};
+    return SubView{s->keys,  s->hkey, s->slots, s->bitmap, s->N, (uint32_t)(s->C - 1), s->exact ? 1u : 0u,
+                   s->rows.order, s->rows.keys, s->rows.hkey};
 }
 
 // Row tile of workgroup b out of G.  Workgroups are dispatched round-robin over the 8 XCDs, so
@@ -24,29 +25,38 @@ __device__ __forceinline__ int64_t tile_index(unsigned b, unsigned G, bool remap
     return (int64_t)((x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + r);
 }
 
-// Loads the lane's row `row0 + lane` (clamped to a valid row for lanes past the end).
+// Loads the lane's row: position `row0 + lane` of the canonical order, or of the slot order
+// with `by_slot` (clamped to a valid row for lanes past the end).
 template <int Wp>
 __device__ __forceinline__ int64_t load_row(const SubView &s, int64_t row0, uint64_t (&key)[Wp], uint64_t &hrow,
-                                            bool &valid) {
+                                            bool &valid, bool by_slot = false) {
     const int64_t i = row0 + threadIdx.x;
     valid = i < s.N;
-    const int64_t r = valid ? i : s.N - 1;
+    const int64_t p = valid ? i : s.N - 1;
+    if (by_slot) {
 #pragma unroll
-    for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + r];
-    hrow = s.hkey[r];
-    return r;
+        for (int w = 0; w < Wp; ++w) key[w] = s.okeys[(int64_t)w * s.N + p];
+        hrow = s.ohkey[p];
+        return s.order[p];
+    }
+#pragma unroll
+    for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + p];
+    hrow = s.hkey[p];
+    return p;
 }
 
-// y[r] = d_r x[r] + sum over the row's present elements of H_rj x[j] for rows row0 .. row0+255,
-// all `nvec` interleaved vectors; FP64 accumulation in group order.
+// y[r] = d_r x[r] + sum over the row's present elements of H_rj x[j] for the rows at positions
+// row0 .. row0+255 (of the canonical order, or of the slot order with `by_slot`), all `nvec`
+// interleaved vectors; FP64 accumulation in group order.
 template <int Wp, int NV, class ET, bool CPLX>
 __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h, const ET *__restrict__ dre,
                                              const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
                                              ET *__restrict__ y, int64_t ldy, int nvec, int64_t row0,
-                                             ChunkLds<Wp> &lds) {
+                                             ChunkLds<Wp> &lds, bool by_slot = false, bool lockstep = false,
+                                             bool filter_first = false) {
     uint64_t key[Wp], hrow;
     bool valid;
-    const int64_t r = load_row<Wp>(s, row0, key, hrow, valid);
+    const int64_t r = load_row<Wp>(s, row0, key, hrow, valid, by_slot);
     double acc_re[NV], acc_im[NV];
     {
         const double dr = (double)dre[r];
@@ -80,7 +90,7 @@ __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h,
                 }
             }
         }
-    });
+    }, nullptr, lockstep, filter_first);
     if (!valid) return;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {

@@ -297,6 +297,75 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
 
 inline unsigned grid_for(int64_t n, int per_block) { return (unsigned)((n + per_block - 1) / per_block); }
 
+// ------------------------------------------------------------------- slot order of the rows
+
+__global__ __launch_bounds__(kBlock) void k_word_counts(const uint32_t *__restrict__ bitmap, int64_t nw,
+                                                        int64_t *__restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < nw) cnt[i] = __popc(bitmap[i]);
+}
+
+// order[base[i] + k] = index held by the k-th occupied slot of bitmap word i.  Every string
+// occupies exactly one slot, so the bitmap holds N set bits and base[i] + popc(word i) <= N.
+__global__ __launch_bounds__(kBlock) void k_slot_order(const uint32_t *__restrict__ bitmap,
+                                                       const uint64_t *__restrict__ slots, int64_t nw,
+                                                       const int64_t *__restrict__ base, uint32_t exact,
+                                                       uint32_t *__restrict__ order) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nw) return;
+    uint32_t w = bitmap[i];
+    int64_t o = base[i];
+    while (w) {
+        const int b = __builtin_ctz(w);
+        w &= w - 1u;
+        const uint64_t slot = slots[i * 32 + b];
+        order[o++] = exact ? ((uint32_t)slot & kExactIdxMask) : (uint32_t)slot;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_rows(const uint64_t *__restrict__ keys,
+                                                        const uint64_t *__restrict__ hkey,
+                                                        const uint32_t *__restrict__ order, int64_t N, int Wp,
+                                                        uint64_t *__restrict__ okeys, uint64_t *__restrict__ ohkey) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= N) return;
+    const int64_t r = order[k];
+    for (int w = 0; w < Wp; ++w) okeys[(int64_t)w * N + k] = keys[(int64_t)w * N + r];
+    ohkey[k] = hkey[r];
+}
+
+// The rows listed in the order of their slots (a compaction of the occupancy bitmap), with
+// their keys and hashes in that order.  A run of consecutive entries holds rows whose home slots
+// share a stretch of the table, so for any group their columns b ^ M_g, whose hashes are
+// h(b) ^ h(M_g), share a stretch too.
+int build_order(const qsd_subspace *sub, int64_t C, bool exact, const uint64_t *slots, const uint32_t *bitmap,
+                SlotRows *out, hipStream_t st) {
+    const int64_t N = sub->N, nw = C / 32;
+    int64_t *base = nullptr;
+    SlotRows o;
+    QSD_TRY(dev_alloc(&base, nw));
+    int rc = dev_alloc(&o.order, N);
+    if (rc == QSD_OK) rc = dev_alloc(&o.keys, (size_t)sub->Wp * N);
+    if (rc == QSD_OK) rc = dev_alloc(&o.hkey, N);
+    if (rc == QSD_OK) {
+        k_word_counts<<<grid_for(nw, kBlock), kBlock, 0, st>>>(bitmap, nw, base);
+        rc = exclusive_scan_i64(base, base, nw, st);
+    }
+    if (rc == QSD_OK) {
+        k_slot_order<<<grid_for(nw, kBlock), kBlock, 0, st>>>(bitmap, slots, nw, base, exact ? 1u : 0u, o.order);
+        k_gather_rows<<<grid_for(N, kBlock), kBlock, 0, st>>>(sub->keys, sub->hkey, o.order, N, sub->Wp, o.keys, o.hkey);
+        if (hipStreamSynchronize(st) != hipSuccess)
+            rc = fail(QSD_ERR_HIP, "slot order failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    dev_free(base);
+    if (rc != QSD_OK) {
+        free_rows(o);
+        return rc;
+    }
+    *out = o;
+    return QSD_OK;
+}
+
 template <int Wp>
 int build_impl(qsd_subspace *sub, const uint64_t *d_bits, int64_t n_in, uint32_t flags, double max_load,
                hipStream_t st) {
@@ -407,6 +476,7 @@ int build_impl(qsd_subspace *sub, const uint64_t *d_bits, int64_t n_in, uint32_t
             rc = fail(QSD_ERR_HIP, "hash build failed: %s", hipGetErrorString(hipGetLastError()));
             break;
         }
+        rc = build_order(sub, C, sub->exact, sub->slots, sub->bitmap, &sub->rows, st);
     } while (0);
     cleanup();
     return rc;
@@ -419,11 +489,13 @@ void free_sub(qsd_subspace *s) {
     dev_free(s->slots);
     dev_free(s->bitmap);
     dev_free(s->ztab);
+    free_rows(s->rows);
     delete s;
 }
 
 SubView view_of(const qsd_subspace *s) {
-    return SubView{s->keys, s->hkey, s->slots, s->bitmap, s->N, (uint32_t)(s->C - 1), s->exact ? 1u : 0u};
+    return SubView{s->keys,  s->hkey, s->slots, s->bitmap, s->N, (uint32_t)(s->C - 1), s->exact ? 1u : 0u,
+                   s->rows.order, s->rows.keys, s->rows.hkey};
 }
 
 }  // namespace
@@ -501,6 +573,8 @@ int rehash_impl(qsd_subspace *sub, int64_t C, hipStream_t st) {
         if (hipStreamSynchronize(st) != hipSuccess)
             rc = fail(QSD_ERR_HIP, "hash rebuild failed: %s", hipGetErrorString(hipGetLastError()));
     }
+    SlotRows rows;
+    if (rc == QSD_OK) rc = build_order(sub, C, exact, slots, bitmap, &rows, st);
     if (rc != QSD_OK) {
         dev_free(slots);
         dev_free(bitmap);
@@ -508,8 +582,10 @@ int rehash_impl(qsd_subspace *sub, int64_t C, hipStream_t st) {
     }
     dev_free(sub->slots);
     dev_free(sub->bitmap);
+    free_rows(sub->rows);
     sub->slots = slots;
     sub->bitmap = bitmap;
+    sub->rows = rows;
     sub->C = C;
     sub->exact = exact;
     return QSD_OK;

@@ -25,34 +25,74 @@ def _ham(keys, tl):
     return qsd.SubspaceHamiltonian(qsd.Subspace(keys, tl.n_qubits), qsd.operator_from_termlist(tl))
 
 
-@pytest.mark.parametrize("case", ["xxz", "fermi", "heavyhex"])
-def test_schedules_bitwise(case):
+def _case(case):
     if case == "xxz":
-        H = _ham(c2_keys(50_000), wl.xxz_grid_6x6())
-    elif case == "fermi":
+        return _ham(c2_keys(50_000), wl.xxz_grid_6x6())
+    if case == "fermi":
         ops, keys = c3_parts(90, 90)
-        H = _ham(keys, ops)
-    else:
-        tl, keys = heavy_hex_small(30_001)
-        H = _ham(keys, tl)
-    rng = np.random.default_rng(3)
-    x = torch.from_numpy(rng.standard_normal((H.N, 3))).cuda()
+        return _ham(keys, ops)
+    if case == "complex":
+        rng = np.random.default_rng(21)
+        n = 14
+        terms = []
+        for _ in range(60):
+            m = int(rng.integers(1, 4))
+            qs = rng.choice(n, size=m, replace=False)
+            word = [(int(q), int(rng.integers(0, 7))) for q in qs]
+            c = complex(rng.normal(), rng.normal())
+            terms.append((c, word))
+            terms.append((c.conjugate(), [(q, {5: 6, 6: 5}.get(k, k)) for q, k in word]))
+        tl = wl.TermList.from_terms(n, terms)
+        from oracle import subspace as osub
+
+        keys = osub.ints_to_keys(sorted(rng.choice(1 << n, size=5000, replace=False).tolist()), 1)
+        return _ham(keys, tl)
+    tl, keys = heavy_hex_small(30_001)
+    return _ham(keys, tl)
+
+
+def _run_all(H, x):
+    """One output per schedule, each written into a NaN-filled buffer (a row no lane writes stays
+    NaN and fails the comparison)."""
     outs = []
-    for sched in (0, qsd.SCHED_XCD_REMAP):
+    for sched in range(qsd.SCHED_ALL + 1):
         H.schedule = sched
-        outs.append(H.matvec(x))
+        y = torch.full_like(x, float("nan"))
+        H.matvec(x, out=y)
+        outs.append(y)
     torch.cuda.synchronize()
+    return outs
+
+
+@pytest.mark.parametrize("case", ["xxz", "fermi", "heavyhex", "complex"])
+def test_schedules_bitwise(case):
+    H = _case(case)
+    rng = np.random.default_rng(3)
+    if H.is_complex:
+        x = torch.from_numpy(rng.standard_normal((H.N, 2)) + 1j * rng.standard_normal((H.N, 2))).cuda()
+    else:
+        x = torch.from_numpy(rng.standard_normal((H.N, 3))).cuda()
+    outs = _run_all(H, x)
     say(case, "N", H.N)
-    assert torch.equal(outs[0], outs[1])
-    r = H.autotune(nvec=1, reps=2)
+    assert not torch.isnan(outs[0]).any()
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    if not H.is_complex:
+        # single precision and one vector, through the slot-order lockstep schedule
+        x32 = x[:, :1].float().contiguous()
+        o32 = _run_all(H, x32)
+        for o in o32[1:]:
+            assert torch.equal(o, o32[0])
+    r = H.autotune(nvec=x.shape[1], dtype=x.dtype, reps=2)
     say(case, "autotune ->", r)
-    assert r["schedule"] in (0, qsd.SCHED_XCD_REMAP) and H.schedule == r["schedule"] and r["ms"] > 0
-    assert r["max_load"] in (0.0625, 0.125, 0.25, 0.5) and H.subspace.capacity == r["capacity"]
+    assert 0 <= r["schedule"] <= qsd.SCHED_ALL and H.schedule == r["schedule"] and r["ms"] > 0
+    assert r["max_load"] in (0.03125, 0.0625, 0.125, 0.25, 0.5) and H.subspace.capacity == r["capacity"]
     assert torch.equal(H.matvec(x), outs[0])  # a rebuilt table gives the same output
     keys_before = H.subspace.keys()
     for load in (0.5, 0.03):
         H.subspace.rehash(load)
-        assert torch.equal(H.matvec(x), outs[0])
+        for o in _run_all(H, x):  # the slot order is rebuilt with the table
+            assert torch.equal(o, outs[0])
         assert torch.equal(H.subspace.lookup(keys_before), torch.arange(H.N, device="cuda"))
     with pytest.raises(qsd.QsdError, match="INVALID_ARG"):
         H.schedule = 0x80
