@@ -182,6 +182,7 @@ struct ChunkLds {
     uint32_t lmask[kChunk];              // ladder-integer bits used for the range (0: all terms)
     uint16_t iptr[kChunk][kIptr];
     uint64_t planes[kBlock / 64][64 * Wp];
+    uint8_t clist[kBlock / 64][kChunk];  // lockstep filter-first: the wave's k-th live group
 };
 
 // Pops the lowest set bit of a 64-bit mask held as two words; -1 when empty.
@@ -285,12 +286,12 @@ __device__ __forceinline__ void occupancy(const SubView &s, const uint64_t *lhas
 }
 
 // Filter-first mode, phase 2: resolves NB groups whose home slot is occupied: reads the slots,
-// follows the run when the home slot holds another string and the next slot may be occupied,
-// and hands hits to on_hit in increasing b.
+// follows the run when the home slot holds another string and the next slot may be occupied
+// (next[b]), and hands hits to on_hit in increasing b.
 template <int Wp, int NB, class OnHit>
 __device__ __forceinline__ void resolve_groups(const SubView &s, const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp],
                                                uint64_t hrow, const uint64_t *planes, int lane, const int (&c)[NB],
-                                               const bool (&act)[NB], uint64_t occn, OnHit &on_hit) {
+                                               const bool (&act)[NB], const bool (&next)[NB], OnHit &on_hit) {
     uint64_t hh[NB], slot[NB];
     uint32_t pos[NB];
 #pragma unroll
@@ -308,7 +309,7 @@ __device__ __forceinline__ void resolve_groups(const SubView &s, const ChunkLds<
         for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ lds.mask[c[b]][w];
         int64_t j = -1;
         if ((uint32_t)(slot[b] >> 32) == tag) j = slot_match<Wp>(s, slot[b], 0u, col);
-        if (j < 0 && ((occn >> c[b]) & 1ull)) j = probe_from<Wp>(s, (pos[b] + 1) & s.cmask, 1u, tag, col);
+        if (j < 0 && next[b]) j = probe_from<Wp>(s, (pos[b] + 1) & s.cmask, 1u, tag, col);
         if (j >= 0) {
             const int cc = c[b];
             const uint32_t lm = lds.lmask[cc];
@@ -379,46 +380,86 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
         uint32_t mlo = (uint32_t)live, mhi = (uint32_t)(live >> 32);
         if (probes) *probes += (unsigned long long)(__popc(mlo) + __popc(mhi));
         __syncthreads();
-        if (filter_first) {
-            // phase 1: occupancy bits of the live groups' home slots (and of the slot after)
+        if (filter_first && lockstep) {
+            // phase 1, wave-uniform groups: bit k of occ / occn is for the wave's k-th live group,
+            // whose chunk index is clist[k]
+            uint8_t *clist = lds.clist[threadIdx.x >> 6];
+            {
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(todo >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)todo, 0u));
+                if ((todo >> lane) & 1ull) clist[below] = (uint8_t)lane;
+            }
             uint64_t occ = 0, occn = 0;
-            if (lockstep) {
-                while (todo) {
-                    int c[kOccBatch];
-                    bool act[kOccBatch];
+            for (int k0 = 0; todo; k0 += kOccBatch) {
+                int c[kOccBatch];
 #pragma unroll
-                    for (int b = 0; b < kOccBatch; ++b) {
-                        c[b] = todo ? (int)__builtin_ctzll(todo) : -1;
-                        todo &= todo - 1ull;
-                        act[b] = c[b] >= 0 && ((live >> c[b]) & 1ull);
-                    }
-                    occupancy<kOccBatch>(s, lds.hash, hrow, c, act, occ, occn);
+                for (int b = 0; b < kOccBatch; ++b) {
+                    c[b] = todo ? (int)__builtin_ctzll(todo) : -1;
+                    todo &= todo - 1ull;
                 }
-            } else {
-                uint64_t rem = live;
-                while (__any(rem != 0ull)) {
-                    int c[kOccBatch];
-                    bool act[kOccBatch];
+                uint32_t pos[kOccBatch], word[kOccBatch];
 #pragma unroll
-                    for (int b = 0; b < kOccBatch; ++b) {
-                        c[b] = rem ? (int)__builtin_ctzll(rem) : -1;
-                        rem &= rem - 1ull;
-                        act[b] = c[b] >= 0;
-                    }
-                    occupancy<kOccBatch>(s, lds.hash, hrow, c, act, occ, occn);
+                for (int b = 0; b < kOccBatch; ++b) {
+                    pos[b] = (uint32_t)(hrow ^ lds.hash[c[b] & (kChunk - 1)]) & s.cmask;
+                    word[b] = c[b] >= 0 ? s.bitmap[pos[b] >> 5] : 0u;  // uniform condition
                 }
+                uint32_t po = 0, pn = 0;
+#pragma unroll
+                for (int b = 0; b < kOccBatch; ++b) {
+                    // a: the lane's row has the group live; t: bit 0 = home slot occupied,
+                    // bit 1 = next slot occupied (or in the next bitmap word, so unknown).
+                    // Past the end of the list (c < 0) the word is 0, so bit 0 of t is 0.
+                    const uint32_t a = (uint32_t)(live >> (c[b] & (kChunk - 1))) & 1u;
+                    const uint32_t t = __builtin_amdgcn_alignbit(1u, word[b], pos[b] & 31u);
+                    po |= (t & a) << b;
+                    pn |= ((t >> 1) & t & a) << b;
+                }
+                occ |= (uint64_t)po << k0;
+                occn |= (uint64_t)pn << k0;
             }
             // phase 2: the slots of the occupied home slots, lowest group first
             while (__any(occ != 0ull)) {
                 int c[kSlotBatch];
-                bool act[kSlotBatch];
+                bool act[kSlotBatch], nxt[kSlotBatch];
+#pragma unroll
+                for (int b = 0; b < kSlotBatch; ++b) {
+                    const int k = occ ? (int)__builtin_ctzll(occ) : -1;
+                    occ &= occ - 1ull;
+                    act[b] = k >= 0;
+                    c[b] = act[b] ? (int)clist[k] : 0;
+                    nxt[b] = act[b] && ((occn >> k) & 1ull);
+                }
+                resolve_groups<Wp, kSlotBatch>(s, lds, key, hrow, planes, lane, c, act, nxt, on_hit);
+            }
+            continue;
+        }
+        if (filter_first) {
+            // phase 1: occupancy bits of the live groups' home slots (and of the slot after)
+            uint64_t occ = 0, occn = 0;
+            uint64_t rem = live;
+            while (__any(rem != 0ull)) {
+                int c[kOccBatch];
+                bool act[kOccBatch];
+#pragma unroll
+                for (int b = 0; b < kOccBatch; ++b) {
+                    c[b] = rem ? (int)__builtin_ctzll(rem) : -1;
+                    rem &= rem - 1ull;
+                    act[b] = c[b] >= 0;
+                }
+                occupancy<kOccBatch>(s, lds.hash, hrow, c, act, occ, occn);
+            }
+            // phase 2: the slots of the occupied home slots, lowest group first
+            while (__any(occ != 0ull)) {
+                int c[kSlotBatch];
+                bool act[kSlotBatch], nxt[kSlotBatch];
 #pragma unroll
                 for (int b = 0; b < kSlotBatch; ++b) {
                     c[b] = occ ? (int)__builtin_ctzll(occ) : -1;
                     occ &= occ - 1ull;
                     act[b] = c[b] >= 0;
+                    nxt[b] = act[b] && ((occn >> c[b]) & 1ull);
                 }
-                resolve_groups<Wp, kSlotBatch>(s, lds, key, hrow, planes, lane, c, act, occn, on_hit);
+                resolve_groups<Wp, kSlotBatch>(s, lds, key, hrow, planes, lane, c, act, nxt, on_hit);
             }
             continue;
         }

@@ -47,6 +47,14 @@ __global__ void k_to_f32(const double *__restrict__ in, float *__restrict__ out,
 
 // ------------------------------------------------------------------------------- matvec
 
+// Rows in slot order touch x, d and y at random positions; with FP64 elements the diagonal
+// term goes to a streaming first pass instead (k_diag_apply), and only rows with off-diagonal
+// elements touch y again.
+template <class ET>
+__host__ __device__ inline bool split_diag(uint32_t sched) {
+    return std::is_same<ET, double>::value && (sched & QSD_SCHED_SLOT_ORDER) != 0;
+}
+
 template <int Wp, int NV, class ET, bool CPLX>
 __global__ __launch_bounds__(kBlock) void k_matvec(SubView s, HamView h, const ET *__restrict__ dre,
                                                    const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
@@ -54,7 +62,8 @@ __global__ __launch_bounds__(kBlock) void k_matvec(SubView s, HamView h, const E
     __shared__ ChunkLds<Wp> lds;
     const int64_t row0 = tile_index(blockIdx.x, gridDim.x, (sched & QSD_SCHED_XCD_REMAP) != 0) * kBlock;
     matvec_block<Wp, NV, ET, CPLX>(s, h, dre, dim, x, ldx, y, ldy, nvec, row0, lds, (sched & QSD_SCHED_SLOT_ORDER) != 0,
-                                   (sched & QSD_SCHED_LOCKSTEP) != 0, (sched & QSD_SCHED_FILTER_FIRST) != 0);
+                                   (sched & QSD_SCHED_LOCKSTEP) != 0, (sched & QSD_SCHED_FILTER_FIRST) != 0,
+                                   split_diag<ET>(sched));
 }
 
 // ---------------------------------------------------------------------------------- CSR
@@ -248,6 +257,9 @@ void launch_mv(const qsd_ham *h, const void *x, int64_t ldx, void *y, int64_t ld
     const bool f32 = std::is_same<ET, float>::value;
     const ET *dre = f32 ? (const ET *)h->diag32 : (const ET *)h->diag;
     const ET *dim = CPLX ? (f32 ? (const ET *)h->diag32_im : (const ET *)h->diag_im) : nullptr;
+    if (split_diag<ET>(h->schedule))
+        k_diag_apply<CPLX><<<grid_for(h->N, 256), 256, 0, st>>>(h->diag, h->diag_im, (const double *)x, ldx, (double *)y,
+                                                                ldy, nvec, h->N);
     k_matvec<Wp, NV, ET, CPLX><<<grid_for(h->N, kBlock), kBlock, 0, st>>>(sview(h->s), view_of(h, f32), dre, dim,
                                                                           (const ET *)x, ldx, (ET *)y, ldy, nvec,
                                                                           h->schedule);

@@ -45,39 +45,91 @@ __device__ __forceinline__ int64_t load_row(const SubView &s, int64_t row0, uint
     return p;
 }
 
+// The diagonal term d_r x_r in FP64, with the same operations wherever it is formed.
+template <bool CPLX>
+__device__ __forceinline__ void diag_term(double dr, double di, double xr, double xi, double &re, double &im) {
+    if (CPLX) {
+        re = fma(dr, xr, -(di * xi));
+        im = fma(dr, xi, di * xr);
+    } else {
+        re = dr * xr;
+        im = 0.0;
+    }
+}
+
+// y[r] = d_r x[r] for every row and vector: the first pass of the split SpMV, whose second pass
+// (matvec_block with `split`) adds the off-diagonal sums to the rows that have any.  Only for
+// FP64 elements, where y holds the FP64 accumulator exactly.
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_diag_apply(const double *__restrict__ dre, const double *__restrict__ dim,
+                                                    const double *__restrict__ x, int64_t ldx, double *__restrict__ y,
+                                                    int64_t ldy, int nvec, int64_t N) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= N) return;
+    const double dr = dre[r], di = CPLX ? dim[r] : 0.0;
+    for (int v = 0; v < nvec; ++v) {
+        double re, im;
+        if (CPLX) {
+            diag_term<true>(dr, di, x[2 * (r * ldx + v)], x[2 * (r * ldx + v) + 1], re, im);
+            y[2 * (r * ldy + v)] = re;
+            y[2 * (r * ldy + v) + 1] = im;
+        } else {
+            diag_term<false>(dr, 0.0, x[r * ldx + v], 0.0, re, im);
+            y[r * ldy + v] = re;
+        }
+    }
+}
+
 // y[r] = d_r x[r] + sum over the row's present elements of H_rj x[j] for the rows at positions
 // row0 .. row0+255 (of the canonical order, or of the slot order with `by_slot`), all `nvec`
-// interleaved vectors; FP64 accumulation in group order.
+// interleaved vectors; FP64 accumulation in group order.  With `split` (FP64 only) y already
+// holds d_r x[r] (k_diag_apply): a row reads it back at its first off-diagonal element and
+// writes y only if it has one, so rows without elements cost no random access to x, d or y.
+// Either way the sum is formed with the same operations in the same order.
 template <int Wp, int NV, class ET, bool CPLX>
 __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h, const ET *__restrict__ dre,
                                              const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
                                              ET *__restrict__ y, int64_t ldy, int nvec, int64_t row0,
                                              ChunkLds<Wp> &lds, bool by_slot = false, bool lockstep = false,
-                                             bool filter_first = false) {
+                                             bool filter_first = false, bool split = false) {
     uint64_t key[Wp], hrow;
     bool valid;
     const int64_t r = load_row<Wp>(s, row0, key, hrow, valid, by_slot);
     double acc_re[NV], acc_im[NV];
-    {
+    bool have = !split;  // acc holds d_r x[r] (+ the elements so far)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc_re[v] = acc_im[v] = 0.0;
+    if (!split) {
         const double dr = (double)dre[r];
         const double di = CPLX ? (double)dim[r] : 0.0;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            acc_re[v] = acc_im[v] = 0.0;
             if (v < nvec) {
-                if (CPLX) {
-                    const double xr = (double)x[2 * (r * ldx + v)], xi = (double)x[2 * (r * ldx + v) + 1];
-                    acc_re[v] = dr * xr - di * xi;
-                    acc_im[v] = dr * xi + di * xr;
-                } else {
-                    acc_re[v] = dr * (double)x[r * ldx + v];
-                }
+                if (CPLX)
+                    diag_term<true>(dr, di, (double)x[2 * (r * ldx + v)], (double)x[2 * (r * ldx + v) + 1], acc_re[v],
+                                    acc_im[v]);
+                else
+                    diag_term<false>(dr, 0.0, (double)x[r * ldx + v], 0.0, acc_re[v], acc_im[v]);
             }
         }
     }
     row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t j, uint32_t t0, uint32_t len) {
         ET vre, vim;
         if (!range_value<Wp, ET>(h, key, t0, len, vre, vim)) return;
+        if (!have) {
+            have = true;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                if (v < nvec) {
+                    if (CPLX) {
+                        acc_re[v] = (double)y[2 * (r * ldy + v)];
+                        acc_im[v] = (double)y[2 * (r * ldy + v) + 1];
+                    } else {
+                        acc_re[v] = (double)y[r * ldy + v];
+                    }
+                }
+            }
+        }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if (v < nvec) {
@@ -91,7 +143,7 @@ __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h,
             }
         }
     }, nullptr, lockstep, filter_first);
-    if (!valid) return;
+    if (!valid || !have) return;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         if (v < nvec) {
