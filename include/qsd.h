@@ -49,7 +49,7 @@ extern "C" {
 #define QSD_ERR_NOT_HERMITIAN (-5) /* QSD_OP_CHECK_HERMITIAN failed */
 #define QSD_ERR_NOT_CONVERGED (-6) /* Lanczos stopped at max_iter; outputs hold the best estimate */
 #define QSD_ERR_DTYPE (-7)         /* dtype does not match the operator (real vs complex) */
-#define QSD_ERR_UNSUPPORTED (-8)   /* a valid request outside what this build implements */
+#define QSD_ERR_UNSUPPORTED (-8)   /* a valid request outside what the library implements */
 
 /* ----------------------------------------------------------------- value types */
 #define QSD_F64 0  /* double */
@@ -109,7 +109,7 @@ int qsd_version(void);
 int qsd_subspace_build(const uint64_t *d_bits, int64_t n_in, int32_t n_qubits, uint32_t flags, double max_load,
                        void *stream, qsd_subspace **out);
 
-/* Largest n_qubits this build supports. */
+/* Largest n_qubits the library supports. */
 int32_t qsd_max_qubits(void);
 
 /* Sizes of a built subspace: N unique strings, n_qubits, W words per string, hash capacity
