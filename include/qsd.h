@@ -236,6 +236,9 @@ int qsd_ham_diag_splitting(const qsd_ham *h, double *lowest, double *splitting, 
  *   QSD_SCHED_FILTER_FIRST  a lane first reads the occupancy bits of all its live groups'
  *                         home slots (8 loads in flight), then the slots of the occupied ones
  *                         (4 in flight), instead of reading bit and slot group by group.
+ * A new operator starts with XCD_REMAP | FILTER_FIRST (faster than the plain schedule on every
+ * workload measured; slot order pays off when most probes miss, which qsd_ham_autotune finds).
+ * The batched entries (qsd_batch_*, qsd_matvec_batched) use each operator's schedule too.
  * qsd_ham_set_schedule sets the bits (INVALID_ARG for unknown bits). */
 #define QSD_SCHED_XCD_REMAP 1u
 #define QSD_SCHED_SLOT_ORDER 2u

@@ -204,8 +204,11 @@ __global__ __launch_bounds__(kThreads) void kbl_scale(const double *src, double 
 // column of R^-1 are zero, so that column of the next block is zero and stays zero; its indices
 // in T are marked dead (decoupled, masked in the Ritz solve).  When every column vanishes the
 // basis spans an invariant subspace: flag[0] = k + 1 (T is exact).  A pivot that is small only
-// relative to the block (near dependence, beyond what Cholesky QR resolves) stops the run:
-// flag[1] = k + 1 (-1 for the start block).
+// relative to the block (near dependence, beyond what Cholesky QR resolves: squared norm <= 1e-14
+// of the block's largest) is deflated the same way at step k; the direction dropped is below 1e-7
+// of the block's largest column, so the Ritz values stay Rayleigh quotients over an orthonormal
+// basis and the run continues with the remaining columns.  In the start block it is an error:
+// flag[1] = -1.
 template <int B>
 __global__ void kbl_chol(const double *__restrict__ G, int mode, const int *__restrict__ kdev, double *__restrict__ Rm,
                          double *__restrict__ A, double *__restrict__ Tb, double *__restrict__ dead,
@@ -259,11 +262,8 @@ __global__ void kbl_chol(const double *__restrict__ G, int mode, const int *__re
     }
     if (mode <= 1) {
         if (near_dep || nlive == 0) flag[1] = -1.0;
-    } else if (flag[0] == 0.0 && flag[1] == 0.0) {
-        if (nlive == 0 && !near_dep)
-            flag[0] = (double)(k + 1);
-        else if (near_dep)
-            flag[1] = (double)(k + 1);
+    } else if (flag[0] == 0.0 && flag[1] == 0.0 && nlive == 0 && !near_dep) {
+        flag[0] = (double)(k + 1);
     }
     double *Rout = Rm + (mode & 1) * (B * B);
     for (int p = 0; p < B; ++p)

@@ -163,7 +163,8 @@ struct qsd_ham {
     int64_t G = 0;   // off-diagonal groups
     int32_t Wp = 0;
     bool is_complex = false;
-    uint32_t schedule = 0;  // QSD_SCHED_* bits of the SpMV launch (results do not depend on it)
+    // QSD_SCHED_* bits of the SpMV launch (results do not depend on it)
+    uint32_t schedule = QSD_SCHED_XCD_REMAP | QSD_SCHED_FILTER_FIRST;
     double *diag = nullptr;       // [N] real part (FP64)
     double *diag_im = nullptr;    // [N] imaginary part (complex operators only)
     uint64_t *g_mask = nullptr;

@@ -119,8 +119,31 @@ __global__ void k_fill0_u64(unsigned long long *p, int64_t n) {
         p[i] = 0ull;
 }
 
+// One stored entry's contribution to the row sums of `nvec` vectors.
+template <int NV, class ET, bool CPLX>
+__device__ __forceinline__ void csr_term(double vr, double vi, int64_t c, const ET *__restrict__ x, int64_t ldx,
+                                         int nvec, double (&are)[NV], double (&aim)[NV]) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (v < nvec) {
+            if (CPLX) {
+                const double xr = (double)x[2 * (c * ldx + v)], xi = (double)x[2 * (c * ldx + v) + 1];
+                are[v] += vr * xr - vi * xi;
+                aim[v] += vr * xi + vi * xr;
+            } else {
+                are[v] += vr * (double)x[c * ldx + v];
+            }
+        }
+    }
+}
+
+constexpr int kCsrBatch = 4;  // stored entries in flight per lane
+
 // y[r] = sum over the row's entries of A_rc x[c] for `nvec` interleaved vectors; LPR lanes per
-// row (consecutive lanes of one wave), FP64 accumulation, fixed reduction tree.
+// row (consecutive lanes of one wave), FP64 accumulation, fixed reduction tree.  A lane takes
+// entries a + sub, a + sub + LPR, ... in order, kCsrBatch at a time: the column indices and values
+// are streamed once (non-temporal loads, so they do not evict x from the caches) and the x gathers
+// of a batch are all in flight together.
 template <int LPR, int NV, class IT, class ET, bool CPLX>
 __global__ __launch_bounds__(256) void k_csr_spmv(const int64_t *__restrict__ indptr, const IT *__restrict__ idx,
                                                  const ET *__restrict__ val, int64_t N, const ET *__restrict__ x,
@@ -133,52 +156,28 @@ __global__ __launch_bounds__(256) void k_csr_spmv(const int64_t *__restrict__ in
     if (row < N) {
         const int64_t a = indptr[row], b = indptr[row + 1];
         int64_t e = a + sub;
-        // two entries per lane in flight
-        for (; e + LPR < b; e += 2 * LPR) {
-            const int64_t c0 = (int64_t)idx[e], c1 = (int64_t)idx[e + LPR];
-            if (CPLX) {
-                const double r0 = (double)val[2 * e], i0 = (double)val[2 * e + 1];
-                const double r1 = (double)val[2 * (e + LPR)], i1 = (double)val[2 * (e + LPR) + 1];
+        for (; e + (kCsrBatch - 1) * LPR < b; e += kCsrBatch * LPR) {
+            int64_t c[kCsrBatch];
+            double vr[kCsrBatch], vi[kCsrBatch];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    if (v < nvec) {
-                        const double x0r = (double)x[2 * (c0 * ldx + v)], x0i = (double)x[2 * (c0 * ldx + v) + 1];
-                        const double x1r = (double)x[2 * (c1 * ldx + v)], x1i = (double)x[2 * (c1 * ldx + v) + 1];
-                        are[v] += r0 * x0r - i0 * x0i;
-                        aim[v] += r0 * x0i + i0 * x0r;
-                        are[v] += r1 * x1r - i1 * x1i;
-                        aim[v] += r1 * x1i + i1 * x1r;
-                    }
-                }
-            } else {
-                const double v0 = (double)val[e], v1 = (double)val[e + LPR];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    if (v < nvec) {
-                        are[v] += v0 * (double)x[c0 * ldx + v];
-                        are[v] += v1 * (double)x[c1 * ldx + v];
-                    }
+            for (int k = 0; k < kCsrBatch; ++k) {
+                const int64_t ek = e + (int64_t)k * LPR;
+                c[k] = (int64_t)__builtin_nontemporal_load(&idx[ek]);
+                if (CPLX) {
+                    vr[k] = (double)__builtin_nontemporal_load(&val[2 * ek]);
+                    vi[k] = (double)__builtin_nontemporal_load(&val[2 * ek + 1]);
+                } else {
+                    vr[k] = (double)__builtin_nontemporal_load(&val[ek]);
+                    vi[k] = 0.0;
                 }
             }
+#pragma unroll
+            for (int k = 0; k < kCsrBatch; ++k) csr_term<NV, ET, CPLX>(vr[k], vi[k], c[k], x, ldx, nvec, are, aim);
         }
-        if (e < b) {
+        for (; e < b; e += LPR) {
             const int64_t c0 = (int64_t)idx[e];
-            if (CPLX) {
-                const double r0 = (double)val[2 * e], i0 = (double)val[2 * e + 1];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    if (v < nvec) {
-                        const double x0r = (double)x[2 * (c0 * ldx + v)], x0i = (double)x[2 * (c0 * ldx + v) + 1];
-                        are[v] += r0 * x0r - i0 * x0i;
-                        aim[v] += r0 * x0i + i0 * x0r;
-                    }
-                }
-            } else {
-                const double v0 = (double)val[e];
-#pragma unroll
-                for (int v = 0; v < NV; ++v)
-                    if (v < nvec) are[v] += v0 * (double)x[c0 * ldx + v];
-            }
+            const double r0 = (double)val[CPLX ? 2 * e : e], i0 = CPLX ? (double)val[2 * e + 1] : 0.0;
+            csr_term<NV, ET, CPLX>(r0, i0, c0, x, ldx, nvec, are, aim);
         }
     }
 #pragma unroll

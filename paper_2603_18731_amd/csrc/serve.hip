@@ -40,6 +40,7 @@ struct ReqDev {
     const int32_t *cidx;
     const void *cval;
     int lpr;
+    uint32_t sched;  // the operator's QSD_SCHED_* bits (row order and probe mode)
 };
 
 struct Tile {
@@ -81,7 +82,10 @@ __global__ __launch_bounds__(kBlock) void kb_matvec(const ReqDev *__restrict__ r
         }
         return;
     }
-    matvec_block<Wp, 1, ET, false>(R.s, R.h, dre, nullptr, x, 1, y, 1, 1, (int64_t)t.idx * kBlock, lds);
+    // the operator's schedule, with the diagonal term formed in the row kernel (no separate pass)
+    matvec_block<Wp, 1, ET, false>(R.s, R.h, dre, nullptr, x, 1, y, 1, 1, (int64_t)t.idx * kBlock, lds,
+                                   (R.sched & QSD_SCHED_SLOT_ORDER) != 0, (R.sched & QSD_SCHED_LOCKSTEP) != 0,
+                                   (R.sched & QSD_SCHED_FILTER_FIRST) != 0);
 }
 
 // x32 = x (to_f32) or w = w32 (back), over 2048-row tiles
@@ -327,8 +331,9 @@ struct MvReq {
     const void *dre, *dim;
     const void *x;
     void *y;
-    int64_t ld;  // leading dimension of x and y (the request's vector count)
-    int nv;      // vectors of this launch (at most the template width)
+    int64_t ld;      // leading dimension of x and y (the request's vector count)
+    int nv;          // vectors of this launch (at most the template width)
+    uint32_t sched;  // the operator's QSD_SCHED_* bits (row order and probe mode)
 };
 
 template <int Wp, int NV, class ET, bool CPLX>
@@ -337,7 +342,8 @@ __global__ __launch_bounds__(kBlock) void kbm_matvec(const MvReq *__restrict__ r
     const Tile t = tiles[blockIdx.x];
     const MvReq &R = reqs[t.slot];
     matvec_block<Wp, NV, ET, CPLX>(R.s, R.h, (const ET *)R.dre, (const ET *)R.dim, (const ET *)R.x, R.ld, (ET *)R.y,
-                                   R.ld, R.nv, (int64_t)t.idx * kBlock, lds);
+                                   R.ld, R.nv, (int64_t)t.idx * kBlock, lds, (R.sched & QSD_SCHED_SLOT_ORDER) != 0,
+                                   (R.sched & QSD_SCHED_LOCKSTEP) != 0, (R.sched & QSD_SCHED_FILTER_FIRST) != 0);
 }
 
 }  // namespace
@@ -533,6 +539,7 @@ int add_impl(qsd_batch *b, const qsd_ham *h, const qsd_csr *c, int32_t v0_mode, 
         d.h = ham_view(h, b->f32);
         d.diag = h->diag;
         d.diag32 = h->diag32;
+        d.sched = h->schedule;
     } else {
         d.diag = c->diag;
         d.cptr = c->indptr;
@@ -776,6 +783,7 @@ extern "C" int qsd_matvec_batched(int32_t n, const qsd_ham *const *hams, const v
                 R.y = (char *)ys[i] + c0 * esz;
                 R.ld = nvecs[i];
                 R.nv = std::min(chunk, nvecs[i] - c0);
+                R.sched = h->schedule;
                 L.nv_max = std::max(L.nv_max, R.nv);
                 const int slot = (int)reqs.size();
                 reqs.push_back(R);

@@ -47,6 +47,12 @@ def _case(case):
 
         keys = osub.ints_to_keys(sorted(rng.choice(1 << n, size=5000, replace=False).tolist()), 1)
         return _ham(keys, tl)
+    if case == "diagonal":
+        # no off-diagonal groups: the slot-order schedules write y from the diagonal pass alone
+        n = 12
+        tl = wl.TermList.from_terms(n, [(-1.0 - 0.25 * i, [(i, 0), ((i + 1) % n, 0)]) for i in range(n)]
+                                    + [(0.5, [(0, 2)])])
+        return _ham(wl.c1_tfim12().keys[::3].copy(), tl)
     tl, keys = heavy_hex_small(30_001)
     return _ham(keys, tl)
 
@@ -64,7 +70,7 @@ def _run_all(H, x):
     return outs
 
 
-@pytest.mark.parametrize("case", ["xxz", "fermi", "heavyhex", "complex"])
+@pytest.mark.parametrize("case", ["xxz", "fermi", "heavyhex", "complex", "diagonal"])
 def test_schedules_bitwise(case):
     H = _case(case)
     rng = np.random.default_rng(3)
@@ -77,6 +83,8 @@ def test_schedules_bitwise(case):
     assert not torch.isnan(outs[0]).any()
     for o in outs[1:]:
         assert torch.equal(o, outs[0])
+    if case == "diagonal":
+        assert torch.equal(outs[0], H.diagonal()[:, None] * x)
     if not H.is_complex:
         # single precision and one vector, through the slot-order lockstep schedule
         x32 = x[:, :1].float().contiguous()
@@ -96,3 +104,29 @@ def test_schedules_bitwise(case):
         assert torch.equal(H.subspace.lookup(keys_before), torch.arange(H.N, device="cuda"))
     with pytest.raises(qsd.QsdError, match="INVALID_ARG"):
         H.schedule = 0x80
+
+
+@pytest.mark.parametrize("case", ["xxz", "heavyhex", "complex"])
+def test_solvers_under_slot_order_schedules(case):
+    """Lanczos (plain, HIP-graph replay, FP32 SpMV) and block Lanczos give the same energies under
+    the slot-order lockstep schedule (two kernels per FP64 SpMV) as under the canonical one."""
+    H = _case(case)
+    res = {}
+    side = torch.cuda.Stream()  # graph capture needs a non-default stream
+    for sched in (0, qsd.SCHED_ALL):
+        H.schedule = sched
+        e, _, info = H.lanczos(tol=1e-10, max_iter=400)
+        with torch.cuda.stream(side):
+            eg, _, _ = H.lanczos(tol=1e-10, max_iter=400, use_graph=True)
+        torch.cuda.synchronize()
+        r = [e, eg]
+        if not H.is_complex:
+            e32, _, _ = H.lanczos(tol=1e-6, max_iter=400, spmv_dtype="f32")
+            eb, _, _ = H.lanczos(tol=1e-9, max_iter=60, block=4)
+            r += [e32, eb]
+        res[sched] = r
+        say(case, "schedule", sched, r, info["iterations"])
+    for a, b in zip(res[0], res[qsd.SCHED_ALL]):
+        assert abs(a - b) <= 1e-9 * abs(a)
+    assert res[0][0] == res[0][1]  # graph replay runs the same kernels
+    assert res[qsd.SCHED_ALL][0] == res[qsd.SCHED_ALL][1]
