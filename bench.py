@@ -251,6 +251,55 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def precision_compare(args):
+    """FP64 vs FP32 SpMV (FP32 elements and vectors, FP64 row accumulation) on one workload: the
+    SpMV time of each (autotuned separately), and the ground-state energy of single-vector and
+    block-8 Lanczos with either SpMV (orthogonalization, the tridiagonal solve and the residual
+    test stay FP64), with the FP32 energy's relative difference from the FP64 one."""
+    import numpy as np
+    import torch
+
+    import paper_2603_18731_amd as qsd
+
+    torch.cuda.set_device(0)
+    w = make_workload(args.workload)
+    sub = qsd.Subspace(w.keys, w.ops.n_qubits)
+    H = qsd.SubspaceHamiltonian(sub, qsd.operator_from_termlist(w.ops))
+    st = torch.cuda.current_stream()
+    out = {"workload": w.name, "N": sub.N}
+    for dt, name in ((torch.float64, "f64"), (torch.float32, "f32")):
+        tune = H.autotune(nvec=1, dtype=dt, reps=2)
+        x = torch.rand(sub.N, dtype=dt, device="cuda")
+        y = torch.empty_like(x)
+        H.matvec(x, out=y)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+        for a, b in ev:
+            a.record(st)
+            H.matvec(x, out=y)
+            b.record(st)
+        torch.cuda.synchronize()
+        out["spmv_ms_" + name] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        out["autotune_" + name] = tune
+        for block in (1, 8):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, _, info = H.lanczos(tol=1e-10 if name == "f64" else 1e-7, max_iter=300 if block == 1 else 80,
+                                   v0="uniform", spmv_dtype=name, block=block, raise_on_nonconv=False)
+            key = "%s_b%d" % (name, block)
+            out["energy_" + key] = e
+            out["solve_s_" + key] = time.perf_counter() - t0
+            out["iterations_" + key] = info["iterations"]
+            out["converged_" + key] = bool(info["converged"])
+            print("# %s: %s SpMV %.3f ms, block %d: %.12f in %.3f s (%d steps)" % (
+                w.name, name, out["spmv_ms_" + name], block, e, out["solve_s_" + key], info["iterations"]),
+                file=sys.stderr, flush=True)
+    for block in (1, 8):
+        e64 = out["energy_f64_b%d" % block]
+        out["energy_rel_err_f32_b%d" % block] = abs(out["energy_f32_b%d" % block] - e64) / abs(e64)
+    print(json.dumps({"precision_compare": out}), flush=True)
+
+
 def csr_compare(args):
     """Matrix-free vs stored-CSR solve on one workload: CSR build time (two-pass and
     lower-triangle), device memory, SpMV time of both operators, Lanczos time and energy."""
@@ -392,6 +441,7 @@ def main():
                     "diagonal string; trimmed vs full ground energy")
     ap.add_argument("--ramps-depth", type=int, default=16)
     ap.add_argument("--csr-compare", action="store_true", help="matrix-free vs stored-CSR solve on --workload")
+    ap.add_argument("--precision", action="store_true", help="FP64 vs FP32 SpMV and solves on --workload")
     ap.add_argument("--serve", action="store_true", help="serving benchmark: batched Lanczos requests with "
                     "Poisson arrivals against the FIFO single-vector solver")
     ap.add_argument("--serve-requests", type=int, default=256)
@@ -404,6 +454,9 @@ def main():
             print("bench.py measures one GPU only (requested --gpus %d)" % args.gpus, file=sys.stderr)
             sys.exit(2)
         ramps_bench(args)
+        return
+    if args.precision:
+        precision_compare(args)
         return
     if args.csr_compare:
         if args.gpus != 1:
