@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2603_18731_amd/csrc/engine.h", "paper_2603_18731_amd/csrc/matvec.h",
                   "paper_2603_18731_amd/csrc/device.h"]
 # the SpMV kernels and their launch in ham.hip (the rest of that file is host code)
-KERNEL_FUNCTIONS = ("paper_2603_18731_amd/csrc/ham.hip", ("inline bool split_diag(", "void k_matvec(", "void launch_mv("))
+KERNEL_FUNCTIONS = ("paper_2603_18731_amd/csrc/ham.hip", ("void k_matvec(", "void launch_mv("))
 
 
 def kernel_digest():
@@ -519,8 +519,6 @@ def main():
     else:
         H.schedule = int(args.schedule)
     sched = H.schedule
-    # FP64 slot-order schedules run the SpMV as two kernels: the diagonal pass, then the rows
-    split = args.dtype == "f64" and bool(sched & qsd.SCHED_SLOT_ORDER)
     setup_s = time.perf_counter() - t_setup
     print("# setup %.1f s: N=%d nnz=%d probes=%d hits=%d groups=%d" % (setup_s, N, nnz, probes, hits, op.n_groups),
           file=sys.stderr, flush=True)
@@ -566,7 +564,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n_qubits": w.ops.n_qubits, "subspace_dim": N, "nnz": nnz,
                    "groups": op.n_groups, "terms": op.n_terms, "nvec": args.nvec,
-                   "kernel": "k_diag_apply + k_matvec" if split else "k_matvec",
+                   "kernel": "k_matvec",
                    "schedule": sched, "hash_capacity": sub.capacity, "autotune": tune},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -229,6 +229,11 @@ int qsd_ham_diag_splitting(const qsd_ham *h, double *lowest, double *splitting, 
  *                         listed by the position of their slot in the hash table, kept with the
  *                         table) instead of the canonical order.  The hash is linear, so the
  *                         columns b ^ M_g of rows whose slots are neighbours are neighbours too.
+ *                         The launch then also writes y = d x, in canonical order, for the rows
+ *                         without off-diagonal elements, and the slot-order rows write only the
+ *                         rows that have some (per-row bits built once per operator, N / 8
+ *                         bytes, by the first qsd_ham_set_schedule or qsd_ham_autotune call that
+ *                         needs them; that call synchronizes).
  *   QSD_SCHED_LOCKSTEP    the 64 lanes of a wave probe the same group in the same instruction
  *                         (lanes whose row does not have it live sit idle) instead of each lane
  *                         walking its own live groups; with SLOT_ORDER the wave's occupancy-bit

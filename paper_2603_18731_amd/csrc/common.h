@@ -180,6 +180,8 @@ struct qsd_ham {
     float *t_coef32 = nullptr;    // [To][2]
     float *diag32 = nullptr;      // [N]
     float *diag32_im = nullptr;
+    // [ceil(N / 64)] bit r = row r has an off-diagonal element; built for the slot-order schedules
+    uint64_t *rowbits = nullptr;
 };
 
 struct qsd_csr {

@@ -47,23 +47,43 @@ __global__ void k_to_f32(const double *__restrict__ in, float *__restrict__ out,
 
 // ------------------------------------------------------------------------------- matvec
 
-// Rows in slot order touch x, d and y at random positions; with FP64 elements the diagonal
-// term goes to a streaming first pass instead (k_diag_apply), and only rows with off-diagonal
-// elements touch y again.
-template <class ET>
-__host__ __device__ inline bool split_diag(uint32_t sched) {
-    return std::is_same<ET, double>::value && (sched & QSD_SCHED_SLOT_ORDER) != 0;
-}
-
+// Rows in slot order touch x, d and y at random positions.  With a slot-order schedule the launch
+// is split by role: the first `nd` workgroups (a multiple of 8, so the XCD of a workgroup is still
+// its index mod 8) write y = d x for the rows without off-diagonal elements in canonical order,
+// the rest take the slot-order tiles and write only the rows with elements; no row is written
+// twice, and each row's value is formed with the same operations as in every other schedule.
 template <int Wp, int NV, class ET, bool CPLX>
 __global__ __launch_bounds__(kBlock) void k_matvec(SubView s, HamView h, const ET *__restrict__ dre,
                                                    const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
-                                                   ET *__restrict__ y, int64_t ldy, int nvec, uint32_t sched) {
+                                                   ET *__restrict__ y, int64_t ldy, int nvec, uint32_t sched,
+                                                   const uint64_t *__restrict__ rowbits, unsigned nd) {
     __shared__ ChunkLds<Wp> lds;
-    const int64_t row0 = tile_index(blockIdx.x, gridDim.x, (sched & QSD_SCHED_XCD_REMAP) != 0) * kBlock;
+    if (blockIdx.x < nd) {
+        diag_rows_block<NV, ET, CPLX>(dre, dim, x, ldx, y, ldy, nvec, s.N, rowbits, (int64_t)blockIdx.x * kBlock);
+        return;
+    }
+    const int64_t row0 = tile_index(blockIdx.x - nd, gridDim.x - nd, (sched & QSD_SCHED_XCD_REMAP) != 0) * kBlock;
     matvec_block<Wp, NV, ET, CPLX>(s, h, dre, dim, x, ldx, y, ldy, nvec, row0, lds, (sched & QSD_SCHED_SLOT_ORDER) != 0,
-                                   (sched & QSD_SCHED_LOCKSTEP) != 0, (sched & QSD_SCHED_FILTER_FIRST) != 0,
-                                   split_diag<ET>(sched));
+                                   (sched & QSD_SCHED_LOCKSTEP) != 0, (sched & QSD_SCHED_FILTER_FIRST) != 0, nd > 0);
+}
+
+// Bit r of `bits` = row r has an off-diagonal element (a probe whose column is present and
+// whose term range has a term passing the row's projector bits).
+template <int Wp>
+__global__ __launch_bounds__(kBlock) void k_row_bits(SubView s, HamView h, uint64_t *__restrict__ bits) {
+    __shared__ ChunkLds<Wp> lds;
+    uint64_t key[Wp], hrow;
+    bool valid;
+    const int64_t row0 = (int64_t)blockIdx.x * kBlock;
+    load_row<Wp>(s, row0, key, hrow, valid);
+    bool has = false;
+    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t, uint32_t t0, uint32_t len) {
+        double vre, vim;
+        if (range_value<Wp, double>(h, key, t0, len, vre, vim)) has = true;
+    });
+    const uint64_t w = __ballot(has && valid);
+    const int64_t word = (row0 >> 6) + (threadIdx.x >> 6);
+    if ((threadIdx.x & 63) == 0 && word * 64 < s.N) bits[word] = w;
 }
 
 // ---------------------------------------------------------------------------------- CSR
@@ -199,6 +219,7 @@ void free_ham(qsd_ham *h) {
     dev_free(h->t_coef32);
     dev_free(h->diag32);
     dev_free(h->diag32_im);
+    dev_free(h->rowbits);
     delete h;
 }
 
@@ -257,12 +278,11 @@ void launch_mv(const qsd_ham *h, const void *x, int64_t ldx, void *y, int64_t ld
     const bool f32 = std::is_same<ET, float>::value;
     const ET *dre = f32 ? (const ET *)h->diag32 : (const ET *)h->diag;
     const ET *dim = CPLX ? (f32 ? (const ET *)h->diag32_im : (const ET *)h->diag_im) : nullptr;
-    if (split_diag<ET>(h->schedule))
-        k_diag_apply<CPLX><<<grid_for(h->N, 256), 256, 0, st>>>(h->diag, h->diag_im, (const double *)x, ldx, (double *)y,
-                                                                ldy, nvec, h->N);
-    k_matvec<Wp, NV, ET, CPLX><<<grid_for(h->N, kBlock), kBlock, 0, st>>>(sview(h->s), view_of(h, f32), dre, dim,
-                                                                          (const ET *)x, ldx, (ET *)y, ldy, nvec,
-                                                                          h->schedule);
+    const unsigned tiles = grid_for(h->N, kBlock);
+    const bool split = (h->schedule & QSD_SCHED_SLOT_ORDER) && h->rowbits;
+    const unsigned nd = split ? (tiles + 7u) & ~7u : 0u;
+    k_matvec<Wp, NV, ET, CPLX><<<nd + tiles, kBlock, 0, st>>>(sview(h->s), view_of(h, f32), dre, dim, (const ET *)x, ldx,
+                                                             (ET *)y, ldy, nvec, h->schedule, h->rowbits, nd);
 }
 
 template <int Wp, class ET, bool CPLX>
@@ -549,10 +569,38 @@ extern "C" int qsd_ham_diag_splitting(const qsd_ham *h, double *lowest, double *
     return QSD_OK;
 }
 
+namespace qsd {
+namespace {
+
+// The per-row bits that the slot-order schedules split the SpMV by (built once per operator).
+int ensure_rowbits(qsd_ham *h, hipStream_t st) {
+    if (h->rowbits || h->N == 0) return QSD_OK;
+    uint64_t *bits = nullptr;
+    QSD_TRY(dev_alloc(&bits, (size_t)((h->N + 63) / 64)));
+    const unsigned g = grid_for(h->N, kBlock);
+    switch (h->Wp) {
+        case 1: k_row_bits<1><<<g, kBlock, 0, st>>>(sview(h->s), view_of(h, false), bits); break;
+        case 2: k_row_bits<2><<<g, kBlock, 0, st>>>(sview(h->s), view_of(h, false), bits); break;
+        case 4: k_row_bits<4><<<g, kBlock, 0, st>>>(sview(h->s), view_of(h, false), bits); break;
+        case 8: k_row_bits<8><<<g, kBlock, 0, st>>>(sview(h->s), view_of(h, false), bits); break;
+        case 16: k_row_bits<16><<<g, kBlock, 0, st>>>(sview(h->s), view_of(h, false), bits); break;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) {
+        dev_free(bits);
+        return fail(QSD_ERR_HIP, "row bits failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    h->rowbits = bits;
+    return QSD_OK;
+}
+
+}  // namespace
+}  // namespace qsd
+
 extern "C" int qsd_ham_set_schedule(qsd_ham *h, uint32_t schedule) {
     clear_error();
     if (!h) return fail(QSD_ERR_INVALID_ARG, "NULL handle");
     if (schedule & ~kSchedAll) return fail(QSD_ERR_INVALID_ARG, "unknown schedule bits 0x%x", schedule);
+    if (schedule & QSD_SCHED_SLOT_ORDER) QSD_TRY(ensure_rowbits(h, nullptr));
     h->schedule = schedule;
     return QSD_OK;
 }
@@ -593,6 +641,7 @@ extern "C" int qsd_ham_autotune(qsd_ham *h, int32_t nvec, int32_t dtype, int32_t
         ms_out /= reps;
         return QSD_OK;
     };
+    if (rc == QSD_OK && (flags & QSD_TUNE_SCHEDULE)) rc = ensure_rowbits(h, st);
     const uint32_t sched0 = h->schedule;
     const int64_t C0 = sub->C;
     float ms_before = INFINITY, best_ms = INFINITY;

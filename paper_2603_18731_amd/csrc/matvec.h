@@ -57,35 +57,39 @@ __device__ __forceinline__ void diag_term(double dr, double di, double xr, doubl
     }
 }
 
-// y[r] = d_r x[r] for every row and vector: the first pass of the split SpMV, whose second pass
-// (matvec_block with `split`) adds the off-diagonal sums to the rows that have any.  Only for
-// FP64 elements, where y holds the FP64 accumulator exactly.
-template <bool CPLX>
-__global__ __launch_bounds__(256) void k_diag_apply(const double *__restrict__ dre, const double *__restrict__ dim,
-                                                    const double *__restrict__ x, int64_t ldx, double *__restrict__ y,
-                                                    int64_t ldy, int nvec, int64_t N) {
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r >= N) return;
-    const double dr = dre[r], di = CPLX ? dim[r] : 0.0;
-    for (int v = 0; v < nvec; ++v) {
-        double re, im;
-        if (CPLX) {
-            diag_term<true>(dr, di, x[2 * (r * ldx + v)], x[2 * (r * ldx + v) + 1], re, im);
-            y[2 * (r * ldy + v)] = re;
-            y[2 * (r * ldy + v) + 1] = im;
-        } else {
-            diag_term<false>(dr, 0.0, x[r * ldx + v], 0.0, re, im);
-            y[r * ldy + v] = re;
+// Rows of rows row0 .. row0+255 (canonical order) that have no off-diagonal element (bit clear
+// in `rowbits`): y[r] = d_r x[r].  The other part of the split SpMV (matvec_block with `split`)
+// writes exactly the rows that have elements, so the two never write the same row.
+template <int NV, class ET, bool CPLX>
+__device__ __forceinline__ void diag_rows_block(const ET *__restrict__ dre, const ET *__restrict__ dim,
+                                                const ET *__restrict__ x, int64_t ldx, ET *__restrict__ y, int64_t ldy,
+                                                int nvec, int64_t N, const uint64_t *__restrict__ rowbits,
+                                                int64_t row0) {
+    const int64_t r = row0 + threadIdx.x;
+    if (r >= N || ((rowbits[r >> 6] >> (r & 63)) & 1ull)) return;
+    const double dr = (double)dre[r], di = CPLX ? (double)dim[r] : 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (v < nvec) {
+            double re, im;
+            if (CPLX) {
+                diag_term<true>(dr, di, (double)x[2 * (r * ldx + v)], (double)x[2 * (r * ldx + v) + 1], re, im);
+                y[2 * (r * ldy + v)] = (ET)re;
+                y[2 * (r * ldy + v) + 1] = (ET)im;
+            } else {
+                diag_term<false>(dr, 0.0, (double)x[r * ldx + v], 0.0, re, im);
+                y[r * ldy + v] = (ET)re;
+            }
         }
     }
 }
 
 // y[r] = d_r x[r] + sum over the row's present elements of H_rj x[j] for the rows at positions
 // row0 .. row0+255 (of the canonical order, or of the slot order with `by_slot`), all `nvec`
-// interleaved vectors; FP64 accumulation in group order.  With `split` (FP64 only) y already
-// holds d_r x[r] (k_diag_apply): a row reads it back at its first off-diagonal element and
-// writes y only if it has one, so rows without elements cost no random access to x, d or y.
-// Either way the sum is formed with the same operations in the same order.
+// interleaved vectors; FP64 accumulation in group order.  With `split` a row forms d_r x[r] at
+// its first off-diagonal element and writes y only if it has one (diag_rows_block writes the
+// others), so rows without elements cost no random access to x, d or y.  Either way the sum is
+// formed with the same operations in the same order.
 template <int Wp, int NV, class ET, bool CPLX>
 __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h, const ET *__restrict__ dre,
                                              const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
@@ -118,15 +122,16 @@ __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h,
         if (!range_value<Wp, ET>(h, key, t0, len, vre, vim)) return;
         if (!have) {
             have = true;
+            const double dr = (double)dre[r];
+            const double di = CPLX ? (double)dim[r] : 0.0;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 if (v < nvec) {
-                    if (CPLX) {
-                        acc_re[v] = (double)y[2 * (r * ldy + v)];
-                        acc_im[v] = (double)y[2 * (r * ldy + v) + 1];
-                    } else {
-                        acc_re[v] = (double)y[r * ldy + v];
-                    }
+                    if (CPLX)
+                        diag_term<true>(dr, di, (double)x[2 * (r * ldx + v)], (double)x[2 * (r * ldx + v) + 1],
+                                        acc_re[v], acc_im[v]);
+                    else
+                        diag_term<false>(dr, 0.0, (double)x[r * ldx + v], 0.0, acc_re[v], acc_im[v]);
                 }
             }
         }
