@@ -52,8 +52,10 @@ __global__ void k_to_f32(const double *__restrict__ in, float *__restrict__ out,
 // its index mod 8) write y = d x for the rows without off-diagonal elements in canonical order,
 // the rest take the slot-order tiles and write only the rows with elements; no row is written
 // twice, and each row's value is formed with the same operations as in every other schedule.
+// (Two- and four-word single-vector kernels are held to 96 registers, five waves per SIMD.)
 template <int Wp, int NV, class ET, bool CPLX>
-__global__ __launch_bounds__(kBlock) void k_matvec(SubView s, HamView h, const ET *__restrict__ dre,
+__global__ __launch_bounds__(kBlock, (Wp == 2 || Wp == 4) && NV == 1 ? 5 : 1) void k_matvec(
+    SubView s, HamView h, const ET *__restrict__ dre,
                                                    const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
                                                    ET *__restrict__ y, int64_t ldy, int nvec, uint32_t sched,
                                                    const uint64_t *__restrict__ rowbits, unsigned nd) {
