@@ -118,6 +118,8 @@ __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h,
         }
     }
     row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t j, uint32_t t0, uint32_t len) {
+        // one real vector: x_j is requested before the term loop, so that both are in flight
+        const double xj = (!CPLX && NV == 1) ? (double)x[j * ldx] : 0.0;
         ET vre, vim;
         if (!range_value<Wp, ET>(h, key, t0, len, vre, vim)) return;
         if (!have) {
@@ -143,7 +145,7 @@ __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h,
                     acc_re[v] += (double)vre * xr - (double)vim * xi;
                     acc_im[v] += (double)vre * xi + (double)vim * xr;
                 } else {
-                    acc_re[v] += (double)vre * (double)x[j * ldx + v];
+                    acc_re[v] += (double)vre * (NV == 1 ? xj : (double)x[j * ldx + v]);
                 }
             }
         }
