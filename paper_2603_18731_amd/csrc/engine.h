@@ -1,8 +1,9 @@
 // Row engine of the subspace Hamiltonian (Methods, Matrix evaluation), shared by the SpMV,
 // the CSR passes and the work counter.
 //
-// Mapping.  One lane owns one row bit-string b_i (rows are consecutive in the canonical order).
-// The off-diagonal groups are processed in chunks of kChunk = 64:
+// Mapping.  One lane owns one row bit-string b_i (rows are consecutive in the canonical order,
+// or in the order of their hash slots; the caller chooses).  The off-diagonal groups are
+// processed in chunks of kChunk = 64:
 //
 //   scan   bit-sliced over the wave's 64 rows.  The rows' keys are transposed once into bit
 //          planes (plane q = bit q of all 64 rows, one 64-bit word).  For the chunk, lane l
@@ -17,7 +18,10 @@
 //          lanes whose group happens to be live.  A probe forms hash(b_i ^ M_g) =
 //          hash(b_i) ^ hash(M_g) (the hash is linear over GF(2)), tests the occupancy bit,
 //          reads the {tag, index} slot and compares the key (Methods, Subspace data
-//          structure).
+//          structure).  Two variants change only which probes share an instruction or a
+//          batch: `lockstep` (the wave probes one group at a time) and `filter_first` (all
+//          occupancy bits of a chunk's live groups first, then the slots of the occupied ones);
+//          see row_engine.
 //   hit    the row's ladder integer selects the group's term range; the terms are refined on
 //          their projector bits and summed with popcount-parity signs; the caller's functor
 //          consumes (j, value).

@@ -93,6 +93,38 @@ def test_matvec_batched_bitwise(hams, dtype):
         assert torch.equal(y, ref)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batched_paths_follow_the_schedule(hams, dtype):
+    """The batched launches take each operator's schedule: under the slot-order lockstep schedule
+    (diagonal term formed in the row kernel) they equal the single SpMV (whose launch writes the
+    rows without elements in canonical order) and the canonical schedule bitwise, and a batched
+    solve gives bitwise the same energy."""
+    rng = np.random.default_rng(9)
+    hs = [hams["xxz20k"], hams["fermi1600"], hams["tfim12"]]
+    xs = [torch.from_numpy(rng.standard_normal((h.N, nv))).to(dtype).cuda() for h, nv in zip(hs, (1, 3, 2))]
+    before = [h.schedule for h in hs]
+    try:
+        outs, energies = {}, {}
+        for sched in (0, qsd.SCHED_ALL):
+            for h in hs:
+                h.schedule = sched
+            ys = qsd.matvec_batched(hs, xs)
+            for h, x, y in zip(hs, xs, ys):
+                assert torch.equal(y, h.matvec(x))
+            outs[sched] = ys
+            b = qsd.LanczosBatch(4, max_iter=100, spmv_dtype="f64" if dtype == torch.float64 else "f32")
+            sl = b.add(hams["xxz20k"], v0="random", seed=3)
+            b.step(25)
+            energies[sched] = b.poll()[1][sl]
+        for a, c in zip(outs[0], outs[qsd.SCHED_ALL]):
+            assert torch.equal(a, c)
+        say("batched schedules", dtype, energies)
+        assert energies[0] == energies[qsd.SCHED_ALL]
+    finally:
+        for h, sc in zip(hs, before):
+            h.schedule = sc
+
+
 def test_matvec_batched_complex():
     rng = np.random.default_rng(12)
     n = 10
