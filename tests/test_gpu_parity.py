@@ -286,9 +286,15 @@ def test_c2_full_sampled_rows():
     x = dyadic_vector(rng, sub.N)
     tld = dyadic(tl)
     Hd = qsd.SubspaceHamiltonian(sub, qsd.operator_from_termlist(tld))
-    y = Hd.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
     y_o = orw.matvec_c(ck_o, tld, x, rows).real
+    # the default launch, then the one bench.py times (load 1/32, slot order, lockstep, filter
+    # first, XCD remap: the autotuner's choice on this workload)
+    y = Hd.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
     np.testing.assert_array_equal(y[rows], y_o)
+    sub.rehash(1 / 32)
+    Hd.schedule = qsd.SCHED_ALL
+    y15 = Hd.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(y15, y)
     ip, ix, dv = _csr_gpu(Hd)
     ipo, co, vo = orw.rows_c(ck_o, tld, rows)
     for k, r in enumerate(rows[:3000]):
@@ -309,6 +315,7 @@ def test_c3_full_sampled_rows():
     rng = np.random.default_rng(9)
     rows = np.sort(rng.choice(sub.N, size=400, replace=False))
     x = dyadic_vector(rng, sub.N)
+    H.schedule = qsd.SCHED_FILTER_FIRST  # the autotuner's choice on this workload (load 1/8)
     y = H.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
     y_o = orw.matvec_c(ck_o, tl, x, rows).real
     np.testing.assert_array_equal(y[rows], y_o)
@@ -328,9 +335,16 @@ def test_c4_full_sampled_rows():
     rng = np.random.default_rng(10)
     rows = np.sort(rng.choice(sub.N, size=5000, replace=False))
     X = dyadic_vector(rng, sub.N, nvec=8)
-    Y = H.matvec(torch.from_numpy(X).cuda()).cpu().numpy()
     Y_o = orw.matvec_c(ck_o, tld, X, rows).real
+    Y = H.matvec(torch.from_numpy(X).cuda()).cpu().numpy()
     np.testing.assert_array_equal(Y[rows], Y_o)
+    # the launch bench.py times: load 1/32, slot order, lockstep, filter first, XCD remap
+    sub.rehash(1 / 32)
+    H.schedule = qsd.SCHED_ALL
+    Y15 = H.matvec(torch.from_numpy(X).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(Y15, Y)
+    y1 = H.matvec(torch.from_numpy(np.ascontiguousarray(X[:, 0])).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(y1[rows], Y_o[:, 0])
 
 
 # ---------------------------------------------------------------------------- Lanczos
