@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kBlock) void k_count_lower(SubView s, HamView h, un
         if (!range_value<Wp, double>(h, key, t0, len, vre, vim)) return;
         ++own;
         atomicAdd(&counts[j], 1ull);  // the mirrored entry (r, j) -> (j, r)
-    });
+    }, nullptr, false, true);
     if (valid) atomicAdd(&counts[r], own);
 }
 
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_lower(SubView s, HamView h, con
         vc.y = -v.y;
         cols[o2] = r;
         vals[o2] = vc;
-    });
+    }, nullptr, false, true);
 }
 
 // Sort each row's (column, value) pairs by column into the output arrays: one workgroup per

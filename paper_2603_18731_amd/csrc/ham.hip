@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_row_bits(SubView s, HamView h, uint6
     row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t, uint32_t t0, uint32_t len) {
         double vre, vim;
         if (range_value<Wp, double>(h, key, t0, len, vre, vim)) has = true;
-    });
+    }, nullptr, false, true);
     const uint64_t w = __ballot(has && valid);
     const int64_t word = (row0 >> 6) + (threadIdx.x >> 6);
     if ((threadIdx.x & 63) == 0 && word * 64 < s.N) bits[word] = w;
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_csr_count(SubView s, HamView h, int6
     row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t, uint32_t t0, uint32_t len) {
         double vre, vim;
         if (range_value<Wp, double>(h, key, t0, len, vre, vim)) ++cnt;
-    });
+    }, nullptr, false, true);
     if (valid) counts[r] = cnt;
 }
 
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_probe_count(SubView s, HamView h, un
     row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t, uint32_t t0, uint32_t len) {
         double vre, vim;
         if (range_value<Wp, double>(h, key, t0, len, vre, vim)) ++hits;
-    }, &probes);
+    }, &probes, false, true);
     for (int d = 32; d >= 1; d >>= 1) {
         probes += __shfl_xor(probes, d, 64);
         hits += __shfl_xor(hits, d, 64);
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_csr_fill(SubView s, HamView h, const
         cols[o] = j;
         vals[o] = v;
         ++o;
-    });
+    }, nullptr, false, true);
 }
 
 // Sort each row's entries by column: one workgroup per row; for rows up to kSortLds entries

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void k_ramps_level(SubView s, HamView h, co
                 n_pre[pos] = next;
             }
         }
-    });
+    }, nullptr, false, true);
 }
 
 __global__ void k_mark(const int64_t *__restrict__ idx, int64_t n, uint8_t *__restrict__ a, uint8_t *__restrict__ b) {
