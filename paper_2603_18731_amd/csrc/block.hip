@@ -67,14 +67,21 @@ struct BlzState {
     }
 };
 
+// Basis blocks per launch row of the Gram kernel: J blocks keep J x B accumulators per lane,
+// so J trades register pressure (occupancy) against re-reading W once per launch row.
+template <int B>
+constexpr int gram_blocks() {
+    return 32 / B;
+}
+
 // part[j][tile] = sum over the tile's rows i of V_j[i][:]^T W[i][:] (B x B), j = 0 .. cnt-1,
-// cnt = *kdev + 1 (or 1 without kdev).  64 / B basis blocks per launch row (blockIdx.y); lane
-// p = tid % B owns column p of V_j and keeps a B x (64 / B) accumulator tile.
+// cnt = *kdev + 1 (or 1 without kdev).  gram_blocks<B>() basis blocks per launch row
+// (blockIdx.y); lane p = tid % B owns column p of V_j and keeps a B x J accumulator tile.
 template <int B>
 __global__ __launch_bounds__(kThreads) void kbl_gram(const double *__restrict__ Vb, int64_t vstride,
                                                     const int *__restrict__ kdev, const double *__restrict__ W,
                                                     int64_t N, double *__restrict__ part) {
-    constexpr int J = 64 / B;
+    constexpr int J = gram_blocks<B>();
     constexpr int RPB = kThreads / B;
     __shared__ double red[4][J][B][B];
     const int cnt = kdev ? *kdev + 1 : 1;
@@ -147,26 +154,32 @@ __global__ void kbl_reduce(const double *__restrict__ part, const int *__restric
     if (A && j == cnt - 1) A[pq] += s;
 }
 
-// W[i][q] -= sum_{j < cnt} sum_p V_j[i][p] C_j[p][q]; grid-stride over rows, C staged in LDS.
+// W[i][q] -= sum_{j < cnt} sum_p V_j[i][p] C_j[p][q]; one thread per row (grid-stride), the row's
+// B values of V_j read together, C staged in LDS (every lane reads the same entry: a broadcast).
 template <int B>
 __global__ __launch_bounds__(kThreads) void kbl_update(const double *__restrict__ Vb, int64_t vstride,
                                                       const int *__restrict__ kdev, const double *__restrict__ C,
                                                       double *__restrict__ W, int64_t N) {
-    constexpr int RPB = kThreads / B;
     __shared__ double Cs[(kMaxSteps + 1) * B * B];
     const int cnt = *kdev + 1;
     for (int t = threadIdx.x; t < cnt * B * B; t += kThreads) Cs[t] = C[t];
     __syncthreads();
-    const int q = threadIdx.x % B;
-    const int base = (threadIdx.x & 63) & ~(B - 1);
-    for (int64_t i = (int64_t)blockIdx.x * RPB + threadIdx.x / B; i < N; i += (int64_t)gridDim.x * RPB) {
-        double acc = 0.0;
-        for (int j = 0; j < cnt; ++j) {
-            const double v = Vb[(int64_t)j * vstride + i * B + q];
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < N; i += (int64_t)gridDim.x * kThreads) {
+        double acc[B];
 #pragma unroll
-            for (int p = 0; p < B; ++p) acc += __shfl(v, base + p, 64) * Cs[(j * B + p) * B + q];
+        for (int q = 0; q < B; ++q) acc[q] = 0.0;
+        for (int j = 0; j < cnt; ++j) {
+            double v[B];
+#pragma unroll
+            for (int p = 0; p < B; ++p) v[p] = Vb[(int64_t)j * vstride + i * B + p];
+            const double *cj = Cs + j * B * B;
+#pragma unroll
+            for (int p = 0; p < B; ++p)
+#pragma unroll
+                for (int q = 0; q < B; ++q) acc[q] += v[p] * cj[p * B + q];
         }
-        W[i * B + q] -= acc;
+#pragma unroll
+        for (int q = 0; q < B; ++q) W[i * B + q] -= acc[q];
     }
 }
 
@@ -576,7 +589,7 @@ int enqueue_step(const SpmvOp &op, BlzState &S, bool f32, hipStream_t st) {
     } else {
         QSD_TRY(op.matvec(B, S.X, B, S.W, B, QSD_F64, st));
     }
-    const unsigned jy = (unsigned)((S.m + 1 + (64 / B) - 1) / (64 / B));
+    const unsigned jy = (unsigned)((S.m + 1 + gram_blocks<B>() - 1) / gram_blocks<B>());
     for (int pass = 0; pass < 2; ++pass) {
         kbl_gram<B><<<dim3(kGramTiles, jy), kThreads, 0, st>>>(S.V, N * B, S.kdev, S.W, N, S.part);
         kbl_reduce<B><<<S.m + 1, 64, 0, st>>>(S.part, S.kdev, S.C, S.A);
