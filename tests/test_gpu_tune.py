@@ -130,3 +130,27 @@ def test_solvers_under_slot_order_schedules(case):
         assert abs(a - b) <= 1e-9 * abs(a)
     assert res[0][0] == res[0][1]  # graph replay runs the same kernels
     assert res[qsd.SCHED_ALL][0] == res[qsd.SCHED_ALL][1]
+
+
+@pytest.mark.parametrize("n_rows", [1, 2, 63, 65, 257, 900])
+def test_schedules_ragged_sizes(n_rows):
+    """Tiny and ragged subspaces (fewer rows than a wave, a workgroup or eight workgroups) under
+    every schedule: the same output bitwise, equal to the oracle (dyadic data: exact sums)."""
+    from oracle import rowwise as orw
+    from oracle import subspace as osub
+
+    from _util import dyadic, dyadic_vector
+
+    rng = np.random.default_rng(100 + n_rows)
+    n = 12
+    tl = dyadic(wl.xxz_terms(n, [(i, (i + 1) % n) for i in range(n)], 1.0, 0.75))
+    # strings of weight 6 (the XXZ sector), so that columns often land in the subspace
+    pool = [v for v in range(1 << n) if bin(v).count("1") == 6]
+    keys = osub.ints_to_keys(sorted(rng.choice(pool, size=n_rows, replace=False).tolist()), 1)
+    H = _ham(keys, tl)
+    x = torch.from_numpy(dyadic_vector(rng, H.N, nvec=2)).cuda()
+    outs = _run_all(H, x)
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    y_o = orw.matvec_c(osub.canonical_keys(keys), tl, x.cpu().numpy()).real
+    np.testing.assert_array_equal(outs[0].cpu().numpy(), y_o)
