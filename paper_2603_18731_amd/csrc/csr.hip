@@ -137,13 +137,26 @@ __device__ __forceinline__ void csr_term(double vr, double vi, int64_t c, const 
     }
 }
 
-constexpr int kCsrBatch = 4;  // stored entries in flight per lane
+// stored entries in flight per lane: more for the long rows that get many lanes (LPR = 64 means a
+// mean row length of 96 or more), two for the short rows
+template <int LPR>
+constexpr int csr_batch() {
+    return LPR >= 64 ? 8 : LPR >= 16 ? 4 : 2;
+}
+
+// Index and value loads: non-temporal for long rows (streamed once, kept out of the caches that
+// hold x), ordinary for short rows, whose neighbouring lanes share cache lines.
+template <int LPR, class T>
+__device__ __forceinline__ T stream_load(const T *p) {
+    if (LPR >= 16) return __builtin_nontemporal_load(p);
+    return *p;
+}
 
 // y[r] = sum over the row's entries of A_rc x[c] for `nvec` interleaved vectors; LPR lanes per
 // row (consecutive lanes of one wave), FP64 accumulation, fixed reduction tree.  A lane takes
-// entries a + sub, a + sub + LPR, ... in order, kCsrBatch at a time: the column indices and values
-// are streamed once (non-temporal loads, so they do not evict x from the caches) and the x gathers
-// of a batch are all in flight together.
+// entries a + sub, a + sub + LPR, ... in order, csr_batch<LPR>() at a time: the column indices and
+// values of long rows are streamed once (non-temporal loads, so they do not evict x from the
+// caches) and the x gathers of a batch are all in flight together.
 template <int LPR, int NV, class IT, class ET, bool CPLX>
 __global__ __launch_bounds__(256) void k_csr_spmv(const int64_t *__restrict__ indptr, const IT *__restrict__ idx,
                                                  const ET *__restrict__ val, int64_t N, const ET *__restrict__ x,
@@ -153,31 +166,39 @@ __global__ __launch_bounds__(256) void k_csr_spmv(const int64_t *__restrict__ in
     double are[NV], aim[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) are[v] = aim[v] = 0.0;
+    constexpr int kCsrBatch = csr_batch<LPR>();
     if (row < N) {
         const int64_t a = indptr[row], b = indptr[row + 1];
-        int64_t e = a + sub;
-        for (; e + (kCsrBatch - 1) * LPR < b; e += kCsrBatch * LPR) {
+        // batches of kCsrBatch entries per lane; past the row's end the loads repeat its last
+        // entry (always valid) and the term is skipped, so the sum takes the entries in order
+        for (int64_t e = a + sub; e < b; e += kCsrBatch * LPR) {
             int64_t c[kCsrBatch];
             double vr[kCsrBatch], vi[kCsrBatch];
 #pragma unroll
             for (int k = 0; k < kCsrBatch; ++k) {
-                const int64_t ek = e + (int64_t)k * LPR;
-                c[k] = (int64_t)__builtin_nontemporal_load(&idx[ek]);
+                const int64_t ek = min(e + (int64_t)k * LPR, b - 1);
+                c[k] = (int64_t)stream_load<LPR>(&idx[ek]);
                 if (CPLX) {
-                    vr[k] = (double)__builtin_nontemporal_load(&val[2 * ek]);
-                    vi[k] = (double)__builtin_nontemporal_load(&val[2 * ek + 1]);
+                    vr[k] = (double)stream_load<LPR>(&val[2 * ek]);
+                    vi[k] = (double)stream_load<LPR>(&val[2 * ek + 1]);
                 } else {
-                    vr[k] = (double)__builtin_nontemporal_load(&val[ek]);
+                    vr[k] = (double)stream_load<LPR>(&val[ek]);
                     vi[k] = 0.0;
                 }
             }
+            if (NV == 1 && !CPLX) {
+                // one real vector: the batch's x gathers are issued together too
+                double xv[kCsrBatch];
 #pragma unroll
-            for (int k = 0; k < kCsrBatch; ++k) csr_term<NV, ET, CPLX>(vr[k], vi[k], c[k], x, ldx, nvec, are, aim);
-        }
-        for (; e < b; e += LPR) {
-            const int64_t c0 = (int64_t)idx[e];
-            const double r0 = (double)val[CPLX ? 2 * e : e], i0 = CPLX ? (double)val[2 * e + 1] : 0.0;
-            csr_term<NV, ET, CPLX>(r0, i0, c0, x, ldx, nvec, are, aim);
+                for (int k = 0; k < kCsrBatch; ++k) xv[k] = (double)x[c[k] * ldx];
+#pragma unroll
+                for (int k = 0; k < kCsrBatch; ++k)
+                    if (e + (int64_t)k * LPR < b) are[0] += vr[k] * xv[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < kCsrBatch; ++k)
+                    if (e + (int64_t)k * LPR < b) csr_term<NV, ET, CPLX>(vr[k], vi[k], c[k], x, ldx, nvec, are, aim);
+            }
         }
     }
 #pragma unroll
