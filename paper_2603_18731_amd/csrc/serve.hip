@@ -75,7 +75,20 @@ __global__ __launch_bounds__(kBlock) void kb_matvec(const ReqDev *__restrict__ r
             double acc = 0.0;
             if (r < rend) {
                 const int64_t a = R.cptr[r], b = R.cptr[r + 1];
-                for (int64_t e = a + sub; e < b; e += lpr) acc += (double)val[e] * (double)x[R.cidx[e]];
+                // four entries (and their x gathers) in flight per lane, taken in order; past the
+                // row's end the loads repeat its last entry and the term is skipped
+                for (int64_t e = a + sub; e < b; e += 4 * lpr) {
+                    double v[4], xv[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int64_t ek = min(e + (int64_t)k * lpr, b - 1);
+                        v[k] = (double)val[ek];
+                        xv[k] = (double)x[R.cidx[ek]];
+                    }
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (e + (int64_t)k * lpr < b) acc += v[k] * xv[k];
+                }
             }
             for (int d = lpr / 2; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
             if (sub == 0 && r < rend) y[r] = (ET)acc;
