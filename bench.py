@@ -3,15 +3,18 @@
 
 A step is one matrix-free SpMV ``y = H_S x`` over the whole subspace (diagonal, group scan,
 ladder-integer ranges, hash probes, projector refinement, accumulation), with the subspace,
-hash table, operator tables and vectors resident in HBM.  The default workload is the 2D XXZ
-model on the open 6x6 grid (Jxy = 1, Jz = 0.8, ladder form) over 2^20 distinct weight-18
-bit-strings, in FP64.
+hash table, operator tables and vectors resident in HBM.  The default workload is the largest
+single-GPU configuration: a random 16-orbital molecular Hamiltonian (h ~ N(0, 0.1), (pq|rs) ~
+N(0, 0.01) with 8-fold symmetry, Jordan-Wigner ladder terms) on the Cartesian product of 1500
+alpha and 1500 beta strings of weight 5 (2.25M determinants), in FP64.
 
 Output: one JSON line.  ``value`` = stored matrix elements (structural nonzeros of H_S)
 processed per second of SpMV.  ``roofline`` prices the SpMV kernel's algorithmic bytes
 against the 8 TB/s HBM peak.  ``cpu_baseline`` times the CPU oracle (term-by-term, binary
-search) on the host cores on the same input.  Extra keys report the ground-state solve time
-(GPU Lanczos, FP64) and the work counters.
+search) on the host cores on a row sample of the same input, lowest of 5 runs at all host
+threads and at one thread.  Extra keys report the ground-state solve time (GPU Lanczos, FP64),
+the work counters, and the same SpMV measurement on the 6x6 XXZ workload (one vector) and the
+200-qubit heavy-hex workload (8 vectors, the block-Lanczos SpMM).
 """
 import argparse
 import json
@@ -24,10 +27,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "matrix elements/s in matrix-free SpMV; ground-state solve s; serve p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
+# the SpMV kernel, the row engine it runs and its launch
 KERNEL_SOURCES = ["paper_2603_18731_amd/csrc/engine.h", "paper_2603_18731_amd/csrc/matvec.h",
-                  "paper_2603_18731_amd/csrc/device.h"]
-# the SpMV kernels and their launch in ham.hip (the rest of that file is host code)
-KERNEL_FUNCTIONS = ("paper_2603_18731_amd/csrc/ham.hip", ("void k_matvec(", "void launch_mv("))
+                  "paper_2603_18731_amd/csrc/device.h", "paper_2603_18731_amd/csrc/spmv_impl.h"]
 
 
 def kernel_digest():
@@ -38,13 +40,6 @@ def kernel_digest():
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    path, names = KERNEL_FUNCTIONS
-    with open(os.path.join(ROOT, path)) as fh:
-        text = fh.read()
-    for name in names:
-        i = text.index(name)
-        j = text.index("\n}\n", i)  # end of the function body
-        h.update(text[i:j].encode())
     return h.hexdigest()[:16]
 
 
@@ -82,10 +77,25 @@ def calibrate_copy():
 
 
 def algorithmic_bytes(N, W, probes, hits, nvec, esz):
-    """Bytes the method must move per SpMV: per row the key (8W), its hash (8), the diagonal
-    (8), x_i and y_i (2 * esz * nvec); per probe one 8-byte slot; per hit the key compare (8W)
-    and the gathered x_j (esz * nvec)."""
-    return N * (8 * W + 16 + 2 * esz * nvec) + probes * 8 + hits * (8 * W + esz * nvec)
+    """Bytes the method must move per SpMV: per row the key (8W), the diagonal (8), x_i and
+    y_i (2 * esz * nvec); per probe one 8-byte slot; per hit the key compare (8W) and the
+    gathered x_j (esz * nvec)."""
+    return N * (8 * W + 8 + 2 * esz * nvec) + probes * 8 + hits * (8 * W + esz * nvec)
+
+
+def cpu_model():
+    """The host CPU's model name (lscpu), or the platform string."""
+    import platform
+    import subprocess
+
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return platform.processor() or platform.machine()
 
 
 def make_workload(name):
@@ -104,9 +114,11 @@ def make_workload(name):
     return w
 
 
-def cpu_baseline(w, nnz_total, budget_s=12.0):
-    """Time the CPU oracle's SpMV over all rows (repeated until ~budget_s) or, for large
-    workloads, over a row sample scaled to the full matrix."""
+def cpu_baseline(w, nnz_total, budget_s=20.0):
+    """Times the CPU oracle's SpMV (plain C, OpenMP over rows, term by term with binary search)
+    on a random row sample sized to the budget, lowest of 5 runs (the paper's convention), at
+    all host threads and at one thread; the rate is the sample's share of the stored elements
+    per second."""
     import numpy as np
 
     from oracle import rowwise as orw
@@ -117,29 +129,31 @@ def cpu_baseline(w, nnz_total, budget_s=12.0):
     rng = np.random.default_rng(0)
     x = rng.normal(size=N)
     threads = orw.max_threads()
-    # probe the cost on a small sample first
-    rows = np.sort(rng.choice(N, size=min(N, 2000), replace=False))
+    # cost per row at all threads, from a small probe
+    rows = np.sort(rng.choice(N, size=min(N, 512), replace=False))
     t0 = time.perf_counter()
     orw.matvec_c(ck, w.ops, x, rows)
     per_row = (time.perf_counter() - t0) / len(rows)
-    if per_row * N <= budget_s / 2:
-        reps, t_total = 0, 0.0
-        while t_total < budget_s and reps < 50:
+    out = {}
+    # 5 runs at all threads take ~half the budget, 5 at one thread the other half
+    for label, nthr, share in (("all", threads, 0.5), ("one", 1, 0.5)):
+        per_row_t = per_row * (threads / nthr if nthr < threads else 1.0)
+        nrow = int(max(64, min(N, budget_s * share / 5 / max(per_row_t, 1e-9))))
+        rs = np.sort(rng.choice(N, size=nrow, replace=False))
+        best = float("inf")
+        for _ in range(5):
             t0 = time.perf_counter()
-            orw.matvec_c(ck, w.ops, x)
-            t_total += time.perf_counter() - t0
-            reps += 1
-        t_mv = t_total / reps
-        sample = "all %d rows, %d repetitions" % (N, reps)
-    else:
-        nrow = max(1000, min(N, int(budget_s / per_row)))
-        rows = np.sort(rng.choice(N, size=nrow, replace=False))
-        t0 = time.perf_counter()
-        orw.matvec_c(ck, w.ops, x, rows)
-        t_mv = (time.perf_counter() - t0) * N / nrow
-        sample = "%d of %d rows, time scaled to all rows" % (nrow, N)
-    return {"value": nnz_total / t_mv, "unit": "matrix elements/s", "cores": threads, "kind": "oracle",
-            "sample": sample, "matvec_s": t_mv}
+            orw.matvec_c(ck, w.ops, x, rs, nthreads=nthr)
+            best = min(best, time.perf_counter() - t0)
+        out[label] = (nrow, best)
+    nrow, t = out["all"]
+    nrow1, t1 = out["one"]
+    return {"value": nnz_total * (nrow / N) / t, "unit": "matrix elements/s", "cores": threads, "kind": "oracle",
+            "sample": "%d random rows of %d at %d threads (lowest of 5); rate = the rows' share of the %d stored "
+                      "elements per second" % (nrow, N, threads, nnz_total),
+            "value_1thread": nnz_total * (nrow1 / N) / t1,
+            "sample_1thread": "%d random rows, 1 thread, lowest of 5" % nrow1,
+            "cpu_model": cpu_model(), "matvec_s": t * N / nrow, "matvec_s_1thread": t1 * N / nrow1}
 
 
 def serve_bench(args):
@@ -424,13 +438,18 @@ def ramps_bench(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="xxz6x6")
+    ap.add_argument("--workload", default="fermi16")
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--nvec", type=int, default=1)
     ap.add_argument("--max-load", type=float, default=0.0, help="hash load factor (0 = library default)")
     ap.add_argument("--schedule", default="auto", help="SpMV schedule bits, or 'auto' for the autotuner")
+    ap.add_argument("--split", type=int, default=-1, help="hash split qubit (0 = none; -1 = the autotuner "
+                    "decides, or none with a fixed schedule)")
+    ap.add_argument("--order-by-mask", type=int, default=0, help="order groups by flip mask (1) instead of by "
+                    "weight, then mask (0)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the XXZ and heavy-hex extra measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--gather-ceiling", action="store_true", help="measure the random-gather rate for "
@@ -486,53 +505,104 @@ def main():
               "GPUs (requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = make_workload(args.workload)
+    by_mask = args.order_by_mask
+    r = measure_spmv(w, args.nvec, args.dtype, args.steps, args.warmup, args.max_load, args.schedule,
+                     split=args.split, solve=not args.no_solve, order_by_mask=bool(by_mask))
+    out = {
+        "metric": METRIC,
+        "value": r["value"],
+        "unit": "matrix elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": r["config"],
+        "roofline": r["roofline"],
+        "work": r["work"],
+    }
+    if "ground_state" in r:
+        out["ground_state"] = r["ground_state"]
+    if not args.no_extra and args.workload == "fermi16":
+        # the other two large configurations, measured the same way (outside the headline)
+        for name, nvec in (("xxz6x6", 1), ("heavyhex200", 8)):
+            we = make_workload(name)
+            re_ = measure_spmv(we, nvec, args.dtype, max(5, args.steps), args.warmup, 0.0, "auto", split=-1,
+                               solve=False, order_by_mask=False)
+            out["extra_%s_nvec%d" % (we.name, nvec)] = {
+                "value": re_["value"], "unit": "matrix elements/s", "ms_per_step": re_["ms_per_step"],
+                "config": re_["config"], "roofline": re_["roofline"], "work": re_["work"]}
+            del we
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(w, r["config"]["nnz"] * args.nvec)
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "value_1thread",
+                                                   "sample_1thread", "cpu_model")}
+        print("# cpu oracle %.3f s per SpMV on %d threads, %.3f s on one (%s)" % (
+            cb["matvec_s"], cb["cores"], cb["matvec_s_1thread"], cb["cpu_model"]), file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+def measure_spmv(w, nvec, dtype_name, steps, warmup, max_load, schedule, split=0, solve=True, order_by_mask=False):
+    """Builds workload ``w`` on the device, counts its work, tunes (``schedule`` = "auto") and
+    times ``steps`` SpMVs after ``warmup`` with HIP events on the launch stream."""
+    import ctypes
+
     import numpy as np
     import torch
 
     import paper_2603_18731_amd as qsd
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
     t_setup = time.perf_counter()
-    w = make_workload(args.workload)
     print("# workload %s: %d strings, %d qubits" % (w.name, w.keys.shape[0], w.ops.n_qubits), file=sys.stderr,
           flush=True)
-    sub = qsd.Subspace(w.keys, w.ops.n_qubits, max_load=args.max_load)
-    op = qsd.operator_from_termlist(w.ops)
+    sub = qsd.Subspace(w.keys, w.ops.n_qubits, max_load=max_load)
+    op = qsd.operator_from_termlist(w.ops, order_by_mask=order_by_mask)
     H = qsd.SubspaceHamiltonian(sub, op)
     N, W = sub.N, sub.W
     # structural nonzeros (CSR count pass) and work counters, outside the timed region
     indptr = torch.empty(N + 1, dtype=torch.int64, device="cuda")
-    import ctypes
-
     nnz_c = ctypes.c_int64()
     qsd._check(qsd.lib().qsd_csr_build(H.handle, qsd._ptr(indptr), None, None, qsd.INDEX_I64,
                                        qsd.C128 if H.is_complex else qsd.F64, ctypes.byref(nnz_c), qsd._stream()))
     nnz = nnz_c.value
     probes, hits = H.work_counts()
     del indptr
-    dt = torch.float64 if args.dtype == "f64" else torch.float32
+    dt = torch.float64 if dtype_name == "f64" else torch.float32
     tune = None
-    if args.schedule == "auto":
-        tune = H.autotune(nvec=args.nvec, dtype=dt, reps=3, load=args.max_load == 0.0)
+    if schedule == "auto":
+        if split > 0:
+            sub.rehash(max_load, split)
+        tune = H.autotune(nvec=nvec, dtype=dt, reps=3, load=max_load == 0.0, split=split < 0)
         print("# autotuner: %s" % json.dumps(tune), file=sys.stderr, flush=True)
     else:
-        H.schedule = int(args.schedule)
+        if split > 0 or max_load:
+            sub.rehash(max_load, max(split, 0))
+        H.schedule = int(schedule)
     sched = H.schedule
+    hsplit, exact = sub.hash_info()
     setup_s = time.perf_counter() - t_setup
     print("# setup %.1f s: N=%d nnz=%d probes=%d hits=%d groups=%d" % (setup_s, N, nnz, probes, hits, op.n_groups),
           file=sys.stderr, flush=True)
 
-    esz = 8 if args.dtype == "f64" else 4
+    esz = 8 if dtype_name == "f64" else 4
     g = torch.Generator(device="cuda")
     g.manual_seed(1)
-    x = torch.rand((N, args.nvec), dtype=dt, device="cuda", generator=g).squeeze(1)
+    x = torch.rand((N, nvec), dtype=dt, device="cuda", generator=g).squeeze(1)
     y = torch.empty_like(x)
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         H.matvec(x, out=y)
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
     for e0, e1 in evs:
         e0.record(stream)
@@ -542,52 +612,40 @@ def main():
     wall = time.perf_counter() - t0
     kms = [e0.elapsed_time(e1) for e0, e1 in evs]
     k_avg = float(np.mean(kms))
-    ms_per_step = wall * 1e3 / args.steps
-    value = nnz * args.nvec / (ms_per_step / 1e3)
-    balg = algorithmic_bytes(N, W, probes, hits, args.nvec, esz)
+    ms_per_step = wall * 1e3 / steps
+    balg = algorithmic_bytes(N, W, probes, hits, nvec, esz)
     achieved = balg / (k_avg / 1e3) / 1e9
     print("# SpMV: %.4f ms/step wall, kernel avg %.4f ms (min %.4f), %.1f GB/s algorithmic" %
           (ms_per_step, k_avg, min(kms), achieved), file=sys.stderr, flush=True)
-
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "matrix elements/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+    res = {
+        "value": nnz * nvec / (ms_per_step / 1e3),
         "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": args.dtype,
-        "data": "synthetic",
         "config": {"workload": w.name, "n_qubits": w.ops.n_qubits, "subspace_dim": N, "nnz": nnz,
-                   "groups": op.n_groups, "terms": op.n_terms, "nvec": args.nvec,
-                   "kernel": "k_matvec",
-                   "schedule": sched, "hash_capacity": sub.capacity, "autotune": tune},
+                   "groups": op.n_groups, "terms": op.n_terms, "nvec": nvec, "kernel": "k_matvec",
+                   "schedule": sched, "hash_capacity": sub.capacity, "part_filter_split": hsplit,
+                   "exact_slots": exact, "groups_by_mask": bool(order_by_mask),
+                   "autotune": tune},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": stored_traffic(w.name, args.dtype, args.nvec, sub.capacity), "bytes_per_launch": balg,
-                     "kernel_ms": k_avg, "kernel_source_digest": kernel_digest()},
+                     "traffic": stored_traffic(w.name, dtype_name, nvec, sub.capacity),
+                     "bytes_per_launch": balg, "kernel_ms": k_avg, "kernel_ms_min": min(kms),
+                     "kernel_source_digest": kernel_digest()},
         "work": {"probes": probes, "hits": hits, "evaluations": N * op.n_groups,
                  "probes_per_s": probes / (k_avg / 1e3), "evaluations_per_s": N * op.n_groups / (k_avg / 1e3)},
     }
-    if not args.no_solve:
+    if solve:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         e, _, info = H.lanczos(tol=1e-10, max_iter=300, v0="uniform", raise_on_nonconv=False)
         solve_s = time.perf_counter() - t0
-        out["ground_state"] = {"energy": e, "solve_s": solve_s, "iterations": info["iterations"],
+        res["ground_state"] = {"energy": e, "solve_s": solve_s, "iterations": info["iterations"],
                                "converged": bool(info["converged"]), "ritz_residual": info["ritz_residual"]}
         print("# ground state %.12f in %.3f s (%d iterations)" % (e, solve_s, info["iterations"]), file=sys.stderr,
               flush=True)
-    if not args.no_cpu_baseline:
-        cb = cpu_baseline(w, nnz * args.nvec)
-        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
-        print("# cpu oracle %.3f s per SpMV on %d threads" % (cb["matvec_s"], cb["cores"]), file=sys.stderr,
-              flush=True)
-    print(json.dumps(out), flush=True)
+    del H, op, sub, x, y
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
 
 
 if __name__ == "__main__":

@@ -116,11 +116,27 @@ int32_t qsd_max_qubits(void);
  * (slots).  Any output pointer may be NULL. */
 int qsd_subspace_info(const qsd_subspace *s, int64_t *N, int32_t *n_qubits, int32_t *W, int64_t *capacity);
 
-/* Rebuilds the hash table (slots and occupancy bitmap) for a new max_load in (0, 0.5] (0 = the
- * default 1/8); keys, canonical indices and every lookup result are unchanged.  The subspace
- * must not be in use on any stream meanwhile (operators bound to it see the new table at their
- * next launch; serving requests hold the old one and must be removed first).  Synchronizes. */
-int qsd_subspace_rehash(qsd_subspace *s, double max_load, void *stream);
+/* Rebuilds the hash table (slots, occupancy bitmap, slot order of the rows) for a new max_load in
+ * (0, 0.5] (0 = the default 1/8), and the part filters for `split`; keys, canonical indices and
+ * every lookup and SpMV result are unchanged.
+ *   split  0: no part filters.  s in [1, n_qubits): the qubits below s form a string's low part,
+ *          the others its high part, and two bitmaps record which low parts and which high parts
+ *          occur in the subspace (parts of at most 16 qubits index them directly, longer parts
+ *          through a 16-bit GF(2)-linear image).  A column b ^ M_g whose low or high part does
+ *          not occur cannot be a member, so the row engine rejects it from the bitmaps (kept in
+ *          LDS for keys of up to 128 qubits) without touching the hash table; a column that
+ *          passes reads its home slot directly.  This is the membership test the occupancy
+ *          bitmap gives (Methods, Subspace data structure), made cheap for subspaces built as
+ *          Cartesian products of alpha and beta strings (Results): split at the first beta
+ *          qubit, a column passes only if both its alpha and its beta string were sampled.
+ * The subspace must not be in use on any stream meanwhile (operators bound to it through
+ * qsd_ham_create are updated; serving requests hold the old table and must be removed first).
+ * Synchronizes.  INVALID_ARG for max_load or split out of range. */
+int qsd_subspace_rehash(qsd_subspace *s, double max_load, int32_t split, void *stream);
+
+/* Split qubit of the part filters (0 = none) and whether slots use the exact layout (one-word
+ * keys whose (home slot, tag) pair is injective).  Either output pointer may be NULL. */
+int qsd_subspace_hash_info(const qsd_subspace *s, int32_t *split, int32_t *exact);
 
 /* New subspace of the strings whose byte in d_mask[N] (device) is nonzero, in the same order
  * (indices renumbered consecutively), with a table for max_load (0 = default).  INVALID_ARG when
@@ -260,14 +276,19 @@ int qsd_ham_get_schedule(const qsd_ham *h, uint32_t *schedule);
  *                      (qsd_subspace_rehash), so the subspace must not be used meanwhile by
  *                      any other handle, batch or stream.  The best table depends on how the
  *                      occupancy bitmap and the slots fit the caches.
- * Neither changes any result bit.  `result` (host, may be NULL) receives the choice, the time
+ *   QSD_TUNE_SPLIT     also the other part-filter choice (split at qubit n_qubits / 2 if the
+ *                      subspace has none, none if it has one), at every load swept (or the
+ *                      current load without QSD_TUNE_LOAD).
+ * None changes any result bit.  `result` (host, may be NULL) receives the choice, the time
  * per SpMV before and after.  Synchronizes; allocates 2 N nvec elements while it runs. */
 #define QSD_TUNE_SCHEDULE 1u
 #define QSD_TUNE_LOAD 2u
+#define QSD_TUNE_SPLIT 4u
 typedef struct {
     uint32_t schedule; /* QSD_SCHED_* bits kept */
     int64_t capacity;  /* hash slots kept */
     double max_load;   /* load parameter of the kept table */
+    int32_t split;     /* split qubit of the kept part filters (0 = none) */
     double ms;         /* SpMV time with the kept choice */
     double ms_before;  /* SpMV time before tuning */
 } qsd_tune_result;

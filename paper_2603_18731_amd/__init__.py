@@ -29,7 +29,7 @@ SUB_ASSUME_SORTED_UNIQUE = 1
 V0_UNIFORM, V0_MIN_DIAG, V0_RANDOM, V0_USER = 0, 1, 2, 3
 SCHED_XCD_REMAP, SCHED_SLOT_ORDER, SCHED_LOCKSTEP, SCHED_FILTER_FIRST = 1, 2, 4, 8
 SCHED_ALL = 15
-TUNE_SCHEDULE, TUNE_LOAD = 1, 2
+TUNE_SCHEDULE, TUNE_LOAD, TUNE_SPLIT = 1, 2, 4
 CSR_LOWER_MIRROR = 1
 ERR_NAMES = {-1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "HIP", -4: "CAPACITY", -5: "NOT_HERMITIAN",
              -6: "NOT_CONVERGED", -7: "DTYPE", -8: "UNSUPPORTED"}
@@ -44,7 +44,7 @@ EXPORTED = [
     "qsd_ham_set_schedule", "qsd_ham_get_schedule", "qsd_ham_autotune", "qsd_subspace_rehash",
     "qsd_csr_create", "qsd_csr_info", "qsd_csr_export", "qsd_csr_matvec", "qsd_csr_lanczos", "qsd_csr_block_lanczos",
     "qsd_csr_destroy", "qsd_subspace_select", "qsd_ramps",
-    "qsd_ham_diag_splitting", "qsd_batch_add_csr", "qsd_batch_footprint_rows",
+    "qsd_ham_diag_splitting", "qsd_batch_add_csr", "qsd_batch_footprint_rows", "qsd_subspace_hash_info",
 ]
 
 
@@ -56,7 +56,7 @@ class QsdError(RuntimeError):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_uint32), ("capacity", ctypes.c_int64), ("max_load", ctypes.c_double),
-                ("ms", ctypes.c_double), ("ms_before", ctypes.c_double)]
+                ("split", ctypes.c_int32), ("ms", ctypes.c_double), ("ms_before", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -134,7 +134,8 @@ def lib():
         "qsd_ham_set_schedule": ([P, U32], ctypes.c_int),
         "qsd_ham_get_schedule": ([P, P], ctypes.c_int),
         "qsd_ham_autotune": ([P, I32, I32, I32, U32, P, P], ctypes.c_int),
-        "qsd_subspace_rehash": ([P, D, P], ctypes.c_int),
+        "qsd_subspace_rehash": ([P, D, I32, P], ctypes.c_int),
+        "qsd_subspace_hash_info": ([P, P, P], ctypes.c_int),
         "qsd_csr_create": ([P, I32, I32, U32, P, PP], ctypes.c_int),
         "qsd_csr_info": ([P, P, P, P], ctypes.c_int),
         "qsd_csr_export": ([P, P, P, P, P], ctypes.c_int),
@@ -273,10 +274,17 @@ class Subspace:
         _check(lib().qsd_subspace_info(self._h, ctypes.byref(N), ctypes.byref(nq), ctypes.byref(Wo), ctypes.byref(C)))
         self.capacity = C.value
 
-    def rehash(self, max_load: float, stream=None):
-        """Rebuilds the hash table for another load (lookups are unchanged)."""
-        _check(lib().qsd_subspace_rehash(self._h, max_load, _stream(stream)))
+    def rehash(self, max_load: float, split: int = 0, stream=None):
+        """Rebuilds the hash table for another load and the part filters for ``split`` (0: none,
+        else the first qubit of the high part); lookups and SpMV results are unchanged."""
+        _check(lib().qsd_subspace_rehash(self._h, max_load, int(split), _stream(stream)))
         self._refresh()
+
+    def hash_info(self):
+        """``(split qubit of the part filters, exact slot layout)``."""
+        sp_, ex = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().qsd_subspace_hash_info(self._h, ctypes.byref(sp_), ctypes.byref(ex)))
+        return sp_.value, bool(ex.value)
 
     def probe_stats(self, stream=None):
         m, x = ctypes.c_double(), ctypes.c_int64()
@@ -408,14 +416,14 @@ class SubspaceHamiltonian:
         _check(lib().qsd_ham_set_schedule(self._h, int(value)))
 
     def autotune(self, nvec: int = 1, dtype=None, reps: int = 3, schedule: bool = True, load: bool = True,
-                 stream=None) -> dict:
-        """Times the SpMV under every candidate schedule and hash load and keeps the fastest
-        (the subspace's table is rebuilt when ``load``)."""
+                 split: bool = False, stream=None) -> dict:
+        """Times the SpMV under every candidate schedule, hash load and (with ``split``) hash
+        family and keeps the fastest (the subspace's table is rebuilt when ``load`` or ``split``)."""
         import torch
 
         dtype = dtype or (torch.complex128 if self.is_complex else torch.float64)
         code = {torch.float64: F64, torch.float32: F32, torch.complex128: C128, torch.complex64: C64}[dtype]
-        flags = (TUNE_SCHEDULE if schedule else 0) | (TUNE_LOAD if load else 0)
+        flags = (TUNE_SCHEDULE if schedule else 0) | (TUNE_LOAD if load else 0) | (TUNE_SPLIT if split else 0)
         r = TuneResult()
         _check(lib().qsd_ham_autotune(self._h, nvec, code, reps, flags, ctypes.byref(r), _stream(stream)))
         self.subspace._refresh()

@@ -14,7 +14,9 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqsd.so")
 
-SOURCES = ["api.cpp", "opcompile.cpp", "subspace.hip", "ham.hip", "lanczos.hip", "diag.hip", "serve.hip", "block.hip", "csr.hip", "ramps.hip"]
+SOURCES = ["ham.hip", "serve.hip", "csr.hip", "spmv_w1.hip", "spmv_w2.hip", "spmv_w4.hip", "spmv_w8.hip",
+           "spmv_w16.hip", "subspace.hip", "lanczos.hip", "block.hip", "ramps.hip", "diag.hip", "opcompile.cpp",
+           "api.cpp"]
 ARCH = os.environ.get("QSD_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -39,7 +41,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(os.cpu_count() or 8, 16, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + ["-o", tmp]

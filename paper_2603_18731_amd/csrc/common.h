@@ -44,11 +44,15 @@ inline int padded_words(int n_qubits) {
     return Wp;
 }
 
-// GF(2)-linear hash of a bit-string: XOR of one fixed pseudo-random 64-bit value per set
+// GF(2)-linear hash of a bit-string: XOR of one fixed pseudo-random 64-bit word per set
 // bit.  Linearity gives hash(row ^ mask) = hash(row) ^ hash(mask), so a probe for the
-// column of any group costs one XOR once the row's hash is known.
-uint64_t qubit_hash_value(int q);  // value for qubit q
-void hash_byte_tables(int Wp, std::vector<uint64_t> &tab);  // [Wp*8][256] byte tabulation
+// column of any group costs one XOR once the row's hash is known.  The home slot is the low
+// log2(C) bits, the tag the high 32.
+//
+uint64_t qubit_hash_value(int q);  // pseudo-random word of qubit q
+void hash_words(int n_qubits, std::vector<uint64_t> &z);  // z[q] per qubit
+void part_words(int n_qubits, int split, std::vector<uint32_t> &pz);  // packed part-index word per qubit
+void hash_byte_tables(int Wp, const std::vector<uint64_t> &z, std::vector<uint64_t> &tab);  // [Wp*8][256]
 
 // Device memory helpers --------------------------------------------------------------
 template <class T>
@@ -70,6 +74,11 @@ void dev_free(T *&p) {
     p = nullptr;
 }
 
+// Hash of every off-diagonal group's flip mask under the subspace's hash words, and its packed
+// part indices under the subspace's part words.
+std::vector<uint64_t> group_hashes(const qsd_op *op, const std::vector<uint64_t> &z);
+std::vector<uint32_t> group_parts(const qsd_op *op, const std::vector<uint32_t> &pz);
+
 // Device-wide exclusive scan of int64 counts (in place allowed); n elements.
 int exclusive_scan_i64(const int64_t *d_in, int64_t *d_out, int64_t n, hipStream_t stream);
 
@@ -83,12 +92,14 @@ struct SlotRows {
     uint32_t *order = nullptr;  // [N] row index of each position
     uint64_t *keys = nullptr;   // [Wp][N]
     uint64_t *hkey = nullptr;   // [N]
+    uint32_t *pkey = nullptr;   // [N] packed part indices (with part filters)
 };
 namespace qsd {
 inline void free_rows(SlotRows &r) {
     dev_free(r.order);
     dev_free(r.keys);
     dev_free(r.hkey);
+    dev_free(r.pkey);
 }
 }  // namespace qsd
 
@@ -105,13 +116,23 @@ struct qsd_subspace {
     uint64_t *ztab = nullptr;    // [Wp * 8][256] byte tabulation of the hash
     SlotRows rows;               // the rows in slot order
     bool exact = false;          // slots carry displacements (see device.h)
+    std::vector<uint64_t> z;     // hash word of each qubit (host copy of what ztab tabulates)
+    // Part filters (none when split = 0): the qubits below `split` form the low part, the others
+    // the high part; pz[q] is qubit q's word of the packed part index (high << 16 | low), a
+    // GF(2)-linear map (the identity on a part of at most 16 qubits, pseudo-random otherwise).
+    int32_t split = 0;
+    std::vector<uint32_t> pz;
+    uint32_t *pfilt = nullptr;   // [kPartWords] low-part filter, then high-part filter
+    uint32_t *pkey = nullptr;    // [N] packed part indices of the rows (canonical order)
+    // operators bound to this subspace: their group hashes follow the hash words on a rehash
+    mutable std::vector<qsd_ham *> bound;
 };
 
 // Whether slots of a table with C slots may use the exact layout: one-word keys, indices below
 // 2^26, and the n qubit hash words, restricted to the bits that the home slot and the tag keep,
 // linearly independent over GF(2) (then the map key -> (home slot, tag) is injective).
 namespace qsd {
-bool exact_tags_ok(int n_qubits, int W, int64_t N, int64_t C);
+bool exact_tags_ok(const std::vector<uint64_t> &z, int W, int64_t N, int64_t C);
 }
 
 struct Letter {
@@ -136,8 +157,7 @@ struct qsd_op {
     std::vector<uint64_t> diag_cws;       // [Td][3][Wp]
     std::vector<double> diag_coef;        // [Td][2]
     // off-diagonal groups
-    std::vector<uint64_t> g_mask;         // [G-1][Wp]
-    std::vector<uint64_t> g_hash;         // [G-1]
+    std::vector<uint64_t> g_mask;         // [G-1][Wp] (their hashes depend on the subspace)
     std::vector<uint64_t> g_pos;          // [G-1] four 16-bit ladder positions
     std::vector<uint64_t> g_scan;         // [G-1] scan record: live table over 4 bits | 4 x 12-bit shifts
     std::vector<uint32_t> g_info;         // [G-1] k | ladder<<3 | care<<4 | live16<<16
@@ -169,6 +189,7 @@ struct qsd_ham {
     double *diag_im = nullptr;    // [N] imaginary part (complex operators only)
     uint64_t *g_mask = nullptr;
     uint64_t *g_hash = nullptr;
+    uint32_t *g_part = nullptr;   // [G] packed part indices (subspaces with part filters)
     uint64_t *g_pos = nullptr;
     uint64_t *g_scan = nullptr;
     uint32_t *g_info = nullptr;

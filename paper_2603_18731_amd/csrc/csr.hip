@@ -29,15 +29,16 @@ template <int Wp>
 __global__ __launch_bounds__(kBlock) void k_count_lower(SubView s, HamView h, unsigned long long *__restrict__ counts) {
     __shared__ ChunkLds<Wp> lds;
     uint64_t key[Wp], hrow;
+    uint32_t prow;
     bool valid;
-    const int64_t r = load_row<Wp>(s, (int64_t)blockIdx.x * kBlock, key, hrow, valid);
+    const int64_t r = load_row<Wp>(s, (int64_t)blockIdx.x * kBlock, key, hrow, prow, valid);
     unsigned long long own = 1;  // diagonal
-    row_engine<Wp, true>(s, h, key, hrow, valid, lds, [&](int64_t j, uint32_t t0, uint32_t len) {
+    row_engine<Wp, true>(s, h, key, hrow, prow, valid, lds, sink([&](int64_t j, uint32_t t0, uint32_t len, int) {
         double vre, vim;
-        if (!range_value<Wp, double>(h, key, t0, len, vre, vim)) return;
+        if (!range_value<Wp, double>(h, lds, key, t0, len, vre, vim)) return;
         ++own;
         atomicAdd(&counts[j], 1ull);  // the mirrored entry (r, j) -> (j, r)
-    }, nullptr, false, true);
+    }), nullptr, false, true);
     if (valid) atomicAdd(&counts[r], own);
 }
 
@@ -48,8 +49,9 @@ __global__ __launch_bounds__(kBlock) void k_fill_lower(SubView s, HamView h, con
                                                        int64_t *__restrict__ cols, typename C2<ET>::T *__restrict__ vals) {
     __shared__ ChunkLds<Wp> lds;
     uint64_t key[Wp], hrow;
+    uint32_t prow;
     bool valid;
-    const int64_t r = load_row<Wp>(s, (int64_t)blockIdx.x * kBlock, key, hrow, valid);
+    const int64_t r = load_row<Wp>(s, (int64_t)blockIdx.x * kBlock, key, hrow, prow, valid);
     if (valid) {
         const int64_t o = indptr[r] + (int64_t)atomicAdd(&cursor[r], 1ull);
         typename C2<ET>::T d;
@@ -58,9 +60,9 @@ __global__ __launch_bounds__(kBlock) void k_fill_lower(SubView s, HamView h, con
         cols[o] = r;
         vals[o] = d;
     }
-    row_engine<Wp, true>(s, h, key, hrow, valid, lds, [&](int64_t j, uint32_t t0, uint32_t len) {
+    row_engine<Wp, true>(s, h, key, hrow, prow, valid, lds, sink([&](int64_t j, uint32_t t0, uint32_t len, int) {
         typename C2<ET>::T v;
-        if (!range_value<Wp, ET>(h, key, t0, len, v.x, v.y)) return;
+        if (!range_value<Wp, ET>(h, lds, key, t0, len, v.x, v.y)) return;
         const int64_t o1 = indptr[r] + (int64_t)atomicAdd(&cursor[r], 1ull);
         cols[o1] = j;
         vals[o1] = v;
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_lower(SubView s, HamView h, con
         vc.y = -v.y;
         cols[o2] = r;
         vals[o2] = vc;
-    }, nullptr, false, true);
+    }), nullptr, false, true);
 }
 
 // Sort each row's (column, value) pairs by column into the output arrays: one workgroup per

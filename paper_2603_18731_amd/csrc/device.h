@@ -19,7 +19,25 @@ struct SubView {
     const uint32_t *__restrict__ order;  // [N] row indices in the order of their slots in the table
     const uint64_t *__restrict__ okeys;  // [Wp][N] keys in that order
     const uint64_t *__restrict__ ohkey;  // [N] hashes in that order
+    // part filters (NULL when the subspace has none): bit u of pfilt[0 .. 2047] is set when some
+    // string's low-part index is u, bit u of pfilt[2048 .. 4095] when some string's high-part
+    // index is u; pkey / opkey hold each row's packed part indices (high << 16 | low) in the
+    // canonical and the slot order.  The indices are GF(2)-linear in the string, so a column's
+    // are the row's XOR the group's.
+    const uint32_t *__restrict__ pfilt;
+    const uint32_t *__restrict__ pkey;
+    const uint32_t *__restrict__ opkey;
 };
+
+constexpr int kPartBits = 16;                        // index bits of each part filter
+constexpr int kPartWords = 2 << (kPartBits - 5);     // both filters, in 32-bit words (16 KB)
+
+// Whether both parts of a string with packed part indices p occur in the subspace (a necessary
+// condition for the string to be a member).
+__device__ __forceinline__ bool part_pass(const uint32_t *pf, uint32_t p) {
+    const uint32_t lo = p & 0xFFFFu, hi = p >> 16;
+    return ((pf[lo >> 5] >> (lo & 31u)) & (pf[(kPartWords / 2) + (hi >> 5)] >> (hi & 31u)) & 1u) != 0u;
+}
 
 // Slot layout.  Default: tag (high 32 bits of the hash) | index (32 bits).  Exact mode (one-word
 // keys, N < 2^26, and the map key -> (home slot, tag) proven injective when the table is built):

@@ -45,6 +45,22 @@ constexpr int kLockBatch = 4;   // groups in flight per wave in lockstep mode
 constexpr int kOccBatch = 8;    // occupancy-bit loads in flight per lane (filter-first mode)
 constexpr int kSlotBatch = 4;   // slot loads in flight per lane (filter-first mode)
 
+// Terms of a chunk staged in LDS (the chunk's groups own one contiguous run of terms): the
+// first TermCacheSize<Wp> of them are read from LDS by every hit of the chunk, the rest (chunks
+// of groups with long term lists) from global memory.  With the 16 KB part filter (one- and
+// two-word keys) the workgroup stays under 32 KB of LDS, so five workgroups (the register
+// limit of the one-vector kernels) fit a CU; wider keys read every term from global memory.
+template <int Wp>
+struct TermCacheSize {
+    static constexpr int value = Wp == 1 ? 224 : Wp == 2 ? 100 : Wp == 4 ? 96 : 0;
+};
+
+// One- and two-word keys copy the part filters into LDS; wider keys read them from memory.
+template <int Wp>
+struct PartLds {
+    static constexpr int words = Wp <= 2 ? kPartWords : 1;
+};
+
 struct HamView {
     const uint64_t *__restrict__ g_mask;   // [G][Wp]
     const uint64_t *__restrict__ g_hash;   // [G]
@@ -57,6 +73,8 @@ struct HamView {
     const uint64_t *__restrict__ t_cws;    // [T][3][Wp] care, want, sign masks
     const void *__restrict__ t_coef;       // [T] double2 or float2
     int64_t G;
+    int coef_f32;                          // t_coef holds float2 (1) or double2 (0)
+    const uint32_t *__restrict__ g_part;   // [G] packed part indices of the flip masks (with filters)
 };
 
 template <class ET>
@@ -84,32 +102,6 @@ __device__ __forceinline__ uint32_t term_parity(const uint64_t (&k)[Wp], const u
 #pragma unroll
     for (int w = 0; w < Wp; ++w) c += (uint32_t)__popcll(k[w] & cws[2 * Wp + w]);
     return c & 1u;
-}
-
-// Sum of the terms [t0, t0 + len) that match the row's projector bits, with popcount-parity
-// signs.  Returns false when no term matches (no stored entry).
-template <int Wp, class ET>
-__device__ __forceinline__ bool range_value(const HamView &h, const uint64_t (&key)[Wp], uint32_t t0, uint32_t len,
-                                            ET &vre, ET &vim) {
-    using CT = typename C2<ET>::T;
-    const CT *__restrict__ coef = (const CT *)h.t_coef;
-    bool any = false;
-    vre = 0;
-    vim = 0;
-    for (uint32_t t = t0; t < t0 + len; ++t) {
-        const uint64_t *cws = h.t_cws + (int64_t)t * 3 * Wp;
-        if (!term_pass<Wp>(key, cws)) continue;
-        any = true;
-        const CT c = coef[t];
-        if (term_parity<Wp>(key, cws)) {
-            vre -= c.x;
-            vim -= c.y;
-        } else {
-            vre += c.x;
-            vim += c.y;
-        }
-    }
-    return any;
 }
 
 // 4-bit ladder integer of a row from a scan record: bit j = row bit at qubit p_j = shift_j + j.
@@ -187,7 +179,43 @@ struct ChunkLds {
     uint16_t iptr[kChunk][kIptr];
     uint64_t planes[kBlock / 64][64 * Wp];
     uint8_t clist[kBlock / 64][kChunk];  // lockstep filter-first: the wave's k-th live group
+    // staged terms: care/want/sign words and the coefficient (double2, or float2 in the low
+    // half) of terms tc_base .. tc_base + tc_count - 1
+    uint64_t tc_cws[TermCacheSize<Wp>::value > 0 ? TermCacheSize<Wp>::value : 1][3 * Wp];
+    uint64_t tc_coef[TermCacheSize<Wp>::value > 0 ? TermCacheSize<Wp>::value : 1][2];
+    uint32_t tc_base, tc_count;
+    uint32_t gpart[kChunk];              // the chunk's groups' packed part indices
+    uint32_t pf[PartLds<Wp>::words];     // part filters (one- and two-word keys)
 };
+
+// Sum of the terms [t0, t0 + len) that match the row's projector bits, with popcount-parity
+// signs.  Returns false when no term matches (no stored entry).  Terms staged in the chunk's
+// LDS cache are read from there.
+template <int Wp, class ET>
+__device__ __forceinline__ bool range_value(const HamView &h, const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp],
+                                            uint32_t t0, uint32_t len, ET &vre, ET &vim) {
+    using CT = typename C2<ET>::T;
+    const CT *__restrict__ coef = (const CT *)h.t_coef;
+    bool any = false;
+    vre = 0;
+    vim = 0;
+    for (uint32_t t = t0; t < t0 + len; ++t) {
+        const uint32_t ct = t - lds.tc_base;
+        const bool cached = ct < lds.tc_count;
+        const uint64_t *cws = cached ? lds.tc_cws[ct] : h.t_cws + (int64_t)t * 3 * Wp;
+        if (!term_pass<Wp>(key, cws)) continue;
+        any = true;
+        const CT c = cached ? *(const CT *)lds.tc_coef[ct] : coef[t];
+        if (term_parity<Wp>(key, cws)) {
+            vre -= c.x;
+            vim -= c.y;
+        } else {
+            vre += c.x;
+            vim += c.y;
+        }
+    }
+    return any;
+}
 
 // Pops the lowest set bit of a 64-bit mask held as two words; -1 when empty.
 __device__ __forceinline__ int pop_group(uint32_t &mlo, uint32_t &mhi) {
@@ -216,52 +244,114 @@ __device__ __forceinline__ uint32_t group_msob(const uint64_t *__restrict__ mask
     return ms;
 }
 
+// A hit consumer: fetch(j) issues the loads a hit on column j needs (x_j, say) and returns them;
+// use(j, t0, len, pre) consumes the hit with what fetch returned.  The engine resolves a batch of
+// groups, then fetches for all of the batch's hits, then uses them in increasing group order, so
+// the fetch latencies overlap while every row's sum keeps its fixed order.
+template <class Use, class Fetch>
+struct HitSink {
+    Use use;
+    Fetch fetch;
+};
+struct NoFetch {
+    __device__ __forceinline__ int operator()(int64_t) const { return 0; }
+};
+template <class Use>
+__device__ __forceinline__ HitSink<Use, NoFetch> sink(Use u) {
+    return HitSink<Use, NoFetch>{u, NoFetch{}};
+}
+template <class Use, class Fetch>
+__device__ __forceinline__ HitSink<Use, Fetch> sink(Use u, Fetch f) {
+    return HitSink<Use, Fetch>{u, f};
+}
+
+// Term range [t0, t0 + len) of chunk group cc for the row (its ladder integer selects it).
+template <int Wp>
+__device__ __forceinline__ void hit_range(const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp], const uint64_t *planes,
+                                          int lane, int cc, uint32_t &t0, uint32_t &len) {
+    const uint32_t lm = lds.lmask[cc];
+    const uint32_t L = row_lint<Wp>(key, lds.rec[cc], planes, lane) & lm;
+    const uint32_t lo = lds.iptr[cc][L];
+    const uint32_t hi = lm ? (uint32_t)lds.iptr[cc][L + 1] : lds.nterm[cc];
+    t0 = lds.term0[cc] + lo;
+    len = hi - lo;
+}
+
+// Fetch then use for a batch whose columns are resolved (j[b] < 0: no hit).
+template <int Wp, int NB, class Sink>
+__device__ __forceinline__ void deliver(const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp], const uint64_t *planes,
+                                        int lane, const int (&c)[NB], const int64_t (&j)[NB], Sink &on_hit) {
+    decltype(on_hit.fetch(0)) pre[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) pre[b] = on_hit.fetch(j[b]);  // fetch(-1) loads nothing
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (j[b] < 0) continue;
+        uint32_t t0, len;
+        hit_range<Wp>(lds, key, planes, lane, c[b], t0, len);
+        on_hit.use(j[b], t0, len, pre[b]);
+    }
+}
+
 // Probes NB groups for the lane's row: c[b] = chunk-local group, act[b] = whether the lane
 // probes it.  All occupancy-bit loads are issued before the slot loads, and the slots before any
-// hit is consumed; hits go to on_hit in increasing b (the caller passes increasing groups).
+// hit is fetched; hits go to on_hit in increasing b (the caller passes increasing groups).
 template <int Wp, int NB, class OnHit>
 __device__ __forceinline__ void probe_groups(const SubView &s, const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp],
-                                             uint64_t hrow, const uint64_t *planes, int lane, const int (&c)[NB],
+                                             uint64_t hrow, uint32_t prow, const uint32_t *pf,
+                                             const uint64_t *planes, int lane, const int (&c)[NB],
                                              const bool (&act)[NB], OnHit &on_hit) {
     // unconditional loads: idle lanes read word 0 / slot 0 and ignore them
     uint64_t hh[NB];
     uint32_t pos[NB], word[NB];
+    bool a[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
+        a[b] = act[b] && (!pf || part_pass(pf, prow ^ lds.gpart[c[b] & (kChunk - 1)]));
         hh[b] = hrow ^ lds.hash[c[b] & (kChunk - 1)];
         pos[b] = (uint32_t)hh[b] & s.cmask;
-        word[b] = s.bitmap[act[b] ? (pos[b] >> 5) : 0u];
+        word[b] = s.bitmap[a[b] ? (pos[b] >> 5) : 0u];
     }
     uint64_t slot[NB];
     bool occ[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        occ[b] = act[b] && ((word[b] >> (pos[b] & 31u)) & 1u);
+        occ[b] = a[b] && ((word[b] >> (pos[b] & 31u)) & 1u);
         slot[b] = s.slots[occ[b] ? pos[b] : 0u];
     }
+    int64_t j[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
+        j[b] = -1;
         if (!occ[b]) continue;
         const uint32_t tag = (uint32_t)(hh[b] >> 32);
         uint64_t col[Wp];
 #pragma unroll
         for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ lds.mask[c[b]][w];
-        int64_t j = -1;
-        if ((uint32_t)(slot[b] >> 32) == tag) j = slot_match<Wp>(s, slot[b], 0u, col);
-        if (j < 0) {
+        if ((uint32_t)(slot[b] >> 32) == tag) j[b] = slot_match<Wp>(s, slot[b], 0u, col);
+        if (j[b] < 0) {
             // the home slot held another string: follow the run while slots stay occupied
             const uint32_t nxt = (pos[b] + 1) & s.cmask;
             const uint32_t nw = ((nxt >> 5) == (pos[b] >> 5)) ? word[b] : s.bitmap[nxt >> 5];
-            if ((nw >> (nxt & 31u)) & 1u) j = probe_from<Wp>(s, nxt, 1u, tag, col);
+            if ((nw >> (nxt & 31u)) & 1u) j[b] = probe_from<Wp>(s, nxt, 1u, tag, col);
         }
-        if (j >= 0) {
-            const int cc = c[b];
-            const uint32_t lm = lds.lmask[cc];
-            const uint32_t L = row_lint<Wp>(key, lds.rec[cc], planes, lane) & lm;
-            const uint32_t lo = lds.iptr[cc][L];
-            const uint32_t hi = lm ? (uint32_t)lds.iptr[cc][L + 1] : lds.nterm[cc];
-            on_hit(j, lds.term0[cc] + lo, hi - lo);
-        }
+    }
+    deliver<Wp, NB>(lds, key, planes, lane, c, j, on_hit);
+}
+
+// Filter-first mode with part filters, phase 1: a group whose column passes both part filters
+// is marked for phase 2 (occ) with the run continued past an occupied home slot (occn); no
+// occupancy bit is read (the slot itself shows whether it is empty), so a column that passes
+// costs one slot read and one that fails costs nothing beyond LDS.
+template <int NB>
+__device__ __forceinline__ void part_occupancy(const uint32_t *pf, const uint32_t *lpart, uint32_t prow,
+                                               const int (&c)[NB], const bool (&act)[NB], uint64_t &occ,
+                                               uint64_t &occn) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const bool o = act[b] && part_pass(pf, prow ^ lpart[c[b] & (kChunk - 1)]);
+        occ |= (uint64_t)o << (c[b] & (kChunk - 1));
+        occn |= (uint64_t)o << (c[b] & (kChunk - 1));
     }
 }
 
@@ -304,28 +394,23 @@ __device__ __forceinline__ void resolve_groups(const SubView &s, const ChunkLds<
         pos[b] = (uint32_t)hh[b] & s.cmask;
         slot[b] = s.slots[act[b] ? pos[b] : 0u];  // unconditional, as above
     }
+    int64_t j[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        if (!act[b]) continue;
+        j[b] = -1;
+        // with part filters the home slot was read without its occupancy bit: empty = absent
+        if (!act[b] || slot[b] == ~0ull) continue;
         const uint32_t tag = (uint32_t)(hh[b] >> 32);
         uint64_t col[Wp];
 #pragma unroll
         for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ lds.mask[c[b]][w];
-        int64_t j = -1;
-        if ((uint32_t)(slot[b] >> 32) == tag) j = slot_match<Wp>(s, slot[b], 0u, col);
-        if (j < 0 && next[b]) j = probe_from<Wp>(s, (pos[b] + 1) & s.cmask, 1u, tag, col);
-        if (j >= 0) {
-            const int cc = c[b];
-            const uint32_t lm = lds.lmask[cc];
-            const uint32_t L = row_lint<Wp>(key, lds.rec[cc], planes, lane) & lm;
-            const uint32_t lo = lds.iptr[cc][L];
-            const uint32_t hi = lm ? (uint32_t)lds.iptr[cc][L + 1] : lds.nterm[cc];
-            on_hit(j, lds.term0[cc] + lo, hi - lo);
-        }
+        if ((uint32_t)(slot[b] >> 32) == tag) j[b] = slot_match<Wp>(s, slot[b], 0u, col);
+        if (j[b] < 0 && next[b]) j[b] = probe_from<Wp>(s, (pos[b] + 1) & s.cmask, 1u, tag, col);
     }
+    deliver<Wp, NB>(lds, key, planes, lane, c, j, on_hit);
 }
 
-// Walks all groups for the lane's row and calls on_hit(j, t0, len) for every probe whose
+// Walks all groups for the lane's row and hands on_hit (a HitSink) every probe whose
 // column b_i ^ M_g is in the subspace (j = its index; [t0, t0 + len) = the group's terms for
 // the row's ladder integer), in increasing g.  All threads of the block must call it (chunks
 // are staged through LDS with barriers).  `valid` = the lane owns a row.
@@ -344,14 +429,25 @@ __device__ __forceinline__ void resolve_groups(const SubView &s, const ChunkLds<
 // increasing group order, so both modes give bitwise the same sums.
 template <int Wp, bool LOWER = false, class OnHit>
 __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, const uint64_t (&key)[Wp],
-                                           uint64_t hrow, bool valid, ChunkLds<Wp> &lds, OnHit &&on_hit,
-                                           unsigned long long *probes = nullptr, bool lockstep = false,
-                                           bool filter_first = false) {
+                                           uint64_t hrow, uint32_t prow, bool valid, ChunkLds<Wp> &lds,
+                                           OnHit &&on_hit, unsigned long long *probes = nullptr,
+                                           bool lockstep = false, bool filter_first = false) {
     const int lane = threadIdx.x & 63;
     uint64_t *planes = lds.planes[threadIdx.x >> 6];
 #pragma unroll
     for (int w = 0; w < Wp; ++w) planes[64 * w + lane] = wave_transpose64(valid ? key[w] : 0ull, lane);
     const uint64_t vrows = __ballot(valid);
+    // part filters: one- and two-word keys read an LDS copy (visible after the first chunk's
+    // barrier, before any probe)
+    const uint32_t *pf = nullptr;
+    if (s.pfilt) {
+        if (PartLds<Wp>::words == kPartWords) {
+            for (int k = threadIdx.x; k < kPartWords; k += kBlock) lds.pf[k] = s.pfilt[k];
+            pf = lds.pf;
+        } else {
+            pf = s.pfilt;
+        }
+    }
     for (int64_t g0 = 0; g0 < h.G; g0 += kChunk) {
         const int nc = (int)((h.G - g0) < kChunk ? (h.G - g0) : kChunk);
         __syncthreads();
@@ -367,6 +463,22 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
             lds.lmask[c] = (info & kInfoLadder) ? ((1u << (info & kInfoKMask)) - 1u) : 0u;
 #pragma unroll
             for (int q = 0; q < kIptr; ++q) lds.iptr[c][q] = h.g_iptr[g * kIptr + q];
+            lds.gpart[c] = pf ? h.g_part[g] : 0u;
+        }
+        {
+            constexpr int kTC = TermCacheSize<Wp>::value;
+            const uint32_t tb = h.g_term0[g0];
+            const uint32_t te = h.g_term0[g0 + nc - 1] + h.g_nterm[g0 + nc - 1];
+            const uint32_t tn = kTC > 0 ? min(te - tb, (uint32_t)kTC) : 0u;
+            for (uint32_t k = threadIdx.x; k < tn * 3u * Wp; k += kBlock)
+                lds.tc_cws[0][k] = h.t_cws[(int64_t)tb * 3 * Wp + k];
+            const uint32_t cw = h.coef_f32 ? 1u : 2u;  // 64-bit words per coefficient
+            const uint64_t *__restrict__ cs = (const uint64_t *)h.t_coef + (int64_t)tb * cw;
+            for (uint32_t k = threadIdx.x; k < tn * cw; k += kBlock) lds.tc_coef[k / cw][k % cw] = cs[k];
+            if (threadIdx.x == 0) {
+                lds.tc_base = tb;
+                lds.tc_count = tn;
+            }
         }
         // scan: lane l evaluates group g0 + l for the wave's 64 rows, then the masks are
         // transposed to one live-group mask per row
@@ -401,13 +513,26 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                     c[b] = todo ? (int)__builtin_ctzll(todo) : -1;
                     todo &= todo - 1ull;
                 }
+                uint32_t po = 0, pn = 0;
+                if (pf) {
+                    // part filters instead of occupancy bits (see part_occupancy)
+#pragma unroll
+                    for (int b = 0; b < kOccBatch; ++b) {
+                        const uint32_t a = c[b] >= 0 ? (uint32_t)(live >> (c[b] & (kChunk - 1))) & 1u : 0u;
+                        const uint32_t t = a && part_pass(pf, prow ^ lds.gpart[c[b] & (kChunk - 1)]) ? 1u : 0u;
+                        po |= t << b;
+                        pn |= t << b;
+                    }
+                    occ |= (uint64_t)po << k0;
+                    occn |= (uint64_t)pn << k0;
+                    continue;
+                }
                 uint32_t pos[kOccBatch], word[kOccBatch];
 #pragma unroll
                 for (int b = 0; b < kOccBatch; ++b) {
                     pos[b] = (uint32_t)(hrow ^ lds.hash[c[b] & (kChunk - 1)]) & s.cmask;
                     word[b] = c[b] >= 0 ? s.bitmap[pos[b] >> 5] : 0u;  // uniform condition
                 }
-                uint32_t po = 0, pn = 0;
 #pragma unroll
                 for (int b = 0; b < kOccBatch; ++b) {
                     // a: the lane's row has the group live; t: bit 0 = home slot occupied,
@@ -450,7 +575,10 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                     rem &= rem - 1ull;
                     act[b] = c[b] >= 0;
                 }
-                occupancy<kOccBatch>(s, lds.hash, hrow, c, act, occ, occn);
+                if (pf)
+                    part_occupancy<kOccBatch>(pf, lds.gpart, prow, c, act, occ, occn);
+                else
+                    occupancy<kOccBatch>(s, lds.hash, hrow, c, act, occ, occn);
             }
             // phase 2: the slots of the occupied home slots, lowest group first
             while (__any(occ != 0ull)) {
@@ -477,7 +605,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                     todo &= todo - 1ull;
                     act[b] = c[b] >= 0 && ((live >> c[b]) & 1ull);
                 }
-                probe_groups<Wp, kLockBatch>(s, lds, key, hrow, planes, lane, c, act, on_hit);
+                probe_groups<Wp, kLockBatch>(s, lds, key, hrow, prow, pf, planes, lane, c, act, on_hit);
             }
             continue;
         }
@@ -494,7 +622,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
             bool act[kProbeBatch];
 #pragma unroll
             for (int b = 0; b < kProbeBatch; ++b) act[b] = c[b] >= 0;
-            probe_groups<Wp, kProbeBatch>(s, lds, key, hrow, planes, lane, c, act, on_hit);
+            probe_groups<Wp, kProbeBatch>(s, lds, key, hrow, prow, pf, planes, lane, c, act, on_hit);
         }
     }
 }

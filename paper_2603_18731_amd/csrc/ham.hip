@@ -8,6 +8,7 @@
 #include "device.h"
 #include "engine.h"
 #include "matvec.h"
+#include "spmv.h"
 
 namespace qsd {
 namespace {
@@ -47,42 +48,21 @@ __global__ void k_to_f32(const double *__restrict__ in, float *__restrict__ out,
 
 // ------------------------------------------------------------------------------- matvec
 
-// Rows in slot order touch x, d and y at random positions.  With a slot-order schedule the launch
-// is split by role: the first `nd` workgroups (a multiple of 8, so the XCD of a workgroup is still
-// its index mod 8) write y = d x for the rows without off-diagonal elements in canonical order,
-// the rest take the slot-order tiles and write only the rows with elements; no row is written
-// twice, and each row's value is formed with the same operations as in every other schedule.
-// (Two- and four-word single-vector kernels are held to 96 registers, five waves per SIMD.)
-template <int Wp, int NV, class ET, bool CPLX>
-__global__ __launch_bounds__(kBlock, (Wp == 2 || Wp == 4) && NV == 1 ? 5 : 1) void k_matvec(
-    SubView s, HamView h, const ET *__restrict__ dre,
-                                                   const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
-                                                   ET *__restrict__ y, int64_t ldy, int nvec, uint32_t sched,
-                                                   const uint64_t *__restrict__ rowbits, unsigned nd) {
-    __shared__ ChunkLds<Wp> lds;
-    if (blockIdx.x < nd) {
-        diag_rows_block<NV, ET, CPLX>(dre, dim, x, ldx, y, ldy, nvec, s.N, rowbits, (int64_t)blockIdx.x * kBlock);
-        return;
-    }
-    const int64_t row0 = tile_index(blockIdx.x - nd, gridDim.x - nd, (sched & QSD_SCHED_XCD_REMAP) != 0) * kBlock;
-    matvec_block<Wp, NV, ET, CPLX>(s, h, dre, dim, x, ldx, y, ldy, nvec, row0, lds, (sched & QSD_SCHED_SLOT_ORDER) != 0,
-                                   (sched & QSD_SCHED_LOCKSTEP) != 0, (sched & QSD_SCHED_FILTER_FIRST) != 0, nd > 0);
-}
-
 // Bit r of `bits` = row r has an off-diagonal element (a probe whose column is present and
 // whose term range has a term passing the row's projector bits).
 template <int Wp>
 __global__ __launch_bounds__(kBlock) void k_row_bits(SubView s, HamView h, uint64_t *__restrict__ bits) {
     __shared__ ChunkLds<Wp> lds;
     uint64_t key[Wp], hrow;
+    uint32_t prow;
     bool valid;
     const int64_t row0 = (int64_t)blockIdx.x * kBlock;
-    load_row<Wp>(s, row0, key, hrow, valid);
+    load_row<Wp>(s, row0, key, hrow, prow, valid);
     bool has = false;
-    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t, uint32_t t0, uint32_t len) {
+    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink([&](int64_t, uint32_t t0, uint32_t len, int) {
         double vre, vim;
-        if (range_value<Wp, double>(h, key, t0, len, vre, vim)) has = true;
-    }, nullptr, false, true);
+        if (range_value<Wp, double>(h, lds, key, t0, len, vre, vim)) has = true;
+    }), nullptr, false, true);
     const uint64_t w = __ballot(has && valid);
     const int64_t word = (row0 >> 6) + (threadIdx.x >> 6);
     if ((threadIdx.x & 63) == 0 && word * 64 < s.N) bits[word] = w;
@@ -94,13 +74,14 @@ template <int Wp>
 __global__ __launch_bounds__(kBlock) void k_csr_count(SubView s, HamView h, int64_t *__restrict__ counts) {
     __shared__ ChunkLds<Wp> lds;
     uint64_t key[Wp], hrow;
+    uint32_t prow;
     bool valid;
-    const int64_t r = load_row<Wp>(s, (int64_t)blockIdx.x * kBlock, key, hrow, valid);
+    const int64_t r = load_row<Wp>(s, (int64_t)blockIdx.x * kBlock, key, hrow, prow, valid);
     int64_t cnt = 1;  // diagonal
-    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t, uint32_t t0, uint32_t len) {
+    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink([&](int64_t, uint32_t t0, uint32_t len, int) {
         double vre, vim;
-        if (range_value<Wp, double>(h, key, t0, len, vre, vim)) ++cnt;
-    }, nullptr, false, true);
+        if (range_value<Wp, double>(h, lds, key, t0, len, vre, vim)) ++cnt;
+    }), nullptr, false, true);
     if (valid) counts[r] = cnt;
 }
 
@@ -110,13 +91,14 @@ template <int Wp>
 __global__ __launch_bounds__(kBlock) void k_probe_count(SubView s, HamView h, unsigned long long *__restrict__ acc) {
     __shared__ ChunkLds<Wp> lds;
     uint64_t key[Wp], hrow;
+    uint32_t prow;
     bool valid;
-    load_row<Wp>(s, (int64_t)blockIdx.x * kBlock, key, hrow, valid);
+    load_row<Wp>(s, (int64_t)blockIdx.x * kBlock, key, hrow, prow, valid);
     unsigned long long probes = 0, hits = 0;
-    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t, uint32_t t0, uint32_t len) {
+    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink([&](int64_t, uint32_t t0, uint32_t len, int) {
         double vre, vim;
-        if (range_value<Wp, double>(h, key, t0, len, vre, vim)) ++hits;
-    }, &probes, false, true);
+        if (range_value<Wp, double>(h, lds, key, t0, len, vre, vim)) ++hits;
+    }), &probes, false, true);
     for (int d = 32; d >= 1; d >>= 1) {
         probes += __shfl_xor(probes, d, 64);
         hits += __shfl_xor(hits, d, 64);
@@ -134,8 +116,9 @@ __global__ __launch_bounds__(kBlock) void k_csr_fill(SubView s, HamView h, const
                                                      int64_t *__restrict__ cols, typename C2<ET>::T *__restrict__ vals) {
     __shared__ ChunkLds<Wp> lds;
     uint64_t key[Wp], hrow;
+    uint32_t prow;
     bool valid;
-    const int64_t r = load_row<Wp>(s, (int64_t)blockIdx.x * kBlock, key, hrow, valid);
+    const int64_t r = load_row<Wp>(s, (int64_t)blockIdx.x * kBlock, key, hrow, prow, valid);
     int64_t o = indptr[r];
     if (valid) {
         cols[o] = r;
@@ -145,13 +128,13 @@ __global__ __launch_bounds__(kBlock) void k_csr_fill(SubView s, HamView h, const
         vals[o] = d;
     }
     ++o;
-    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t j, uint32_t t0, uint32_t len) {
+    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink([&](int64_t j, uint32_t t0, uint32_t len, int) {
         typename C2<ET>::T v;
-        if (!range_value<Wp, ET>(h, key, t0, len, v.x, v.y)) return;
+        if (!range_value<Wp, ET>(h, lds, key, t0, len, v.x, v.y)) return;
         cols[o] = j;
         vals[o] = v;
         ++o;
-    }, nullptr, false, true);
+    }), nullptr, false, true);
 }
 
 // Sort each row's entries by column: one workgroup per row; for rows up to kSortLds entries
@@ -206,10 +189,15 @@ int upload(T **dst, const std::vector<T> &src, hipStream_t st) {
 
 void free_ham(qsd_ham *h) {
     if (!h) return;
+    if (h->s) {
+        auto &b = h->s->bound;
+        b.erase(std::remove(b.begin(), b.end(), h), b.end());
+    }
     dev_free(h->diag);
     dev_free(h->diag_im);
     dev_free(h->g_mask);
     dev_free(h->g_hash);
+    dev_free(h->g_part);
     dev_free(h->g_pos);
     dev_free(h->g_scan);
     dev_free(h->g_info);
@@ -234,7 +222,13 @@ void launch_diag(const qsd_ham *h, const uint64_t *cws, const double *coef, int6
 int create_impl(qsd_ham *h, hipStream_t st) {
     const qsd_op *op = h->op;
     QSD_TRY(upload(&h->g_mask, op->g_mask, st));
-    QSD_TRY(upload(&h->g_hash, op->g_hash, st));
+    const std::vector<uint64_t> gh = group_hashes(op, h->s->z);  // alive until the synchronize below
+    QSD_TRY(upload(&h->g_hash, gh, st));
+    std::vector<uint32_t> gp;
+    if (h->s->split > 0) {
+        gp = group_parts(op, h->s->pz);
+        QSD_TRY(upload(&h->g_part, gp, st));
+    }
     QSD_TRY(upload(&h->g_pos, op->g_pos, st));
     QSD_TRY(upload(&h->g_scan, op->g_scan, st));
     QSD_TRY(upload(&h->g_info, op->g_info, st));
@@ -275,40 +269,14 @@ int create_impl(qsd_ham *h, hipStream_t st) {
     return rc;
 }
 
-template <int Wp, int NV, class ET, bool CPLX>
-void launch_mv(const qsd_ham *h, const void *x, int64_t ldx, void *y, int64_t ldy, int nvec, hipStream_t st) {
-    const bool f32 = std::is_same<ET, float>::value;
-    const ET *dre = f32 ? (const ET *)h->diag32 : (const ET *)h->diag;
-    const ET *dim = CPLX ? (f32 ? (const ET *)h->diag32_im : (const ET *)h->diag_im) : nullptr;
-    const unsigned tiles = grid_for(h->N, kBlock);
-    const bool split = (h->schedule & QSD_SCHED_SLOT_ORDER) && h->rowbits;
-    const unsigned nd = split ? (tiles + 7u) & ~7u : 0u;
-    k_matvec<Wp, NV, ET, CPLX><<<nd + tiles, kBlock, 0, st>>>(sview(h->s), view_of(h, f32), dre, dim, (const ET *)x, ldx,
-                                                             (ET *)y, ldy, nvec, h->schedule, h->rowbits, nd);
-}
-
-template <int Wp, class ET, bool CPLX>
-void dispatch_nv(const qsd_ham *h, const void *x, int64_t ldx, void *y, int64_t ldy, int nvec, hipStream_t st) {
-    if (nvec <= 1)
-        launch_mv<Wp, 1, ET, CPLX>(h, x, ldx, y, ldy, nvec, st);
-    else if (nvec <= 2)
-        launch_mv<Wp, 2, ET, CPLX>(h, x, ldx, y, ldy, nvec, st);
-    else if (nvec <= 4 || CPLX)
-        launch_mv<Wp, 4, ET, CPLX>(h, x, ldx, y, ldy, nvec, st);
-    else if (nvec <= 8)
-        launch_mv<Wp, CPLX ? 4 : 8, ET, CPLX>(h, x, ldx, y, ldy, nvec, st);
-    else
-        launch_mv<Wp, CPLX ? 4 : 16, ET, CPLX>(h, x, ldx, y, ldy, nvec, st);
-}
-
 template <class ET, bool CPLX>
 void dispatch_w(const qsd_ham *h, const void *x, int64_t ldx, void *y, int64_t ldy, int nvec, hipStream_t st) {
     switch (h->Wp) {
-        case 1: dispatch_nv<1, ET, CPLX>(h, x, ldx, y, ldy, nvec, st); break;
-        case 2: dispatch_nv<2, ET, CPLX>(h, x, ldx, y, ldy, nvec, st); break;
-        case 4: dispatch_nv<4, ET, CPLX>(h, x, ldx, y, ldy, nvec, st); break;
-        case 8: dispatch_nv<8, ET, CPLX>(h, x, ldx, y, ldy, nvec, st); break;
-        case 16: dispatch_nv<16, ET, CPLX>(h, x, ldx, y, ldy, nvec, st); break;
+        case 1: spmv_dispatch<1, ET, CPLX>(h, x, ldx, y, ldy, nvec, st); break;
+        case 2: spmv_dispatch<2, ET, CPLX>(h, x, ldx, y, ldy, nvec, st); break;
+        case 4: spmv_dispatch<4, ET, CPLX>(h, x, ldx, y, ldy, nvec, st); break;
+        case 8: spmv_dispatch<8, ET, CPLX>(h, x, ldx, y, ldy, nvec, st); break;
+        case 16: spmv_dispatch<16, ET, CPLX>(h, x, ldx, y, ldy, nvec, st); break;
     }
 }
 
@@ -371,6 +339,7 @@ extern "C" int qsd_ham_create(const qsd_subspace *s, const qsd_op *op, uint32_t 
         free_ham(h);
         return rc;
     }
+    s->bound.push_back(h);
     *out = h;
     return QSD_OK;
 }
@@ -625,7 +594,7 @@ extern "C" int qsd_ham_autotune(qsd_ham *h, int32_t nvec, int32_t dtype, int32_t
     if (!h) return fail(QSD_ERR_INVALID_ARG, "NULL handle");
     if (nvec < 1 || nvec > 16) return fail(QSD_ERR_INVALID_ARG, "nvec must be in [1, 16]");
     if (reps < 1) return fail(QSD_ERR_INVALID_ARG, "reps must be >= 1");
-    if (flags & ~(QSD_TUNE_SCHEDULE | QSD_TUNE_LOAD)) return fail(QSD_ERR_INVALID_ARG, "unknown tuning flags");
+    if (flags & ~(QSD_TUNE_SCHEDULE | QSD_TUNE_LOAD | QSD_TUNE_SPLIT)) return fail(QSD_ERR_INVALID_ARG, "unknown tuning flags");
     QSD_TRY(check_dtype(h, dtype));
     hipStream_t st = (hipStream_t)stream;
     qsd_subspace *sub = const_cast<qsd_subspace *>(h->s);
@@ -651,19 +620,21 @@ extern "C" int qsd_ham_autotune(qsd_ham *h, int32_t nvec, int32_t dtype, int32_t
     if (rc == QSD_OK && (flags & QSD_TUNE_SCHEDULE)) rc = ensure_rowbits(h, st);
     const uint32_t sched0 = h->schedule;
     const int64_t C0 = sub->C;
+    const int32_t split0 = sub->split;
+    const double load0 = (double)sub->N / (double)sub->C;
     float ms_before = INFINITY, best_ms = INFINITY;
     if (rc == QSD_OK) rc = time_it(ms_before);
     uint32_t best_sched = sched0;
-    double best_load = (double)sub->N / (double)sub->C;
-    int64_t best_C = C0;
+    double best_load = load0;
+    int32_t best_split = split0;
     auto consider = [&](uint32_t sc, double l, float &ms) -> int {
         h->schedule = sc;
         QSD_TRY(time_it(ms));
         if (ms < best_ms) {
             best_ms = ms;
             best_sched = sc;
-            best_C = sub->C;
-            best_load = l > 0.0 ? l : best_load;
+            best_load = l;
+            best_split = sub->split;
         }
         return QSD_OK;
     };
@@ -672,7 +643,7 @@ extern "C" int qsd_ham_autotune(qsd_ham *h, int32_t nvec, int32_t dtype, int32_t
     if (flags & QSD_TUNE_SCHEDULE) {
         for (uint32_t sc = 0; sc <= kSchedAll && rc == QSD_OK; ++sc) {
             float ms = 0.0f;
-            rc = consider(sc, 0.0, ms);
+            rc = consider(sc, load0, ms);
             ranked.push_back({ms, sc});
         }
         std::sort(ranked.begin(), ranked.end());
@@ -680,23 +651,32 @@ extern "C" int qsd_ham_autotune(qsd_ham *h, int32_t nvec, int32_t dtype, int32_t
     } else {
         ranked.push_back({0.0f, sched0});
     }
-    if (flags & QSD_TUNE_LOAD) {
-        for (double l : {0.03125, 0.0625, 0.125, 0.25, 0.5}) {
-            if (rc != QSD_OK) break;
-            if ((rc = qsd_subspace_rehash(sub, l, stream)) != QSD_OK) break;
-            if (sub->C == C0 && (flags & QSD_TUNE_SCHEDULE)) {  // already timed
-                if (best_C == C0 && best_load == (double)sub->N / (double)C0) best_load = l;
-                continue;
-            }
-            for (auto &p : ranked) {
-                float ms = 0.0f;
-                if ((rc = consider(p.second, l, ms)) != QSD_OK) break;
-            }
+    // candidate tables: load x part-filter split (none, or at the middle qubit)
+    std::vector<int32_t> splits{split0};
+    if ((flags & QSD_TUNE_SPLIT) && h->s->n_qubits >= 2) splits.push_back(split0 ? 0 : h->s->n_qubits / 2);
+    std::vector<std::pair<double, int32_t>> tables;
+    for (size_t k = 0; k < splits.size(); ++k) {
+        if (flags & QSD_TUNE_LOAD)
+            for (double l : {0.03125, 0.0625, 0.125, 0.25, 0.5}) tables.push_back({l, splits[k]});
+        else if (k > 0)
+            tables.push_back({load0, splits[k]});
+    }
+    for (auto &tb : tables) {
+        if (rc != QSD_OK) break;
+        if ((rc = qsd_subspace_rehash(sub, tb.first, tb.second, stream)) != QSD_OK) break;
+        if (sub->C == C0 && sub->split == split0 && (flags & QSD_TUNE_SCHEDULE)) {
+            // the starting table, already timed under every schedule
+            if (best_load == load0 && best_split == split0) best_load = tb.first;
+            continue;
+        }
+        for (auto &p : ranked) {
+            float ms = 0.0f;
+            if ((rc = consider(p.second, tb.first, ms)) != QSD_OK) break;
         }
     }
     // keep the best table and schedule (or restore the starting ones after an error)
     if (rc == QSD_OK) {
-        if (sub->C != best_C) rc = qsd_subspace_rehash(sub, best_load, stream);
+        rc = qsd_subspace_rehash(sub, best_load, best_split, stream);
         h->schedule = best_sched;
     } else {
         h->schedule = sched0;
@@ -710,6 +690,7 @@ extern "C" int qsd_ham_autotune(qsd_ham *h, int32_t nvec, int32_t dtype, int32_t
         result->schedule = best_sched;
         result->capacity = sub->C;
         result->max_load = best_load;
+        result->split = sub->split;
         result->ms = best_ms;
         result->ms_before = ms_before;
     }

@@ -8,12 +8,14 @@ namespace qsd {
 
 inline HamView ham_view(const qsd_ham *h, bool f32) {
     return HamView{h->g_mask, h->g_hash, h->g_pos,  h->g_scan, h->g_info, h->g_term0, h->g_nterm,
-                   h->g_iptr, h->t_cws,  f32 ? (const void *)h->t_coef32 : (const void *)h->t_coef, h->G};
+                   h->g_iptr, h->t_cws,  f32 ? (const void *)h->t_coef32 : (const void *)h->t_coef, h->G,
+                   f32 ? 1 : 0, h->g_part};
 }
 
 inline SubView sub_view(const qsd_subspace *s) {
-    return SubView{s->keys,  s->hkey, s->slots, s->bitmap, s->N, (uint32_t)(s->C - 1), s->exact ? 1u : 0u,
-                   s->rows.order, s->rows.keys, s->rows.hkey};
+    return SubView{s->keys,       s->hkey,      s->slots,     s->bitmap, s->N, (uint32_t)(s->C - 1),
+                   s->exact ? 1u : 0u, s->rows.order, s->rows.keys, s->rows.hkey, s->pfilt, s->pkey,
+                   s->rows.pkey};
 }
 
 // Row tile of workgroup b out of G.  Workgroups are dispatched round-robin over the 8 XCDs, so
@@ -29,7 +31,7 @@ __device__ __forceinline__ int64_t tile_index(unsigned b, unsigned G, bool remap
 // with `by_slot` (clamped to a valid row for lanes past the end).
 template <int Wp>
 __device__ __forceinline__ int64_t load_row(const SubView &s, int64_t row0, uint64_t (&key)[Wp], uint64_t &hrow,
-                                            bool &valid, bool by_slot = false) {
+                                            uint32_t &prow, bool &valid, bool by_slot = false) {
     const int64_t i = row0 + threadIdx.x;
     valid = i < s.N;
     const int64_t p = valid ? i : s.N - 1;
@@ -37,11 +39,13 @@ __device__ __forceinline__ int64_t load_row(const SubView &s, int64_t row0, uint
 #pragma unroll
         for (int w = 0; w < Wp; ++w) key[w] = s.okeys[(int64_t)w * s.N + p];
         hrow = s.ohkey[p];
+        prow = s.pfilt ? s.opkey[p] : 0u;
         return s.order[p];
     }
 #pragma unroll
     for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + p];
     hrow = s.hkey[p];
+    prow = s.pfilt ? s.pkey[p] : 0u;
     return p;
 }
 
@@ -97,8 +101,9 @@ __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h,
                                              ChunkLds<Wp> &lds, bool by_slot = false, bool lockstep = false,
                                              bool filter_first = false, bool split = false) {
     uint64_t key[Wp], hrow;
+    uint32_t prow;
     bool valid;
-    const int64_t r = load_row<Wp>(s, row0, key, hrow, valid, by_slot);
+    const int64_t r = load_row<Wp>(s, row0, key, hrow, prow, valid, by_slot);
     double acc_re[NV], acc_im[NV];
     bool have = !split;  // acc holds d_r x[r] (+ the elements so far)
 #pragma unroll
@@ -117,11 +122,11 @@ __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h,
             }
         }
     }
-    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t j, uint32_t t0, uint32_t len) {
-        // one real vector: x_j is requested before the term loop, so that both are in flight
-        const double xj = (!CPLX && NV == 1) ? (double)x[j * ldx] : 0.0;
+    // one real vector: x_j is fetched for a whole batch of hits before any is consumed
+    auto fetch = [&](int64_t j) -> double { return (!CPLX && NV == 1 && j >= 0) ? (double)x[j * ldx] : 0.0; };
+    auto use = [&](int64_t j, uint32_t t0, uint32_t len, double xj) {
         ET vre, vim;
-        if (!range_value<Wp, ET>(h, key, t0, len, vre, vim)) return;
+        if (!range_value<Wp, ET>(h, lds, key, t0, len, vre, vim)) return;
         if (!have) {
             have = true;
             const double dr = (double)dre[r];
@@ -149,7 +154,8 @@ __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h,
                 }
             }
         }
-    }, nullptr, lockstep, filter_first);
+    };
+    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink(use, fetch), nullptr, lockstep, filter_first);
     if (!valid || !have) return;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {

@@ -16,12 +16,13 @@
 
 namespace qsd {
 
-bool exact_tags_ok(int n_qubits, int W, int64_t N, int64_t C) {
+bool exact_tags_ok(const std::vector<uint64_t> &z, int W, int64_t N, int64_t C) {
+    const int n_qubits = (int)z.size();
     if (W != 1 || N >= (1ll << 26) || n_qubits > 64) return false;
     const uint64_t P = (uint64_t)(C - 1) | 0xFFFFFFFF00000000ull;  // home-slot bits and tag bits
     uint64_t piv[64] = {0};  // piv[b]: the basis vector whose leading bit is b
     for (int q = 0; q < n_qubits; ++q) {
-        uint64_t v = qubit_hash_value(q) & P;
+        uint64_t v = z[q] & P;
         int b = 63;
         while (v) {
             while (!((v >> b) & 1ull)) --b;  // leading bit of v
@@ -44,15 +45,56 @@ uint64_t qubit_hash_value(int q) {
     return z ^ (z >> 31);
 }
 
-void hash_byte_tables(int Wp, std::vector<uint64_t> &tab) {
+void hash_words(int n_qubits, std::vector<uint64_t> &z) {
+    z.resize(n_qubits);
+    for (int q = 0; q < n_qubits; ++q) z[q] = qubit_hash_value(q);
+}
+
+void part_words(int n_qubits, int split, std::vector<uint32_t> &pz) {
+    pz.assign(n_qubits, 0u);
+    if (split <= 0) return;
+    const int nlo = split, nhi = n_qubits - split;
+    for (int q = 0; q < n_qubits; ++q) {
+        const bool lo = q < split;
+        const int k = lo ? q : q - split;
+        // a part of at most 16 qubits is indexed by its own bits (no false passes); a longer
+        // one by a pseudo-random 16-bit linear image (another splitmix64 stream)
+        const uint32_t v = (lo ? nlo : nhi) <= 16 ? (1u << k) : (uint32_t)(qubit_hash_value(q + 65536) & 0xFFFFu);
+        pz[q] = lo ? v : (v << 16);
+    }
+}
+
+void hash_byte_tables(int Wp, const std::vector<uint64_t> &z, std::vector<uint64_t> &tab) {
     tab.assign((size_t)Wp * 8 * 256, 0);
     for (int c = 0; c < Wp * 8; ++c)
         for (int v = 0; v < 256; ++v) {
             uint64_t h = 0;
             for (int b = 0; b < 8; ++b)
-                if (v >> b & 1) h ^= qubit_hash_value(8 * c + b);
+                if ((v >> b & 1) && 8 * c + b < (int)z.size()) h ^= z[8 * c + b];
             tab[(size_t)c * 256 + v] = h;
         }
+}
+
+std::vector<uint32_t> group_parts(const qsd_op *op, const std::vector<uint32_t> &pz) {
+    const int Wp = op->Wp;
+    const size_t G = op->g_mask.size() / (size_t)Wp;
+    std::vector<uint32_t> out(G, 0u);
+    for (size_t g = 0; g < G; ++g)
+        for (int w = 0; w < Wp; ++w)
+            for (uint64_t m = op->g_mask[g * Wp + w]; m; m &= m - 1)
+                out[g] ^= pz[64 * w + __builtin_ctzll(m)];
+    return out;
+}
+
+std::vector<uint64_t> group_hashes(const qsd_op *op, const std::vector<uint64_t> &z) {
+    const int Wp = op->Wp;
+    const size_t G = op->g_mask.size() / (size_t)Wp;
+    std::vector<uint64_t> out(G, 0);
+    for (size_t g = 0; g < G; ++g)
+        for (int w = 0; w < Wp; ++w)
+            for (uint64_t m = op->g_mask[g * Wp + w]; m; m &= m - 1)
+                out[g] ^= z[64 * w + __builtin_ctzll(m)];
+    return out;
 }
 
 }  // namespace qsd
@@ -420,10 +462,7 @@ extern "C" int qsd_op_compile(int32_t n_qubits, int64_t n_terms, const int64_t *
         }
         uint64_t gpos = 0;
         for (size_t k = 0; k < pos.size() && k < 4; ++k) gpos |= (uint64_t)pos[k] << (16 * k);
-        uint64_t gh = 0;
-        for (int p : pos) gh ^= qubit_hash_value(p);
         op->g_mask.insert(op->g_mask.end(), M.begin(), M.end());
-        op->g_hash.push_back(gh);
         op->g_pos.push_back(gpos);
         // Scan record.  The device forms a 4-bit ladder integer from four positions (unused
         // ones repeat qubit j's bit, so they are don't-cares): bits 0..15 hold the live table

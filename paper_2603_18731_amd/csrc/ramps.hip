@@ -37,10 +37,11 @@ __global__ __launch_bounds__(kBlock) void k_ramps_level(SubView s, HamView h, co
 #pragma unroll
     for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + r];
     const uint64_t hrow = s.hkey[r];
-    row_engine<Wp>(s, h, key, hrow, valid, lds, [&](int64_t k, uint32_t t0, uint32_t len) {
+    const uint32_t prow = s.pfilt ? s.pkey[r] : 0u;
+    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink([&](int64_t k, uint32_t t0, uint32_t len, int) {
         if (in_s0[k]) return;  // the model space is not followed
         double vre, vim;
-        if (!range_value<Wp, double>(h, key, t0, len, vre, vim)) return;
+        if (!range_value<Wp, double>(h, lds, key, t0, len, vre, vim)) return;
         double amp, next;
         {
 #pragma clang fp contract(off)
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_ramps_level(SubView s, HamView h, co
                 n_pre[pos] = next;
             }
         }
-    }, nullptr, false, true);
+    }), nullptr, false, true);
 }
 
 __global__ void k_mark(const int64_t *__restrict__ idx, int64_t n, uint8_t *__restrict__ a, uint8_t *__restrict__ b) {

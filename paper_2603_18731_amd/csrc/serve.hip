@@ -788,8 +788,7 @@ extern "C" int qsd_matvec_batched(int32_t n, const qsd_ham *const *hams, const v
                 if (h->Wp != Wp || nvecs[i] <= c0 || h->N == 0) continue;
                 MvReq R{};
                 R.s = sub_view(h->s);
-                R.h = HamView{h->g_mask, h->g_hash, h->g_pos, h->g_scan, h->g_info, h->g_term0, h->g_nterm, h->g_iptr,
-                              h->t_cws, f32 ? (const void *)h->t_coef32 : (const void *)h->t_coef, h->G};
+                R.h = ham_view(h, f32);
                 R.dre = f32 ? (const void *)h->diag32 : (const void *)h->diag;
                 R.dim = cplx ? (f32 ? (const void *)h->diag32_im : (const void *)h->diag_im) : nullptr;
                 R.x = (const char *)xs[i] + c0 * esz;

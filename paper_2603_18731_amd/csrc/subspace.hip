@@ -325,21 +325,44 @@ __global__ __launch_bounds__(kBlock) void k_slot_order(const uint32_t *__restric
 
 __global__ __launch_bounds__(kBlock) void k_gather_rows(const uint64_t *__restrict__ keys,
                                                         const uint64_t *__restrict__ hkey,
+                                                        const uint32_t *__restrict__ pkey,
                                                         const uint32_t *__restrict__ order, int64_t N, int Wp,
-                                                        uint64_t *__restrict__ okeys, uint64_t *__restrict__ ohkey) {
+                                                        uint64_t *__restrict__ okeys, uint64_t *__restrict__ ohkey,
+                                                        uint32_t *__restrict__ opkey) {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= N) return;
     const int64_t r = order[k];
     for (int w = 0; w < Wp; ++w) okeys[(int64_t)w * N + k] = keys[(int64_t)w * N + r];
     ohkey[k] = hkey[r];
+    if (pkey) opkey[k] = pkey[r];
+}
+
+// Packed part indices of every row (byte tabulation of the part words) and both part filters:
+// bit (low index) of the low filter and bit (high index) of the high filter, for every row.
+template <int Wp>
+__global__ __launch_bounds__(kBlock) void k_part_keys(const uint64_t *__restrict__ keys, int64_t N,
+                                                      const uint32_t *__restrict__ ptab, uint32_t *__restrict__ pkey,
+                                                      uint32_t *__restrict__ pfilt) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= N) return;
+    uint32_t p = 0;
+#pragma unroll
+    for (int w = 0; w < Wp; ++w) {
+        const uint64_t k = keys[(int64_t)w * N + i];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) p ^= ptab[(w * 8 + c) * 256 + ((k >> (8 * c)) & 255u)];
+    }
+    pkey[i] = p;
+    atomicOr(&pfilt[(p & 0xFFFFu) >> 5], 1u << (p & 31u));
+    atomicOr(&pfilt[kPartWords / 2 + (p >> 21)], 1u << ((p >> 16) & 31u));
 }
 
 // The rows listed in the order of their slots (a compaction of the occupancy bitmap), with
 // their keys and hashes in that order.  A run of consecutive entries holds rows whose home slots
 // share a stretch of the table, so for any group their columns b ^ M_g, whose hashes are
 // h(b) ^ h(M_g), share a stretch too.
-int build_order(const qsd_subspace *sub, int64_t C, bool exact, const uint64_t *slots, const uint32_t *bitmap,
-                SlotRows *out, hipStream_t st) {
+int build_order(const qsd_subspace *sub, const uint64_t *hkey, const uint32_t *pkey, int64_t C, bool exact,
+                const uint64_t *slots, const uint32_t *bitmap, SlotRows *out, hipStream_t st) {
     const int64_t N = sub->N, nw = C / 32;
     int64_t *base = nullptr;
     SlotRows o;
@@ -347,13 +370,15 @@ int build_order(const qsd_subspace *sub, int64_t C, bool exact, const uint64_t *
     int rc = dev_alloc(&o.order, N);
     if (rc == QSD_OK) rc = dev_alloc(&o.keys, (size_t)sub->Wp * N);
     if (rc == QSD_OK) rc = dev_alloc(&o.hkey, N);
+    if (rc == QSD_OK && pkey) rc = dev_alloc(&o.pkey, N);
     if (rc == QSD_OK) {
         k_word_counts<<<grid_for(nw, kBlock), kBlock, 0, st>>>(bitmap, nw, base);
         rc = exclusive_scan_i64(base, base, nw, st);
     }
     if (rc == QSD_OK) {
         k_slot_order<<<grid_for(nw, kBlock), kBlock, 0, st>>>(bitmap, slots, nw, base, exact ? 1u : 0u, o.order);
-        k_gather_rows<<<grid_for(N, kBlock), kBlock, 0, st>>>(sub->keys, sub->hkey, o.order, N, sub->Wp, o.keys, o.hkey);
+        k_gather_rows<<<grid_for(N, kBlock), kBlock, 0, st>>>(sub->keys, hkey, pkey, o.order, N, sub->Wp, o.keys,
+                                                              o.hkey, o.pkey);
         if (hipStreamSynchronize(st) != hipSuccess)
             rc = fail(QSD_ERR_HIP, "slot order failed: %s", hipGetErrorString(hipGetLastError()));
     }
@@ -457,9 +482,10 @@ int build_impl(qsd_subspace *sub, const uint64_t *d_bits, int64_t n_in, uint32_t
             break;
         }
         sub->C = C;
-        sub->exact = exact_tags_ok(sub->n_qubits, sub->W, N, C);
+        hash_words(sub->n_qubits, sub->z);
+        sub->exact = exact_tags_ok(sub->z, sub->W, N, C);
         std::vector<uint64_t> tab;
-        hash_byte_tables(Wp, tab);
+        hash_byte_tables(Wp, sub->z, tab);
         if ((rc = dev_alloc(&sub->ztab, tab.size())) != QSD_OK) break;
         if ((rc = dev_alloc(&sub->slots, C)) != QSD_OK) break;
         if ((rc = dev_alloc(&sub->bitmap, C / 32)) != QSD_OK) break;
@@ -476,7 +502,7 @@ int build_impl(qsd_subspace *sub, const uint64_t *d_bits, int64_t n_in, uint32_t
             rc = fail(QSD_ERR_HIP, "hash build failed: %s", hipGetErrorString(hipGetLastError()));
             break;
         }
-        rc = build_order(sub, C, sub->exact, sub->slots, sub->bitmap, &sub->rows, st);
+        rc = build_order(sub, sub->hkey, nullptr, C, sub->exact, sub->slots, sub->bitmap, &sub->rows, st);
     } while (0);
     cleanup();
     return rc;
@@ -489,13 +515,16 @@ void free_sub(qsd_subspace *s) {
     dev_free(s->slots);
     dev_free(s->bitmap);
     dev_free(s->ztab);
+    dev_free(s->pfilt);
+    dev_free(s->pkey);
     free_rows(s->rows);
     delete s;
 }
 
 SubView view_of(const qsd_subspace *s) {
-    return SubView{s->keys,  s->hkey, s->slots, s->bitmap, s->N, (uint32_t)(s->C - 1), s->exact ? 1u : 0u,
-                   s->rows.order, s->rows.keys, s->rows.hkey};
+    return SubView{s->keys,       s->hkey,      s->slots,     s->bitmap, s->N, (uint32_t)(s->C - 1),
+                   s->exact ? 1u : 0u, s->rows.order, s->rows.keys, s->rows.hkey, s->pfilt, s->pkey,
+                   s->rows.pkey};
 }
 
 }  // namespace
@@ -558,60 +587,180 @@ extern "C" int qsd_subspace_build(const uint64_t *d_bits, int64_t n_in, int32_t 
 namespace qsd {
 namespace {
 
+// Rebuilds, as needed, the table for C slots, the part filters for the split qubit (0 = none)
+// and the slot order of the rows; the subspace keeps its old state until all of them are built.
+// Operators bound to the subspace get their groups' part indices anew.  The hash words never
+// change here, so row and group hashes stay valid (`new_words` keeps the path that rebuilds
+// them for a table built under other words).
 template <int Wp>
-int rehash_impl(qsd_subspace *sub, int64_t C, hipStream_t st) {
-    uint64_t *slots = nullptr;
-    uint32_t *bitmap = nullptr;
-    QSD_TRY(dev_alloc(&slots, C));
-    int rc = dev_alloc(&bitmap, C / 32);
-    const bool exact = exact_tags_ok(sub->n_qubits, sub->W, sub->N, C);
-    if (rc == QSD_OK) {
-        k_fill_u64<<<1024, kBlock, 0, st>>>(slots, C, ~0ull);
-        k_fill_u32<<<256, kBlock, 0, st>>>(bitmap, C / 32, 0u);
-        SubView v{sub->keys, sub->hkey, slots, bitmap, sub->N, (uint32_t)(C - 1), exact ? 1u : 0u};
-        k_hash_insert<Wp><<<grid_for(sub->N, kBlock), kBlock, 0, st>>>(v, slots, bitmap, sub->hkey, sub->ztab);
-        if (hipStreamSynchronize(st) != hipSuccess)
-            rc = fail(QSD_ERR_HIP, "hash rebuild failed: %s", hipGetErrorString(hipGetLastError()));
+int rehash_impl(qsd_subspace *sub, int64_t C, int split, hipStream_t st) {
+    const bool new_words = false;
+    const bool new_table = new_words || C != sub->C;
+    std::vector<uint64_t> z = sub->z;
+    uint64_t *slots = sub->slots, *ztab = sub->ztab, *hkey = sub->hkey;
+    uint32_t *bitmap = sub->bitmap;
+    bool exact = sub->exact;
+    uint32_t *pfilt = nullptr, *pkey = nullptr, *ptab_d = nullptr;
+    std::vector<uint32_t> pz;
+    std::vector<uint64_t> tab;
+    int rc = QSD_OK;
+    if (new_words) {
+        ztab = nullptr;
+        hkey = nullptr;
+        hash_words(sub->n_qubits, z);
+        hash_byte_tables(Wp, z, tab);
+        rc = dev_alloc(&ztab, tab.size());
+        if (rc == QSD_OK) rc = dev_alloc(&hkey, sub->N);
+        if (rc == QSD_OK && hipMemcpyAsync(ztab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+            rc = fail(QSD_ERR_HIP, "copy failed");
     }
+    if (rc == QSD_OK && new_table) {
+        slots = nullptr;
+        bitmap = nullptr;
+        exact = exact_tags_ok(z, sub->W, sub->N, C);
+        rc = dev_alloc(&slots, C);
+        if (rc == QSD_OK) rc = dev_alloc(&bitmap, C / 32);
+        if (rc == QSD_OK) {
+            k_fill_u64<<<1024, kBlock, 0, st>>>(slots, C, ~0ull);
+            k_fill_u32<<<256, kBlock, 0, st>>>(bitmap, C / 32, 0u);
+            // writes the row hashes (the same values when the words did not change)
+            SubView v{sub->keys, hkey, slots, bitmap, sub->N, (uint32_t)(C - 1), exact ? 1u : 0u};
+            k_hash_insert<Wp><<<grid_for(sub->N, kBlock), kBlock, 0, st>>>(v, slots, bitmap, hkey, ztab);
+        }
+    }
+    if (rc == QSD_OK && split > 0) {
+        part_words(sub->n_qubits, split, pz);
+        std::vector<uint32_t> ptab((size_t)Wp * 8 * 256, 0u);
+        for (int c = 0; c < Wp * 8; ++c)
+            for (int v = 0; v < 256; ++v)
+                for (int b = 0; b < 8; ++b)
+                    if ((v >> b & 1) && 8 * c + b < sub->n_qubits) ptab[(size_t)c * 256 + v] ^= pz[8 * c + b];
+        rc = dev_alloc(&pfilt, kPartWords);
+        if (rc == QSD_OK) rc = dev_alloc(&pkey, sub->N);
+        if (rc == QSD_OK) rc = dev_alloc(&ptab_d, ptab.size());
+        if (rc == QSD_OK &&
+            hipMemcpyAsync(ptab_d, ptab.data(), ptab.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+            rc = fail(QSD_ERR_HIP, "copy failed");
+        if (rc == QSD_OK) {
+            k_fill_u32<<<16, kBlock, 0, st>>>(pfilt, kPartWords, 0u);
+            k_part_keys<Wp><<<grid_for(sub->N, kBlock), kBlock, 0, st>>>(sub->keys, sub->N, ptab_d, pkey, pfilt);
+        }
+        // the host tables must outlive their copies
+        if (rc == QSD_OK && hipStreamSynchronize(st) != hipSuccess)
+            rc = fail(QSD_ERR_HIP, "part filter build failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    if (rc == QSD_OK && hipStreamSynchronize(st) != hipSuccess)
+        rc = fail(QSD_ERR_HIP, "hash rebuild failed: %s", hipGetErrorString(hipGetLastError()));
     SlotRows rows;
-    if (rc == QSD_OK) rc = build_order(sub, C, exact, slots, bitmap, &rows, st);
+    if (rc == QSD_OK) rc = build_order(sub, hkey, pkey, C, exact, slots, bitmap, &rows, st);
+    // the bound operators' group hashes (new words) and part indices (part filters)
+    const size_t nb = sub->bound.size();
+    std::vector<uint64_t *> ghash(nb, nullptr);
+    std::vector<uint32_t *> gparts(nb, nullptr);
+    std::vector<std::vector<uint64_t>> gh(nb);
+    std::vector<std::vector<uint32_t>> gp(nb);
+    for (size_t k = 0; k < nb && rc == QSD_OK; ++k) {
+        const qsd_op *op = sub->bound[k]->op;
+        if (new_words) {
+            gh[k] = group_hashes(op, z);
+            rc = dev_alloc(&ghash[k], gh[k].size());
+            if (rc == QSD_OK && !gh[k].empty() &&
+                hipMemcpyAsync(ghash[k], gh[k].data(), gh[k].size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+                rc = fail(QSD_ERR_HIP, "copy failed");
+        }
+        if (rc == QSD_OK && split > 0) {
+            gp[k] = group_parts(op, pz);
+            rc = dev_alloc(&gparts[k], gp[k].size());
+            if (rc == QSD_OK && !gp[k].empty() &&
+                hipMemcpyAsync(gparts[k], gp[k].data(), gp[k].size() * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+                rc = fail(QSD_ERR_HIP, "copy failed");
+        }
+    }
+    if (rc == QSD_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(QSD_ERR_HIP, "operator update failed");
     if (rc != QSD_OK) {
-        dev_free(slots);
-        dev_free(bitmap);
+        for (auto *p : ghash) dev_free(p);
+        for (auto *p : gparts) dev_free(p);
+        free_rows(rows);
+        if (new_words) {
+            dev_free(ztab);
+            dev_free(hkey);
+        }
+        if (new_table) {
+            dev_free(slots);
+            dev_free(bitmap);
+        }
+        dev_free(pfilt);
+        dev_free(pkey);
+        dev_free(ptab_d);
         return rc;
     }
-    dev_free(sub->slots);
-    dev_free(sub->bitmap);
+    dev_free(ptab_d);
+    if (new_words) {
+        dev_free(sub->ztab);
+        dev_free(sub->hkey);
+    }
+    if (new_table) {
+        dev_free(sub->slots);
+        dev_free(sub->bitmap);
+    }
+    dev_free(sub->pfilt);
+    dev_free(sub->pkey);
     free_rows(sub->rows);
+    sub->z = z;
+    sub->ztab = ztab;
+    sub->hkey = hkey;
     sub->slots = slots;
     sub->bitmap = bitmap;
-    sub->rows = rows;
-    sub->C = C;
     sub->exact = exact;
+    sub->C = C;
+    sub->rows = rows;
+    sub->pfilt = pfilt;
+    sub->pkey = pkey;
+    sub->pz = pz;
+    sub->split = split;
+    for (size_t k = 0; k < nb; ++k) {
+        qsd_ham *h = sub->bound[k];
+        if (new_words) {
+            dev_free(h->g_hash);
+            h->g_hash = ghash[k];
+        }
+        dev_free(h->g_part);
+        h->g_part = gparts[k];
+    }
     return QSD_OK;
 }
 
 }  // namespace
 }  // namespace qsd
 
-extern "C" int qsd_subspace_rehash(qsd_subspace *s, double max_load, void *stream) {
+extern "C" int qsd_subspace_rehash(qsd_subspace *s, double max_load, int32_t split, void *stream) {
     clear_error();
     if (!s) return fail(QSD_ERR_INVALID_ARG, "subspace is NULL");
     if (max_load == 0.0) max_load = 0.125;
     if (!(max_load > 0.0 && max_load <= 0.5)) return fail(QSD_ERR_INVALID_ARG, "max_load must be in (0, 0.5]");
+    if (split < 0 || split >= s->n_qubits)
+        return fail(QSD_ERR_INVALID_ARG, "split qubit %d outside [0, %d)", split, s->n_qubits);
     int64_t C = 64;
     while ((double)s->N / (double)C > max_load) C <<= 1;
     if (C > (1ll << 32)) return fail(QSD_ERR_CAPACITY, "hash table would exceed 2^32 slots");
-    if (C == s->C) return QSD_OK;
+    if (C == s->C && split == s->split) return QSD_OK;
     hipStream_t st = (hipStream_t)stream;
     switch (s->Wp) {
-        case 1: return rehash_impl<1>(s, C, st);
-        case 2: return rehash_impl<2>(s, C, st);
-        case 4: return rehash_impl<4>(s, C, st);
-        case 8: return rehash_impl<8>(s, C, st);
-        case 16: return rehash_impl<16>(s, C, st);
+        case 1: return rehash_impl<1>(s, C, split, st);
+        case 2: return rehash_impl<2>(s, C, split, st);
+        case 4: return rehash_impl<4>(s, C, split, st);
+        case 8: return rehash_impl<8>(s, C, split, st);
+        case 16: return rehash_impl<16>(s, C, split, st);
     }
     return fail(QSD_ERR_UNSUPPORTED, "unsupported width");
+}
+
+extern "C" int qsd_subspace_hash_info(const qsd_subspace *s, int32_t *split, int32_t *exact) {
+    clear_error();
+    if (!s) return fail(QSD_ERR_INVALID_ARG, "subspace is NULL");
+    if (split) *split = s->split;
+    if (exact) *exact = s->exact ? 1 : 0;
+    return QSD_OK;
 }
 
 extern "C" int qsd_subspace_info(const qsd_subspace *s, int64_t *N, int32_t *n_qubits, int32_t *W, int64_t *capacity) {

@@ -97,13 +97,44 @@ def test_schedules_bitwise(case):
     assert r["max_load"] in (0.03125, 0.0625, 0.125, 0.25, 0.5) and H.subspace.capacity == r["capacity"]
     assert torch.equal(H.matvec(x), outs[0])  # a rebuilt table gives the same output
     keys_before = H.subspace.keys()
-    for load in (0.5, 0.03):
-        H.subspace.rehash(load)
-        for o in _run_all(H, x):  # the slot order is rebuilt with the table
+    nq = H.subspace.n_qubits
+    # other loads, and part filters (a split at the middle, near the bottom and near the top)
+    for load, split in ((0.5, 0), (0.03, 0), (0.25, nq // 2), (0.5, 3), (0.0625, nq - 1)):
+        H.subspace.rehash(load, split)
+        assert H.subspace.hash_info()[0] == split
+        for o in _run_all(H, x):  # the slot order and the group part indices follow the table
             assert torch.equal(o, outs[0])
         assert torch.equal(H.subspace.lookup(keys_before), torch.arange(H.N, device="cuda"))
+    r = H.autotune(nvec=x.shape[1], dtype=x.dtype, reps=1, split=True)
+    assert r["split"] == H.subspace.hash_info()[0] and torch.equal(H.matvec(x), outs[0])
+    with pytest.raises(qsd.QsdError, match="INVALID_ARG"):
+        H.subspace.rehash(0.25, nq)
     with pytest.raises(qsd.QsdError, match="INVALID_ARG"):
         H.schedule = 0x80
+
+
+def test_part_filters_groups_by_mask_exact():
+    """The fermionic product subspace with groups ordered by flip mask and part filters split at
+    the first beta qubit (exact filters), at a mid-alpha qubit, and none, under every schedule:
+    equal to the oracle bit for bit (dyadic data)."""
+    from oracle import rowwise as orw
+    from oracle import subspace as osub
+
+    from _util import dyadic, dyadic_vector
+
+    ops, keys = c3_parts(90, 90)
+    tl = dyadic(ops)
+    sub = qsd.Subspace(keys, tl.n_qubits)
+    H = qsd.SubspaceHamiltonian(sub, qsd.operator_from_termlist(tl, order_by_mask=True))
+    rng = np.random.default_rng(31)
+    x = torch.from_numpy(dyadic_vector(rng, H.N, nvec=2)).cuda()
+    y_o = orw.matvec_c(osub.canonical_keys(keys), tl, x.cpu().numpy()).real
+    for load, split in ((0.125, 16), (0.5, 16), (0.03125, 16), (0.25, 5), (0.25, 0)):
+        sub.rehash(load, split)
+        assert sub.hash_info()[0] == split
+        say("split", split, "capacity", sub.capacity)
+        for o in _run_all(H, x):
+            np.testing.assert_array_equal(o.cpu().numpy(), y_o)
 
 
 @pytest.mark.parametrize("case", ["xxz", "heavyhex", "complex"])
