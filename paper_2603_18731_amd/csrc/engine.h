@@ -45,16 +45,6 @@ constexpr int kLockBatch = 4;   // groups in flight per wave in lockstep mode
 constexpr int kOccBatch = 8;    // occupancy-bit loads in flight per lane (filter-first mode)
 constexpr int kSlotBatch = 4;   // slot loads in flight per lane (filter-first mode)
 
-// Terms of a chunk staged in LDS (the chunk's groups own one contiguous run of terms): the
-// first TermCacheSize<Wp> of them are read from LDS by every hit of the chunk, the rest (chunks
-// of groups with long term lists) from global memory.  With the 16 KB part filter (one- and
-// two-word keys) the workgroup stays under 32 KB of LDS, so five workgroups (the register
-// limit of the one-vector kernels) fit a CU; wider keys read every term from global memory.
-template <int Wp>
-struct TermCacheSize {
-    static constexpr int value = Wp == 1 ? 224 : Wp == 2 ? 100 : Wp == 4 ? 96 : 0;
-};
-
 // One- and two-word keys copy the part filters into LDS; wider keys read them from memory.
 template <int Wp>
 struct PartLds {
@@ -179,18 +169,12 @@ struct ChunkLds {
     uint16_t iptr[kChunk][kIptr];
     uint64_t planes[kBlock / 64][64 * Wp];
     uint8_t clist[kBlock / 64][kChunk];  // lockstep filter-first: the wave's k-th live group
-    // staged terms: care/want/sign words and the coefficient (double2, or float2 in the low
-    // half) of terms tc_base .. tc_base + tc_count - 1
-    uint64_t tc_cws[TermCacheSize<Wp>::value > 0 ? TermCacheSize<Wp>::value : 1][3 * Wp];
-    uint64_t tc_coef[TermCacheSize<Wp>::value > 0 ? TermCacheSize<Wp>::value : 1][2];
-    uint32_t tc_base, tc_count;
     uint32_t gpart[kChunk];              // the chunk's groups' packed part indices
     uint32_t pf[PartLds<Wp>::words];     // part filters (one- and two-word keys)
 };
 
 // Sum of the terms [t0, t0 + len) that match the row's projector bits, with popcount-parity
-// signs.  Returns false when no term matches (no stored entry).  Terms staged in the chunk's
-// LDS cache are read from there.
+// signs.  Returns false when no term matches (no stored entry).
 template <int Wp, class ET>
 __device__ __forceinline__ bool range_value(const HamView &h, const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp],
                                             uint32_t t0, uint32_t len, ET &vre, ET &vim) {
@@ -200,12 +184,10 @@ __device__ __forceinline__ bool range_value(const HamView &h, const ChunkLds<Wp>
     vre = 0;
     vim = 0;
     for (uint32_t t = t0; t < t0 + len; ++t) {
-        const uint32_t ct = t - lds.tc_base;
-        const bool cached = ct < lds.tc_count;
-        const uint64_t *cws = cached ? lds.tc_cws[ct] : h.t_cws + (int64_t)t * 3 * Wp;
+        const uint64_t *cws = h.t_cws + (int64_t)t * 3 * Wp;
         if (!term_pass<Wp>(key, cws)) continue;
         any = true;
-        const CT c = cached ? *(const CT *)lds.tc_coef[ct] : coef[t];
+        const CT c = coef[t];
         if (term_parity<Wp>(key, cws)) {
             vre -= c.x;
             vim -= c.y;
@@ -427,7 +409,7 @@ __device__ __forceinline__ void resolve_groups(const SubView &s, const ChunkLds<
 // h(b_i) ^ h(M_g), land in one stretch as well, and the wave's occupancy-bit loads for the group
 // touch one or two cache lines instead of one line per lane.  Each lane still meets its hits in
 // increasing group order, so both modes give bitwise the same sums.
-template <int Wp, bool LOWER = false, class OnHit>
+template <int Wp, bool LOWER = false, bool PF = true, class OnHit>
 __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, const uint64_t (&key)[Wp],
                                            uint64_t hrow, uint32_t prow, bool valid, ChunkLds<Wp> &lds,
                                            OnHit &&on_hit, unsigned long long *probes = nullptr,
@@ -439,14 +421,27 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
     const uint64_t vrows = __ballot(valid);
     // part filters: one- and two-word keys read an LDS copy (visible after the first chunk's
     // barrier, before any probe)
+    // PF = false compiles the engine without part filters (the launch checks that the subspace
+    // has none); PF = true tests them when the subspace has them
     const uint32_t *pf = nullptr;
-    if (s.pfilt) {
+    if (PF && s.pfilt) {
         if (PartLds<Wp>::words == kPartWords) {
             for (int k = threadIdx.x; k < kPartWords; k += kBlock) lds.pf[k] = s.pfilt[k];
             pf = lds.pf;
         } else {
             pf = s.pfilt;
         }
+    }
+    // When every row of the wave has the same high (or low) part, as consecutive rows of an
+    // alpha x beta product do, that part's filter test depends on the group only: the scan
+    // applies it to the whole wave's live word before any lane probes.
+    uint32_t uni_mask = 0u, uni_part = 0u;
+    if (pf) {
+        const int first = (int)__builtin_ctzll(vrows | (1ull << 63));
+        const uint32_t p0 = (uint32_t)__shfl((int)prow, first, 64);
+        if (__all(!valid || ((prow ^ p0) >> 16) == 0u)) uni_mask |= 0xFFFF0000u;
+        if (__all(!valid || ((prow ^ p0) & 0xFFFFu) == 0u)) uni_mask |= 0x0000FFFFu;
+        uni_part = p0;
     }
     for (int64_t g0 = 0; g0 < h.G; g0 += kChunk) {
         const int nc = (int)((h.G - g0) < kChunk ? (h.G - g0) : kChunk);
@@ -465,21 +460,6 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
             for (int q = 0; q < kIptr; ++q) lds.iptr[c][q] = h.g_iptr[g * kIptr + q];
             lds.gpart[c] = pf ? h.g_part[g] : 0u;
         }
-        {
-            constexpr int kTC = TermCacheSize<Wp>::value;
-            const uint32_t tb = h.g_term0[g0];
-            const uint32_t te = h.g_term0[g0 + nc - 1] + h.g_nterm[g0 + nc - 1];
-            const uint32_t tn = kTC > 0 ? min(te - tb, (uint32_t)kTC) : 0u;
-            for (uint32_t k = threadIdx.x; k < tn * 3u * Wp; k += kBlock)
-                lds.tc_cws[0][k] = h.t_cws[(int64_t)tb * 3 * Wp + k];
-            const uint32_t cw = h.coef_f32 ? 1u : 2u;  // 64-bit words per coefficient
-            const uint64_t *__restrict__ cs = (const uint64_t *)h.t_coef + (int64_t)tb * cw;
-            for (uint32_t k = threadIdx.x; k < tn * cw; k += kBlock) lds.tc_coef[k / cw][k % cw] = cs[k];
-            if (threadIdx.x == 0) {
-                lds.tc_base = tb;
-                lds.tc_count = tn;
-            }
-        }
         // scan: lane l evaluates group g0 + l for the wave's 64 rows, then the masks are
         // transposed to one live-group mask per row
         uint64_t live = 0;
@@ -490,6 +470,14 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
             for (int j = 0; j < 4; ++j) P[j] = planes[((uint32_t)(rec >> (16 + 12 * j)) & 0xFFFu) + (uint32_t)j];
             live = sliced_table((uint32_t)rec & 0xFFFFu, P[0], P[1], P[2], P[3]) & vrows;
             if (LOWER) live &= planes[group_msob<Wp>(h.g_mask + (g0 + lane) * Wp)];
+            if (uni_mask) {
+                // the part shared by the whole wave, through this group's flips
+                const uint32_t q = uni_part ^ h.g_part[g0 + lane];
+                const uint32_t lo = q & 0xFFFFu, hi = q >> 16;
+                const bool lo_ok = !(uni_mask & 0xFFFFu) || ((pf[lo >> 5] >> (lo & 31u)) & 1u);
+                const bool hi_ok = !(uni_mask >> 16) || ((pf[kPartWords / 2 + (hi >> 5)] >> (hi & 31u)) & 1u);
+                if (!(lo_ok && hi_ok)) live = 0ull;
+            }
         }
         uint64_t todo = __ballot(live != 0ull);  // groups live for some row of the wave
         live = wave_transpose64(live, lane);

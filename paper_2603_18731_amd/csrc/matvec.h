@@ -94,7 +94,7 @@ __device__ __forceinline__ void diag_rows_block(const ET *__restrict__ dre, cons
 // its first off-diagonal element and writes y only if it has one (diag_rows_block writes the
 // others), so rows without elements cost no random access to x, d or y.  Either way the sum is
 // formed with the same operations in the same order.
-template <int Wp, int NV, class ET, bool CPLX>
+template <int Wp, int NV, class ET, bool CPLX, bool PF = true>
 __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h, const ET *__restrict__ dre,
                                              const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
                                              ET *__restrict__ y, int64_t ldy, int nvec, int64_t row0,
@@ -155,7 +155,7 @@ __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h,
             }
         }
     };
-    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink(use, fetch), nullptr, lockstep, filter_first);
+    row_engine<Wp, false, PF>(s, h, key, hrow, prow, valid, lds, sink(use, fetch), nullptr, lockstep, filter_first);
     if (!valid || !have) return;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {

@@ -23,7 +23,7 @@ inline unsigned grid_for(int64_t n, int per_block) { return (unsigned)((n + per_
 // the rest take the slot-order tiles and write only the rows with elements; no row is written
 // twice, and each row's value is formed with the same operations as in every other schedule.
 // (Single-vector kernels for up to four key words are held to five waves per SIMD.)
-template <int Wp, int NV, class ET, bool CPLX>
+template <int Wp, int NV, class ET, bool CPLX, bool PF>
 __global__ __launch_bounds__(kBlock, Wp <= 4 && NV == 1 ? 5 : 1) void k_matvec(
     SubView s, HamView h, const ET *__restrict__ dre,
                                                    const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
@@ -35,8 +35,9 @@ __global__ __launch_bounds__(kBlock, Wp <= 4 && NV == 1 ? 5 : 1) void k_matvec(
         return;
     }
     const int64_t row0 = tile_index(blockIdx.x - nd, gridDim.x - nd, (sched & QSD_SCHED_XCD_REMAP) != 0) * kBlock;
-    matvec_block<Wp, NV, ET, CPLX>(s, h, dre, dim, x, ldx, y, ldy, nvec, row0, lds, (sched & QSD_SCHED_SLOT_ORDER) != 0,
-                                   (sched & QSD_SCHED_LOCKSTEP) != 0, (sched & QSD_SCHED_FILTER_FIRST) != 0, nd > 0);
+    matvec_block<Wp, NV, ET, CPLX, PF>(s, h, dre, dim, x, ldx, y, ldy, nvec, row0, lds,
+                                       (sched & QSD_SCHED_SLOT_ORDER) != 0, (sched & QSD_SCHED_LOCKSTEP) != 0,
+                                       (sched & QSD_SCHED_FILTER_FIRST) != 0, nd > 0);
 }
 
 template <int Wp, int NV, class ET, bool CPLX>
@@ -47,8 +48,16 @@ void launch_mv(const qsd_ham *h, const void *x, int64_t ldx, void *y, int64_t ld
     const unsigned tiles = grid_for(h->N, kBlock);
     const bool split = (h->schedule & QSD_SCHED_SLOT_ORDER) && h->rowbits;
     const unsigned nd = split ? (tiles + 7u) & ~7u : 0u;
-    k_matvec<Wp, NV, ET, CPLX><<<nd + tiles, kBlock, 0, st>>>(sub_view(h->s), ham_view(h, f32), dre, dim, (const ET *)x, ldx,
-                                                             (ET *)y, ldy, nvec, h->schedule, h->rowbits, nd);
+    // the part-filter variant only for subspaces that have filters (the other one carries no
+    // filter code, so it keeps its registers)
+    if (h->s->pfilt)
+        k_matvec<Wp, NV, ET, CPLX, true><<<nd + tiles, kBlock, 0, st>>>(sub_view(h->s), ham_view(h, f32), dre, dim,
+                                                                       (const ET *)x, ldx, (ET *)y, ldy, nvec,
+                                                                       h->schedule, h->rowbits, nd);
+    else
+        k_matvec<Wp, NV, ET, CPLX, false><<<nd + tiles, kBlock, 0, st>>>(sub_view(h->s), ham_view(h, f32), dre, dim,
+                                                                        (const ET *)x, ldx, (ET *)y, ldy, nvec,
+                                                                        h->schedule, h->rowbits, nd);
 }
 
 template <int Wp, class ET, bool CPLX>
