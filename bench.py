@@ -98,6 +98,27 @@ def cpu_model():
     return platform.processor() or platform.machine()
 
 
+def gather_ceiling():
+    """Random-gather rate of the device for buffers of 256 KiB .. 1 GiB (the bench-only
+    microbenchmark library, not part of the C-ABI)."""
+    import ctypes
+
+    import torch
+
+    path = os.path.join(ROOT, "paper_2603_18731_amd", "libqsd_bench.so")
+    lib = ctypes.CDLL(path)
+    lib.qsdbench_gather_rate.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    lib.qsdbench_gather_rate.restype = ctypes.c_int
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for kib in (256, 1024, 2048, 4096, 8192, 32768, 131072, 524288, 1048576):
+        for ilp in (1, 2, 4, 8):
+            r = ctypes.c_double()
+            rc = lib.qsdbench_gather_rate(kib << 10, ilp, ctypes.byref(r), stream)
+            if rc != 0:
+                raise SystemExit("gather benchmark failed (%d)" % rc)
+            print(json.dumps({"buffer_kib": kib, "ilp": ilp, "loads_per_s": r.value}), flush=True)
+
+
 def make_workload(name):
     import workloads as wl
 
@@ -493,12 +514,7 @@ def main():
         calibrate_copy()
         return
     if args.gather_ceiling:
-        import paper_2603_18731_amd as qsd
-
-        for kib in (256, 1024, 2048, 4096, 8192, 32768, 131072, 524288, 1048576):
-            for ilp in (1, 2, 4, 8):
-                r = qsd.device_gather_rate(kib << 10, ilp)
-                print(json.dumps({"buffer_kib": kib, "ilp": ilp, "loads_per_s": r}), flush=True)
+        gather_ceiling()
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library does not shard the subspace SpMV across "

@@ -34,6 +34,7 @@
 #ifndef QSD_H
 #define QSD_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -82,6 +83,29 @@ typedef struct qsd_subspace qsd_subspace;
 typedef struct qsd_op qsd_op;
 typedef struct qsd_ham qsd_ham;
 
+/* ------------------------------------------------------------------ device memory
+ * Every creating call (and every call that needs scratch) takes its device memory from a
+ * caller-supplied allocator, so that a framework's caching allocator (PyTorch's, in the Python
+ * binding) sees and accounts for every byte; NULL (or NULL function pointers) selects
+ * hipMalloc / hipFree.
+ *   alloc(ctx, bytes, stream)  returns `bytes` of device memory on the current device, usable
+ *                              by work enqueued on `stream` (the stream of the library call),
+ *                              or NULL when it cannot (the call then fails with
+ *                              QSD_ERR_OUT_OF_MEMORY after releasing what it took).
+ *   free(ctx, ptr, stream)     returns ptr; the library calls it once all of its work that
+ *                              uses ptr has been enqueued on `stream` (stream-ordered release:
+ *                              the allocator may hand the block to later work on that stream).
+ * A handle keeps a copy of its allocator (ctx must outlive the handle) and releases its memory
+ * through it when destroyed, on the stream it was created on; the caller must not destroy a
+ * handle while work using it is pending on another stream.  Scratch of a call on a handle comes
+ * from the handle's allocator unless the call takes an allocator of its own.  The library never
+ * calls the allocator from another thread than the caller's. */
+typedef struct {
+    void *ctx;
+    void *(*alloc)(void *ctx, size_t bytes, void *stream);
+    void (*free)(void *ctx, void *ptr, void *stream);
+} qsd_allocator;
+
 /* Message of the last failing call on this thread ("" if none).  Valid until the next call. */
 const char *qsd_last_error(void);
 
@@ -101,13 +125,14 @@ int qsd_version(void);
  *   flags     QSD_SUB_* bits.
  *   max_load  hash load factor in (0, 0.5]; 0 selects 0.125 (a low load lets most absent strings
  *             stop at an empty occupancy bit).
+ *   alloc     device memory of the handle and of the build's scratch (NULL: hipMalloc).
  *   out       receives the new handle.
  *   Synchronizes `stream` (the unique count N is read back).  Errors: INVALID_ARG if n_in < 1,
  *   n_qubits < 1, a bit >= n_qubits is set, or max_load is out of range; CAPACITY if
  *   N >= 2^32 - 1; UNSUPPORTED if W exceeds the widest compiled key (see qsd_max_qubits).
  */
 int qsd_subspace_build(const uint64_t *d_bits, int64_t n_in, int32_t n_qubits, uint32_t flags, double max_load,
-                       void *stream, qsd_subspace **out);
+                       const qsd_allocator *alloc, void *stream, qsd_subspace **out);
 
 /* Largest n_qubits the library supports. */
 int32_t qsd_max_qubits(void);
@@ -212,9 +237,11 @@ int qsd_op_destroy(qsd_op *op);
  *   an operator with the same n_qubits, uploads the group and term tables and computes the
  *   diagonal d_i = H_ii once (projector letters tested before any sign is formed).  The
  *   handle references `s` and `op`; they must outlive it.  flags: reserved, pass 0.
+ *   alloc: device memory of the handle and the scratch of later calls on it (NULL: hipMalloc).
  *   Enqueued on `stream`.
  */
-int qsd_ham_create(const qsd_subspace *s, const qsd_op *op, uint32_t flags, void *stream, qsd_ham **out);
+int qsd_ham_create(const qsd_subspace *s, const qsd_op *op, uint32_t flags, const qsd_allocator *alloc, void *stream,
+                   qsd_ham **out);
 
 /* Copies the cached diagonal (FP64 real part; imaginary parts of a Hermitian H are zero) to
  * device d_out[N]. */
@@ -350,6 +377,7 @@ typedef struct {
     int32_t check_every; /* iterations between convergence checks (default 5) */
     int32_t want_vector; /* write the normalized Ritz vector to d_evec */
     int32_t use_graph;   /* capture one iteration in a HIP graph and replay it */
+    const qsd_allocator *alloc; /* basis and work vectors (NULL: the operator's allocator) */
 } qsd_lanczos_opts;
 
 typedef struct {
@@ -379,9 +407,11 @@ void qsd_lanczos_default_opts(qsd_lanczos_opts *opts);
 int qsd_lanczos(const qsd_ham *h, const qsd_lanczos_opts *opts, double *eval_out, void *d_evec,
                 qsd_lanczos_info *info, void *stream);
 
-/* Block Lanczos (not in the paper): `block` (4 or 8) vectors per step, so every hash probe of
- * the SpMM serves `block` vectors.  Block classical Gram-Schmidt applied twice against the
- * whole basis, Cholesky QR applied twice for the next block, FP64 basis and recurrence;
+/* Block Lanczos (not in the paper): `block` (4, 8 or 16) vectors per step, so every hash probe
+ * of the SpMM serves `block` vectors.  max_iter counts block steps: at most 80 for blocks of 4
+ * and 8, 40 for blocks of 16 (the Ritz solve keeps T's band in one workgroup's LDS).  Block
+ * classical Gram-Schmidt applied twice against the whole basis, Cholesky QR applied twice for
+ * the next block, FP64 basis and recurrence;
  * spmv_dtype F32 stores SpMM elements and vectors in single precision with FP64 accumulation.
  * The lowest eigenvalue of the block tridiagonal T is found on the device by bisection with a
  * banded Cholesky positive-definiteness test, its eigenvector by inverse iteration; the
@@ -411,8 +441,9 @@ int qsd_block_lanczos(const qsd_ham *h, int32_t block, const qsd_lanczos_opts *o
  *   is taken as the conjugate of the lower one).
  *   index_type QSD_INDEX_I32 / I64 (CAPACITY if N >= 2^31 with I32); dtype as for
  *   qsd_csr_build (F64 / F32 real, C128 / C64 complex; DTYPE if it does not match `h`).
- *   Synchronizes.  Device memory: (N + 1) * 8 + nnz * (index + value size), plus the build's
- *   scratch of nnz * (8 + 2 * value size) bytes while it runs.  `h` may be destroyed after.
+ *   Synchronizes.  Device memory (from `alloc`, NULL: hipMalloc): (N + 1) * 8 + nnz * (index +
+ *   value size), plus the build's scratch of nnz * (8 + 2 * value size) bytes while it runs.
+ *   `h` may be destroyed after.
  * qsd_csr_info      N, nnz, device bytes held.
  * qsd_csr_export    copies indptr [N+1] (int64), indices [nnz], data [nnz] to device buffers
  *                   (any may be NULL); async on `stream`.
@@ -426,7 +457,8 @@ int qsd_block_lanczos(const qsd_ham *h, int32_t block, const qsd_lanczos_opts *o
  */
 #define QSD_CSR_LOWER_MIRROR 1u
 typedef struct qsd_csr qsd_csr;
-int qsd_csr_create(const qsd_ham *h, int32_t index_type, int32_t dtype, uint32_t flags, void *stream, qsd_csr **out);
+int qsd_csr_create(const qsd_ham *h, int32_t index_type, int32_t dtype, uint32_t flags, const qsd_allocator *alloc,
+                   void *stream, qsd_csr **out);
 int qsd_csr_info(const qsd_csr *c, int64_t *N, int64_t *nnz, int64_t *bytes);
 int qsd_csr_export(const qsd_csr *c, int64_t *d_indptr, void *d_indices, void *d_data, void *stream);
 int qsd_csr_matvec(const qsd_csr *c, int32_t nvec, const void *d_x, int64_t ldx, void *d_y, int64_t ldy, int32_t dtype,
@@ -476,7 +508,9 @@ int qsd_ramps(const qsd_ham *h, const int64_t *s0, int64_t n0, double E, double 
  * mix.  Not in the paper (it hands its operator to external eigensolvers).
  *
  * qsd_batch_create     up to max_requests slots, at most max_iter iterations per request,
- *                      SpMV in spmv_dtype (QSD_F64, or QSD_F32 with FP64 accumulation).
+ *                      SpMV in spmv_dtype (QSD_F64, or QSD_F32 with FP64 accumulation); the
+ *                      batch's own tables and library-allocated workspaces come from `alloc`
+ *                      (NULL: hipMalloc).
  * qsd_batch_footprint  device bytes of one request's workspace for `h` (Krylov basis, work
  *                      vectors, partial sums, tridiagonal state).
  * qsd_batch_add        binds a real operator `h` (it must outlive the request) and starts
@@ -485,7 +519,7 @@ int qsd_ramps(const qsd_ham *h, const int64_t *s0, int64_t n0, double E, double 
  *                      device memory of at least qsd_batch_footprint bytes, 256-byte aligned,
  *                      owned by the caller and kept valid until the slot is removed and the
  *                      work enqueued before has finished; NULL makes the library allocate it
- *                      (hipMalloc) and free it at removal.  All requests of a batch must have
+ *                      (the batch's allocator) and free it at removal.  All requests of a batch must have
  *                      the same key width.  Errors: CAPACITY (no free slot), OUT_OF_MEMORY,
  *                      UNSUPPORTED (complex operator or other key width), INVALID_ARG (empty
  *                      subspace, short or misaligned workspace).  Synchronizes `stream`.
@@ -500,11 +534,12 @@ int qsd_ramps(const qsd_ham *h, const int64_t *s0, int64_t n0, double E, double 
  *                      slot (host arrays of max_requests entries, any may be NULL): status
  *                      0 free, 1 running, 2 converged, 3 iteration limit; energy (theta);
  *                      iterations taken; Ritz residual estimate.  Synchronizes.
- * qsd_batch_remove     frees a slot; a library-allocated workspace is released with hipFree
- *                      (which waits for the device).
+ * qsd_batch_remove     frees a slot; a library-allocated workspace is released after the
+ *                      device has finished the work enqueued on it.
  */
 typedef struct qsd_batch qsd_batch;
-int qsd_batch_create(int32_t max_requests, int32_t max_iter, int32_t spmv_dtype, qsd_batch **out);
+int qsd_batch_create(int32_t max_requests, int32_t max_iter, int32_t spmv_dtype, const qsd_allocator *alloc,
+                     qsd_batch **out);
 int qsd_batch_footprint(const qsd_ham *h, int32_t max_iter, int32_t spmv_dtype, int64_t *bytes);
 int qsd_batch_add(qsd_batch *b, const qsd_ham *h, int32_t v0_mode, uint64_t seed, double tol, void *workspace,
                   int64_t workspace_bytes, int32_t *slot_out, void *stream);
@@ -518,12 +553,6 @@ int qsd_batch_remove(qsd_batch *b, int32_t slot);
 int qsd_batch_destroy(qsd_batch *b);
 
 /* ====================================================================== diagnostics */
-
-/* Random-gather rate of the current device: `ilp` (1, 2, 4, 8) independent random 4-byte loads
- * in flight per lane from a buffer of `bytes` (a power of two, 1 KiB .. 16 GiB, allocated and
- * freed by the call).  The rate bounds hash probing (one random load per occupancy test).
- * Host output, synchronizes. */
-int qsd_device_gather_rate(int64_t bytes, int32_t ilp, double *loads_per_s, void *stream);
 
 #ifdef __cplusplus
 }

@@ -39,7 +39,7 @@ EXPORTED = [
     "qsd_subspace_keys", "qsd_subspace_lookup", "qsd_subspace_probe_stats", "qsd_subspace_destroy",
     "qsd_op_compile", "qsd_op_info", "qsd_op_export", "qsd_op_destroy", "qsd_ham_create", "qsd_ham_diagonal",
     "qsd_ham_destroy", "qsd_ham_info", "qsd_ham_work_counts", "qsd_matvec", "qsd_csr_build", "qsd_lanczos_default_opts", "qsd_lanczos",
-    "qsd_device_gather_rate", "qsd_batch_create", "qsd_batch_footprint", "qsd_batch_add", "qsd_batch_step",
+    "qsd_batch_create", "qsd_batch_footprint", "qsd_batch_add", "qsd_batch_step",
     "qsd_batch_poll", "qsd_batch_remove", "qsd_batch_destroy", "qsd_matvec_batched", "qsd_block_lanczos",
     "qsd_ham_set_schedule", "qsd_ham_get_schedule", "qsd_ham_autotune", "qsd_subspace_rehash",
     "qsd_csr_create", "qsd_csr_info", "qsd_csr_export", "qsd_csr_matvec", "qsd_csr_lanczos", "qsd_csr_block_lanczos",
@@ -73,7 +73,58 @@ class RampsInfo(ctypes.Structure):
 class LanczosOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("v0_mode", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("spmv_dtype", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("want_vector", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("want_vector", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("alloc", ctypes.c_void_p)]
+
+
+# ----------------------------------------------------------------------- device memory
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    """``qsd_allocator``: device memory for the library's handles and scratch."""
+
+    _fields_ = [("ctx", ctypes.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN)]
+
+
+def _torch_alloc(ctx, nbytes, stream):
+    import torch
+
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:  # out of memory: the library sees NULL and fails with OUT_OF_MEMORY
+        return None
+
+
+def _torch_free(ctx, ptr, stream):
+    try:
+        import torch
+
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:  # interpreter shutdown: torch already torn down; the process frees it all
+        pass
+
+
+# PyTorch's caching allocator (the default): every byte the library holds is visible to
+# torch.cuda.memory_allocated() and reusable by PyTorch after release.
+TORCH_ALLOCATOR = Allocator(None, ALLOC_FN(_torch_alloc), FREE_FN(_torch_free))
+_default_allocator = TORCH_ALLOCATOR
+
+
+def set_default_allocator(a):
+    """Allocator for handles created from now on: ``TORCH_ALLOCATOR`` (default), ``None``
+    (hipMalloc / hipFree inside the library) or any ``Allocator`` (kept alive by the caller)."""
+    global _default_allocator
+    _default_allocator = a
+
+
+def _resolve_allocator(a="default"):
+    return _default_allocator if a == "default" else a
+
+
+def _alloc_arg(a):
+    return ctypes.c_void_p(0) if a is None else ctypes.cast(ctypes.pointer(a), ctypes.c_void_p)
 
 
 class LanczosInfo(ctypes.Structure):
@@ -107,7 +158,7 @@ def lib():
         "qsd_last_error": ([], ctypes.c_char_p),
         "qsd_version": ([], ctypes.c_int),
         "qsd_max_qubits": ([], I32),
-        "qsd_subspace_build": ([P, I64, I32, U32, D, P, PP], ctypes.c_int),
+        "qsd_subspace_build": ([P, I64, I32, U32, D, P, P, PP], ctypes.c_int),
         "qsd_subspace_info": ([P, P, P, P, P], ctypes.c_int),
         "qsd_subspace_keys": ([P, P, P], ctypes.c_int),
         "qsd_subspace_lookup": ([P, P, I64, P, P], ctypes.c_int),
@@ -117,7 +168,7 @@ def lib():
         "qsd_op_info": ([P, P, P, P, P, P], ctypes.c_int),
         "qsd_op_export": ([P, P, P, P, P, P, P], ctypes.c_int),
         "qsd_op_destroy": ([P], ctypes.c_int),
-        "qsd_ham_create": ([P, P, U32, P, PP], ctypes.c_int),
+        "qsd_ham_create": ([P, P, U32, P, P, PP], ctypes.c_int),
         "qsd_ham_diagonal": ([P, P, P], ctypes.c_int),
         "qsd_ham_destroy": ([P], ctypes.c_int),
         "qsd_ham_info": ([P, P, P, P], ctypes.c_int),
@@ -126,8 +177,7 @@ def lib():
         "qsd_csr_build": ([P, P, P, P, I32, I32, P, P], ctypes.c_int),
         "qsd_lanczos_default_opts": ([ctypes.POINTER(LanczosOpts)], None),
         "qsd_lanczos": ([P, ctypes.POINTER(LanczosOpts), P, P, ctypes.POINTER(LanczosInfo), P], ctypes.c_int),
-        "qsd_device_gather_rate": ([I64, I32, P, P], ctypes.c_int),
-        "qsd_batch_create": ([I32, I32, I32, PP], ctypes.c_int),
+        "qsd_batch_create": ([I32, I32, I32, P, PP], ctypes.c_int),
         "qsd_batch_footprint": ([P, I32, I32, P], ctypes.c_int),
         "qsd_batch_add": ([P, P, I32, ctypes.c_uint64, D, P, I64, P, P], ctypes.c_int),
         "qsd_matvec_batched": ([I32, P, P, P, P, I32, P], ctypes.c_int),
@@ -136,7 +186,7 @@ def lib():
         "qsd_ham_autotune": ([P, I32, I32, I32, U32, P, P], ctypes.c_int),
         "qsd_subspace_rehash": ([P, D, I32, P], ctypes.c_int),
         "qsd_subspace_hash_info": ([P, P, P], ctypes.c_int),
-        "qsd_csr_create": ([P, I32, I32, U32, P, PP], ctypes.c_int),
+        "qsd_csr_create": ([P, I32, I32, U32, P, P, PP], ctypes.c_int),
         "qsd_csr_info": ([P, P, P, P], ctypes.c_int),
         "qsd_csr_export": ([P, P, P, P, P], ctypes.c_int),
         "qsd_csr_matvec": ([P, I32, P, I64, P, I64, I32, P], ctypes.c_int),
@@ -200,19 +250,13 @@ def _device_tensor(a, dtype=None):
     return t.cuda().contiguous()
 
 
-def device_gather_rate(nbytes: int, ilp: int = 4, stream=None) -> float:
-    """Random 4-byte loads per second from a buffer of ``nbytes`` (power of two)."""
-    r = ctypes.c_double()
-    _check(lib().qsd_device_gather_rate(int(nbytes), int(ilp), ctypes.byref(r), _stream(stream)))
-    return r.value
-
-
 # ----------------------------------------------------------------------------- classes
 
 class Subspace:
     """Canonical bit-string subspace on the device (Methods, Subspace data structure)."""
 
-    def __init__(self, bits, n_qubits: int, max_load: float = 0.0, assume_sorted_unique: bool = False, stream=None):
+    def __init__(self, bits, n_qubits: int, max_load: float = 0.0, assume_sorted_unique: bool = False, stream=None,
+                 allocator="default"):
         import torch
 
         b = _device_tensor(bits)
@@ -222,9 +266,10 @@ class Subspace:
         b = b.reshape(-1, W) if b.numel() else b.reshape(0, W)
         self.n_qubits = int(n_qubits)
         h = ctypes.c_void_p()
+        self._allocator = _resolve_allocator(allocator)  # its callbacks outlive the handle
         _check(lib().qsd_subspace_build(_ptr(b), b.shape[0], self.n_qubits,
                                         SUB_ASSUME_SORTED_UNIQUE if assume_sorted_unique else 0, max_load,
-                                        _stream(stream), ctypes.byref(h)))
+                                        _alloc_arg(self._allocator), _stream(stream), ctypes.byref(h)))
         self._h = h
         N, nq, Wo, C = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
         _check(lib().qsd_subspace_info(h, ctypes.byref(N), ctypes.byref(nq), ctypes.byref(Wo), ctypes.byref(C)))
@@ -254,9 +299,10 @@ class Subspace:
         return out
 
     @classmethod
-    def _wrap(cls, handle, n_qubits: int):
+    def _wrap(cls, handle, n_qubits: int, allocator=None):
         self = cls.__new__(cls)
         self._h = handle
+        self._allocator = allocator
         self.n_qubits = int(n_qubits)
         N, nq, Wo, C = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
         _check(lib().qsd_subspace_info(handle, ctypes.byref(N), ctypes.byref(nq), ctypes.byref(Wo), ctypes.byref(C)))
@@ -267,7 +313,7 @@ class Subspace:
         """The strings whose byte in ``mask`` (device uint8 [N]) is nonzero, as a new subspace."""
         h = ctypes.c_void_p()
         _check(lib().qsd_subspace_select(self._h, _ptr(mask), max_load, _stream(stream), ctypes.byref(h)))
-        return Subspace._wrap(h, self.n_qubits)
+        return Subspace._wrap(h, self.n_qubits, self._allocator)  # the library gives it this allocator
 
     def _refresh(self):
         N, nq, Wo, C = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
@@ -367,10 +413,12 @@ def operator_from_termlist(tl, **kw):
 class SubspaceHamiltonian:
     """Operator restricted to a subspace (Methods, Matrix evaluation)."""
 
-    def __init__(self, subspace: Subspace, op: _Operator, stream=None):
+    def __init__(self, subspace: Subspace, op: _Operator, stream=None, allocator="default"):
         self.subspace, self.op = subspace, op  # kept alive: the handle references both
         h = ctypes.c_void_p()
-        _check(lib().qsd_ham_create(subspace.handle, op.handle, 0, _stream(stream), ctypes.byref(h)))
+        self._allocator = _resolve_allocator(allocator)
+        _check(lib().qsd_ham_create(subspace.handle, op.handle, 0, _alloc_arg(self._allocator), _stream(stream),
+                                    ctypes.byref(h)))
         self._h = h
         self.N = subspace.N
         self.is_complex = op.is_complex
@@ -482,7 +530,7 @@ class SubspaceHamiltonian:
                 want_vector=False, use_graph=False, v0_vector=None, stream=None, raise_on_nonconv=True, block=1):
         """Lowest eigenvalue by GPU Lanczos: ``(energy, vector or None, info dict)``.
 
-        ``block`` 4 or 8 runs block Lanczos (``max_iter`` then counts block steps)."""
+        ``block`` 4, 8 or 16 runs block Lanczos (``max_iter`` then counts block steps)."""
         return _lanczos(lib().qsd_lanczos, lib().qsd_block_lanczos, self._h, self.N, max_iter, tol, v0, seed,
                         spmv_dtype, check_every, want_vector, use_graph, v0_vector, stream, raise_on_nonconv, block,
                         self.is_complex)
@@ -534,7 +582,7 @@ class CsrMatrix:
     """The operator's CSR matrix kept on the device (``qsd_csr_*``): SpMV and Lanczos on it."""
 
     def __init__(self, ham: "SubspaceHamiltonian", index_type: int = INDEX_I32, dtype=None,
-                 lower_mirror: bool = False, stream=None):
+                 lower_mirror: bool = False, stream=None, allocator="default"):
         import torch
 
         if dtype is None:
@@ -542,8 +590,9 @@ class CsrMatrix:
         self.dtype = dtype
         code = {torch.float64: F64, torch.float32: F32, torch.complex128: C128, torch.complex64: C64}[dtype]
         h = ctypes.c_void_p()
+        self._allocator = _resolve_allocator(allocator)
         _check(lib().qsd_csr_create(ham.handle, index_type, code, CSR_LOWER_MIRROR if lower_mirror else 0,
-                                    _stream(stream), ctypes.byref(h)))
+                                    _alloc_arg(self._allocator), _stream(stream), ctypes.byref(h)))
         self._h = h
         self.index_type = index_type
         N, nnz, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
@@ -631,11 +680,13 @@ class LanczosBatch:
 
     RUNNING, CONVERGED, LIMIT = 1, 2, 3
 
-    def __init__(self, max_requests: int, max_iter: int = 300, spmv_dtype: str = "f64"):
+    def __init__(self, max_requests: int, max_iter: int = 300, spmv_dtype: str = "f64", allocator="default"):
         self.max_requests, self.max_iter = int(max_requests), int(max_iter)
         self.dtype = {"f64": F64, "f32": F32}[spmv_dtype]
         h = ctypes.c_void_p()
-        _check(lib().qsd_batch_create(self.max_requests, self.max_iter, self.dtype, ctypes.byref(h)))
+        self._allocator = _resolve_allocator(allocator)
+        _check(lib().qsd_batch_create(self.max_requests, self.max_iter, self.dtype, _alloc_arg(self._allocator),
+                                      ctypes.byref(h)))
         self._h = h
         self._hams = {}
 

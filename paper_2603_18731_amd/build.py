@@ -15,8 +15,10 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqsd.so")
 
 SOURCES = ["ham.hip", "serve.hip", "csr.hip", "spmv_w1.hip", "spmv_w2.hip", "spmv_w4.hip", "spmv_w8.hip",
-           "spmv_w16.hip", "subspace.hip", "lanczos.hip", "block.hip", "ramps.hip", "diag.hip", "opcompile.cpp",
-           "api.cpp"]
+           "spmv_w16.hip", "subspace.hip", "lanczos.hip", "block.hip", "ramps.hip", "opcompile.cpp", "api.cpp"]
+# bench-only microbenchmarks, a library of their own (not part of the C-ABI in include/qsd.h)
+BENCH_SOURCES = ["bench/gather_rate.hip"]
+BENCH_LIB = os.path.join(HERE, "libqsd_bench.so")
 ARCH = os.environ.get("QSD_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -29,7 +31,7 @@ DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-p
 
 def _compile(src: str) -> str:
     path = os.path.join(CSRC, src)
-    obj = os.path.join(BUILD, src + ".o")
+    obj = os.path.join(BUILD, src.replace("/", "_") + ".o")
     cmd = [HIPCC] + COMMON + ["-c", path, "-o", obj]
     if src.endswith(".hip"):
         cmd = [HIPCC] + COMMON + DEVICE + ["-x", "hip", "-c", path, "-o", obj]
@@ -49,8 +51,15 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr[-8000:]))
     os.replace(tmp, LIB)
+    bobjs = [_compile(src) for src in BENCH_SOURCES]
+    tmp = BENCH_LIB + ".tmp"
+    r = subprocess.run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH] + bobjs + ["-o", tmp],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("bench library link failed:\n%s" % r.stderr[-8000:])
+    os.replace(tmp, BENCH_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", BENCH_LIB)
     return LIB
 
 

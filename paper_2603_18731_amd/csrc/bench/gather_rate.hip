@@ -1,9 +1,9 @@
-// Device diagnostics: the random-gather rate that bounds hash probing.
-#include <vector>
+// Bench-only microbenchmark (not part of the library's C-ABI; built into libqsd_bench.so and
+// loaded by bench.py --gather-ceiling): the random-gather rate that bounds hash probing.
+#include <hip/hip_runtime.h>
 
-#include "common.h"
+#include <cstdint>
 
-namespace qsd {
 namespace {
 
 // Each lane issues `ilp` independent random 4-byte loads per iteration from an array of
@@ -33,24 +33,25 @@ __global__ __launch_bounds__(256) void k_gather(const uint32_t *__restrict__ a, 
 }
 
 }  // namespace
-}  // namespace qsd
 
-using namespace qsd;
-
-extern "C" int qsd_device_gather_rate(int64_t bytes, int32_t ilp, double *loads_per_s, void *stream) {
-    clear_error();
-    if (!loads_per_s || bytes < 1024 || (bytes & (bytes - 1)) != 0 || bytes > (int64_t(1) << 34))
-        return fail(QSD_ERR_INVALID_ARG, "bytes must be a power of two in [1 KiB, 16 GiB]");
-    if (ilp != 1 && ilp != 2 && ilp != 4 && ilp != 8) return fail(QSD_ERR_INVALID_ARG, "ilp must be 1, 2, 4 or 8");
+// Random 4-byte loads per second (`ilp` independent loads in flight per lane) from a buffer of
+// `bytes` (power of two, 1 KiB .. 16 GiB) on the current device.  Returns 0, or -1 on bad
+// arguments, -2 when the buffers cannot be allocated, -3 on a HIP error.
+extern "C" int qsdbench_gather_rate(int64_t bytes, int32_t ilp, double *loads_per_s, void *stream) {
+    if (!loads_per_s || bytes < 1024 || (bytes & (bytes - 1)) != 0 || bytes > (int64_t(1) << 34)) return -1;
+    if (ilp != 1 && ilp != 2 && ilp != 4 && ilp != 8) return -1;
     hipStream_t st = (hipStream_t)stream;
     uint32_t *a = nullptr, *out = nullptr;
     const int blocks = 256 * 32;
-    QSD_TRY(dev_alloc(&a, (size_t)(bytes / 4)));
-    int rc = dev_alloc(&out, (size_t)blocks * 256);
+    if (hipMalloc((void **)&a, (size_t)bytes) != hipSuccess) return -2;
+    if (hipMalloc((void **)&out, (size_t)blocks * 256 * 4) != hipSuccess) {
+        (void)hipFree(a);
+        return -2;
+    }
+    int rc = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (rc == QSD_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
-        rc = fail(QSD_ERR_HIP, "event create failed");
-    if (rc == QSD_OK) {
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = -3;
+    if (rc == 0) {
         const uint32_t mask = (uint32_t)(bytes / 4 - 1);
         const int iters = 64 / ilp;
         auto launch = [&]() {
@@ -68,13 +69,13 @@ extern "C" int qsd_device_gather_rate(int64_t bytes, int32_t ilp, double *loads_
         hipEventRecord(e1, st);
         float ms = 0.0f;
         if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-            rc = fail(QSD_ERR_HIP, "gather benchmark failed: %s", hipGetErrorString(hipGetLastError()));
+            rc = -3;
         else
             *loads_per_s = 5.0 * blocks * 256.0 * 64.0 / (ms * 1e-3);
     }
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
-    dev_free(a);
-    dev_free(out);
+    (void)hipFree(a);
+    (void)hipFree(out);
     return rc;
 }

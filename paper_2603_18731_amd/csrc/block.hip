@@ -26,8 +26,17 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kGramTiles = 512;   // row tiles of the Gram reductions (a multiple of 4)
-constexpr int kMaxSteps = 80;     // block steps; T is at most (kMaxSteps + 1) * b square
-constexpr int kRitzMaxN = (kMaxSteps + 1) * 8;
+constexpr int kMaxSteps = 80;     // block steps for b = 4, 8; T is at most (kMaxSteps + 1) * b square
+// Step limit per block size: the Ritz solve keeps T's band, (steps + 1) b rows of b + 1, in the
+// LDS of one workgroup (gfx950 gives a workgroup up to 160 KB), so b = 16 takes at most 40 steps
+// (a Krylov space of 640, 94 KB of band).
+template <int B>
+struct BlockLimits {
+    static constexpr int steps = B <= 8 ? kMaxSteps : 40;
+    static constexpr int ritz_rows = (steps + 1) * B;
+    // coefficient blocks of C staged in LDS at a time by the update kernel (all of them for b <= 8)
+    static constexpr int stage = B <= 8 ? kMaxSteps + 1 : 8;
+};
 
 struct BlzState {
     int64_t N = 0;
@@ -160,26 +169,37 @@ template <int B>
 __global__ __launch_bounds__(kThreads) void kbl_update(const double *__restrict__ Vb, int64_t vstride,
                                                       const int *__restrict__ kdev, const double *__restrict__ C,
                                                       double *__restrict__ W, int64_t N) {
-    __shared__ double Cs[(kMaxSteps + 1) * B * B];
+    constexpr int JS = BlockLimits<B>::stage;  // blocks of C in LDS at a time
+    __shared__ double Cs[JS * B * B];
     const int cnt = *kdev + 1;
-    for (int t = threadIdx.x; t < cnt * B * B; t += kThreads) Cs[t] = C[t];
-    __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < N; i += (int64_t)gridDim.x * kThreads) {
+    // the loop over row batches is uniform per workgroup, so every thread meets the barriers
+    for (int64_t i0 = (int64_t)blockIdx.x * kThreads; i0 < N; i0 += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = i0 + threadIdx.x;
+        const bool on = i < N;
         double acc[B];
 #pragma unroll
         for (int q = 0; q < B; ++q) acc[q] = 0.0;
-        for (int j = 0; j < cnt; ++j) {
-            double v[B];
+        for (int js = 0; js < cnt; js += JS) {
+            const int jn = min(JS, cnt - js);
+            __syncthreads();
+            for (int t = threadIdx.x; t < jn * B * B; t += kThreads) Cs[t] = C[(int64_t)js * B * B + t];
+            __syncthreads();
+            if (!on) continue;
+            for (int j = 0; j < jn; ++j) {
+                double v[B];
 #pragma unroll
-            for (int p = 0; p < B; ++p) v[p] = Vb[(int64_t)j * vstride + i * B + p];
-            const double *cj = Cs + j * B * B;
+                for (int p = 0; p < B; ++p) v[p] = Vb[(int64_t)(js + j) * vstride + i * B + p];
+                const double *cj = Cs + j * B * B;
 #pragma unroll
-            for (int p = 0; p < B; ++p)
+                for (int p = 0; p < B; ++p)
 #pragma unroll
-                for (int q = 0; q < B; ++q) acc[q] += v[p] * cj[p * B + q];
+                    for (int q = 0; q < B; ++q) acc[q] += v[p] * cj[p * B + q];
+            }
         }
+        if (on) {
 #pragma unroll
-        for (int q = 0; q < B; ++q) W[i * B + q] -= acc[q];
+            for (int q = 0; q < B; ++q) W[i * B + q] -= acc[q];
+        }
     }
 }
 
@@ -361,15 +381,21 @@ __global__ __launch_bounds__(kThreads) void kbl_argmin(const double *__restrict_
 // spread over lanes.
 template <int B>
 __device__ bool band_chol(double *M, int n, int lane) {
-    int pa = 0, pb = 0;
-    {
-        int t = lane, a = 1;
+    // pair number t -> (a, b): t = a (a - 1) / 2 + (b - 1); each pair updates its own element of
+    // the band from column i only, so the pairs are independent (b = 16 has 136 of them, taken
+    // 64 at a time)
+    constexpr int kPairs = B * (B + 1) / 2;
+    constexpr int kRounds = (kPairs + 63) / 64;
+    int pa[kRounds], pb[kRounds];
+#pragma unroll
+    for (int k = 0; k < kRounds; ++k) {
+        int t = lane + 64 * k, a = 1;
         while (a <= B && t >= a) {
             t -= a;
             ++a;
         }
-        pa = a;
-        pb = t + 1;  // valid when a <= B
+        pa[k] = a;
+        pb[k] = t + 1;  // valid when a <= B
     }
     for (int i = 0; i < n; ++i) {
         const double piv = M[i * (B + 1)];
@@ -379,9 +405,12 @@ __device__ bool band_chol(double *M, int n, int lane) {
         if (lane >= 1 && lane <= B && i + lane < n) M[(i + lane) * (B + 1) + lane] /= l;
         if (lane == 0) M[i * (B + 1)] = l;
         __syncthreads();
-        if (pa <= B && i + pa < n) {
-            const int r = i + pa, c = i + pb;
-            M[r * (B + 1) + (pa - pb)] -= M[r * (B + 1) + pa] * M[c * (B + 1) + pb];
+#pragma unroll
+        for (int k = 0; k < kRounds; ++k) {
+            if (pa[k] <= B && i + pa[k] < n) {
+                const int r = i + pa[k], c = i + pb[k];
+                M[r * (B + 1) + (pa[k] - pb[k])] -= M[r * (B + 1) + pa[k]] * M[c * (B + 1) + pb[k]];
+            }
         }
         __syncthreads();
     }
@@ -407,8 +436,8 @@ __device__ void band_load(double *M, const double *__restrict__ Tb, const double
 template <int B>
 __global__ __launch_bounds__(64) void kbl_ritz(const double *__restrict__ Tb, const double *__restrict__ dead, int nblocks,
                                                double *__restrict__ out) {
-    __shared__ double M[kRitzMaxN * (B + 1)];
-    __shared__ double z[kRitzMaxN];
+    __shared__ double M[BlockLimits<B>::ritz_rows * (B + 1)];
+    __shared__ double z[BlockLimits<B>::ritz_rows];
     __shared__ double sh[2];
     const int n = nblocks * B;
     const int lane = threadIdx.x;
@@ -570,7 +599,7 @@ void enqueue_cholqr2(BlzState &S, double *dst, double *Vb, int off, int mode_bas
     const int *kd = mode_base >= 2 ? S.kdev : nullptr;
     for (int pass = 0; pass < 2; ++pass) {
         kbl_gram<B><<<dim3(kGramTiles, 1), kThreads, 0, st>>>(S.W, 0, nullptr, S.W, N, S.part);
-        kbl_reduce<B><<<1, 64, 0, st>>>(S.part, nullptr, S.C, nullptr);
+        kbl_reduce<B><<<1, B * B < 64 ? 64 : B * B, 0, st>>>(S.part, nullptr, S.C, nullptr);
         kbl_chol<B><<<1, 64, 0, st>>>(S.C, mode_base + pass, kd, S.Rm, S.A, S.Tb, S.dead, S.flag);
         if (pass == 0)
             kbl_scale<B><<<rows_grid(N, B), kThreads, 0, st>>>(S.W, S.W, S.Rm + 2 * B * B, N, nullptr, 0, nullptr, 0);
@@ -592,7 +621,7 @@ int enqueue_step(const SpmvOp &op, BlzState &S, bool f32, hipStream_t st) {
     const unsigned jy = (unsigned)((S.m + 1 + gram_blocks<B>() - 1) / gram_blocks<B>());
     for (int pass = 0; pass < 2; ++pass) {
         kbl_gram<B><<<dim3(kGramTiles, jy), kThreads, 0, st>>>(S.V, N * B, S.kdev, S.W, N, S.part);
-        kbl_reduce<B><<<S.m + 1, 64, 0, st>>>(S.part, S.kdev, S.C, S.A);
+        kbl_reduce<B><<<S.m + 1, B * B < 64 ? 64 : B * B, 0, st>>>(S.part, S.kdev, S.C, S.A);
         kbl_update<B><<<rows_grid(N, B), kThreads, 0, st>>>(S.V, N * B, S.kdev, S.C, S.W, N);
     }
     enqueue_cholqr2<B>(S, S.X, S.V, 1, 2, st);
@@ -794,9 +823,10 @@ int block_entry(const SpmvOp &op, int32_t block, const qsd_lanczos_opts *opts, d
     qsd_lanczos_default_opts(&o);
     if (opts) o = *opts;
     if (op.is_complex()) return fail(QSD_ERR_UNSUPPORTED, "block Lanczos for complex operators is not implemented");
-    if (block != 4 && block != 8) return fail(QSD_ERR_INVALID_ARG, "block must be 4 or 8");
-    if (o.max_iter < 1 || o.max_iter > kMaxSteps)
-        return fail(QSD_ERR_INVALID_ARG, "max_iter (block steps) must be in [1, %d]", kMaxSteps);
+    if (block != 4 && block != 8 && block != 16) return fail(QSD_ERR_INVALID_ARG, "block must be 4, 8 or 16");
+    const int max_steps = block == 16 ? BlockLimits<16>::steps : kMaxSteps;
+    if (o.max_iter < 1 || o.max_iter > max_steps)
+        return fail(QSD_ERR_INVALID_ARG, "max_iter (block steps) must be in [1, %d] for block %d", max_steps, block);
     if (!(o.tol > 0)) return fail(QSD_ERR_INVALID_ARG, "tol must be > 0");
     if (o.spmv_dtype != QSD_F64 && o.spmv_dtype != QSD_F32) return fail(QSD_ERR_DTYPE, "spmv_dtype must be F64 or F32");
     if (!op.takes(o.spmv_dtype)) return fail(QSD_ERR_DTYPE, "spmv_dtype must be the stored matrix's dtype");
@@ -805,8 +835,10 @@ int block_entry(const SpmvOp &op, int32_t block, const qsd_lanczos_opts *opts, d
         return fail(QSD_ERR_INVALID_ARG, "d_evec is required for QSD_V0_USER / want_vector");
     if (o.check_every < 1) o.check_every = 1;
     hipStream_t st = (hipStream_t)stream;
-    return block == 8 ? block_lanczos<8>(op, o, eval_out, d_evec, info, st)
-                      : block_lanczos<4>(op, o, eval_out, d_evec, info, st);
+    AllocScope scope(o.alloc ? o.alloc : op.allocator(), stream);
+    return block == 16 ? block_lanczos<16>(op, o, eval_out, d_evec, info, st)
+           : block == 8 ? block_lanczos<8>(op, o, eval_out, d_evec, info, st)
+                        : block_lanczos<4>(op, o, eval_out, d_evec, info, st);
 }
 
 }  // namespace

@@ -54,23 +54,41 @@ void hash_words(int n_qubits, std::vector<uint64_t> &z);  // z[q] per qubit
 void part_words(int n_qubits, int split, std::vector<uint32_t> &pz);  // packed part-index word per qubit
 void hash_byte_tables(int Wp, const std::vector<uint64_t> &z, std::vector<uint64_t> &tab);  // [Wp*8][256]
 
-// Device memory helpers --------------------------------------------------------------
+// Device memory ----------------------------------------------------------------------
+// Every device allocation goes through the allocator of the current scope: each entry point
+// opens an AllocScope with the allocator of the handle it works for (or the one the caller
+// passes) and its stream; outside any scope, or with a NULL allocator, hipMalloc / hipFree.
+struct AllocScope {
+    AllocScope(const qsd_allocator *a, void *stream);
+    ~AllocScope();
+    AllocScope(const AllocScope &) = delete;
+    AllocScope &operator=(const AllocScope &) = delete;
+
+  private:
+    const qsd_allocator *prev_a;
+    void *prev_s;
+};
+void *raw_alloc(size_t bytes);  // NULL on failure
+void raw_free(void *p);
+bool custom_allocator();         // the current scope has a caller's allocator
+
+// The allocator a handle keeps (a copy of the caller's; all NULL = hipMalloc / hipFree).
+inline qsd_allocator keep_allocator(const qsd_allocator *a) {
+    qsd_allocator k{nullptr, nullptr, nullptr};
+    if (a && a->alloc && a->free) k = *a;
+    return k;
+}
+
 template <class T>
 int dev_alloc(T **p, size_t count) {
-    *p = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return fail(QSD_ERR_OUT_OF_MEMORY, "hipMalloc(%zu bytes) failed: %s", count * sizeof(T),
-                    hipGetErrorString(e));
-    }
+    *p = (T *)raw_alloc(count * sizeof(T));
+    if (!*p) return fail(QSD_ERR_OUT_OF_MEMORY, "device allocation of %zu bytes failed", count * sizeof(T));
     return QSD_OK;
 }
 template <class T>
 void dev_free(T *&p) {
-    if (p) (void)hipFree((void *)p);
+    raw_free((void *)p);
     p = nullptr;
 }
 
@@ -104,6 +122,8 @@ inline void free_rows(SlotRows &r) {
 }  // namespace qsd
 
 struct qsd_subspace {
+    qsd_allocator alloc{nullptr, nullptr, nullptr};  // device memory of this handle (all NULL: hipMalloc)
+    void *stream = nullptr;                          // stream of the build (frees at destroy)
     int32_t n_qubits = 0;
     int32_t W = 0;   // words per string
     int32_t Wp = 0;  // padded words used by kernels
@@ -177,6 +197,8 @@ constexpr uint32_t kInfoLadder = 1u << 3;
 constexpr uint32_t kInfoCare = 1u << 4;
 
 struct qsd_ham {
+    qsd_allocator alloc{nullptr, nullptr, nullptr};
+    void *stream = nullptr;
     const qsd_subspace *s = nullptr;
     const qsd_op *op = nullptr;
     int64_t N = 0;
@@ -206,6 +228,8 @@ struct qsd_ham {
 };
 
 struct qsd_csr {
+    qsd_allocator alloc{nullptr, nullptr, nullptr};
+    void *stream = nullptr;
     int64_t N = 0;
     int64_t nnz = 0;
     int32_t index_type = QSD_INDEX_I32;
@@ -226,6 +250,7 @@ struct SpmvOp {
     int64_t N() const { return c ? c->N : h->N; }
     bool is_complex() const { return c ? c->cplx : h->is_complex; }
     const double *diag() const { return c ? c->diag : h->diag; }
+    const qsd_allocator *allocator() const { return c ? &c->alloc : &h->alloc; }
     bool takes(int32_t dtype) const { return !c || c->dtype == dtype; }
     int matvec(int nvec, const void *x, int64_t ldx, void *y, int64_t ldy, int32_t dtype, hipStream_t st) const {
         return c ? qsd_csr_matvec(c, nvec, x, ldx, y, ldy, dtype, st) : qsd_matvec(h, nvec, x, ldx, y, ldy, dtype, st);

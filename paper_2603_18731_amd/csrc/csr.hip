@@ -269,8 +269,8 @@ void spmv_dtype(const qsd_csr *c, const void *x, int64_t ldx, void *y, int64_t l
 void free_csr(qsd_csr *c) {
     if (!c) return;
     dev_free(c->indptr);
-    if (c->indices) (void)hipFree(c->indices);
-    if (c->data) (void)hipFree(c->data);
+    dev_free(c->indices);
+    dev_free(c->data);
     dev_free(c->diag);
     delete c;
 }
@@ -322,14 +322,8 @@ int build_lower(const qsd_ham *h, qsd_csr *c, hipStream_t st) {
     if (rc == QSD_OK) rc = f32 ? dev_alloc((float2 **)&vals, nnz) : dev_alloc((double2 **)&vals, nnz);
     const size_t isz = c->index_type == QSD_INDEX_I32 ? 4 : 8;
     const size_t vsz = (f32 ? 4 : 8) * (c->cplx ? 2 : 1);
-    if (rc == QSD_OK && hipMalloc(&c->indices, std::max<size_t>(1, nnz * isz)) != hipSuccess) {
-        c->indices = nullptr;
-        rc = fail(QSD_ERR_OUT_OF_MEMORY, "CSR indices allocation failed");
-    }
-    if (rc == QSD_OK && hipMalloc(&c->data, std::max<size_t>(1, nnz * vsz)) != hipSuccess) {
-        c->data = nullptr;
-        rc = fail(QSD_ERR_OUT_OF_MEMORY, "CSR data allocation failed");
-    }
+    if (rc == QSD_OK) rc = dev_alloc((uint8_t **)&c->indices, nnz * isz);
+    if (rc == QSD_OK) rc = dev_alloc((uint8_t **)&c->data, nnz * vsz);
     if (rc == QSD_OK) {
         k_fill0_u64<<<1024, 256, 0, st>>>(cnt, N + 1);
         const SubView sv = sub_view(h->s);
@@ -350,7 +344,7 @@ int build_lower(const qsd_ham *h, qsd_csr *c, hipStream_t st) {
     }
     dev_free(cnt);
     dev_free(cols);
-    if (vals) (void)hipFree(vals);
+    dev_free(vals);
     return rc;
 }
 
@@ -359,8 +353,8 @@ int build_lower(const qsd_ham *h, qsd_csr *c, hipStream_t st) {
 
 using namespace qsd;
 
-extern "C" int qsd_csr_create(const qsd_ham *h, int32_t index_type, int32_t dtype, uint32_t flags, void *stream,
-                              qsd_csr **out) {
+extern "C" int qsd_csr_create(const qsd_ham *h, int32_t index_type, int32_t dtype, uint32_t flags,
+                              const qsd_allocator *alloc, void *stream, qsd_csr **out) {
     clear_error();
     if (!h || !out) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
     *out = nullptr;
@@ -375,6 +369,9 @@ extern "C" int qsd_csr_create(const qsd_ham *h, int32_t index_type, int32_t dtyp
     hipStream_t st = (hipStream_t)stream;
     auto *c = new (std::nothrow) qsd_csr();
     if (!c) return fail(QSD_ERR_OUT_OF_MEMORY, "host allocation failed");
+    c->alloc = keep_allocator(alloc);
+    c->stream = stream;
+    AllocScope scope(&c->alloc, stream);
     c->N = h->N;
     c->index_type = index_type;
     c->dtype = dtype;
@@ -397,14 +394,8 @@ extern "C" int qsd_csr_create(const qsd_ham *h, int32_t index_type, int32_t dtyp
             rc = qsd_csr_build(h, c->indptr, nullptr, nullptr, index_type, dtype, &nnz, stream);
             const size_t isz = index_type == QSD_INDEX_I32 ? 4 : 8;
             const size_t vsz = ((dtype == QSD_F32 || dtype == QSD_C64) ? 4 : 8) * (c->cplx ? 2 : 1);
-            if (rc == QSD_OK && hipMalloc(&c->indices, std::max<size_t>(1, nnz * isz)) != hipSuccess) {
-                c->indices = nullptr;
-                rc = fail(QSD_ERR_OUT_OF_MEMORY, "CSR indices allocation failed");
-            }
-            if (rc == QSD_OK && hipMalloc(&c->data, std::max<size_t>(1, nnz * vsz)) != hipSuccess) {
-                c->data = nullptr;
-                rc = fail(QSD_ERR_OUT_OF_MEMORY, "CSR data allocation failed");
-            }
+            if (rc == QSD_OK) rc = dev_alloc((uint8_t **)&c->indices, nnz * isz);
+            if (rc == QSD_OK) rc = dev_alloc((uint8_t **)&c->data, nnz * vsz);
             if (rc == QSD_OK) rc = qsd_csr_build(h, c->indptr, c->indices, c->data, index_type, dtype, &nnz, stream);
             c->nnz = nnz;
         }
@@ -470,6 +461,8 @@ extern "C" int qsd_csr_matvec(const qsd_csr *c, int32_t nvec, const void *d_x, i
 
 extern "C" int qsd_csr_destroy(qsd_csr *c) {
     clear_error();
+    if (!c) return QSD_OK;
+    AllocScope scope(&c->alloc, c->stream);
     free_csr(c);
     return QSD_OK;
 }

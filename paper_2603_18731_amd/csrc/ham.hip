@@ -318,7 +318,8 @@ int check_dtype(const qsd_ham *h, int32_t dtype) {
 
 using namespace qsd;
 
-extern "C" int qsd_ham_create(const qsd_subspace *s, const qsd_op *op, uint32_t flags, void *stream, qsd_ham **out) {
+extern "C" int qsd_ham_create(const qsd_subspace *s, const qsd_op *op, uint32_t flags, const qsd_allocator *alloc,
+                              void *stream, qsd_ham **out) {
     clear_error();
     if (!out) return fail(QSD_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -328,6 +329,9 @@ extern "C" int qsd_ham_create(const qsd_subspace *s, const qsd_op *op, uint32_t 
     (void)flags;
     auto *h = new (std::nothrow) qsd_ham();
     if (!h) return fail(QSD_ERR_OUT_OF_MEMORY, "host allocation failed");
+    h->alloc = keep_allocator(alloc);
+    h->stream = stream;
+    AllocScope scope(&h->alloc, stream);
     h->s = s;
     h->op = op;
     h->N = s->N;
@@ -362,6 +366,8 @@ extern "C" int qsd_ham_diagonal(const qsd_ham *h, double *d_out, void *stream) {
 
 extern "C" int qsd_ham_destroy(qsd_ham *h) {
     clear_error();
+    if (!h) return QSD_OK;
+    AllocScope scope(&h->alloc, h->stream);
     free_ham(h);
     return QSD_OK;
 }
@@ -400,6 +406,7 @@ extern "C" int qsd_csr_build(const qsd_ham *h, int64_t *d_indptr, void *d_indice
     if (index_type == QSD_INDEX_I32 && h->N >= (1ll << 31))
         return fail(QSD_ERR_CAPACITY, "N = %lld does not fit int32 column indices", (long long)h->N);
     QSD_TRY(check_dtype(h, dtype));
+    AllocScope scope(&h->alloc, stream);
     hipStream_t st = (hipStream_t)stream;
     const bool fill = d_indices && d_data;
     if ((d_indices == nullptr) != (d_data == nullptr))
@@ -463,7 +470,7 @@ extern "C" int qsd_csr_build(const qsd_ham *h, int64_t *d_indptr, void *d_indice
             rc = fail(QSD_ERR_HIP, "CSR fill failed: %s", hipGetErrorString(hipGetLastError()));
     }
     dev_free(cols);
-    if (vals) (void)hipFree(vals);
+    dev_free(vals);
     if (nnz_out) *nnz_out = nnz;
     return rc;
 }
@@ -471,6 +478,7 @@ extern "C" int qsd_csr_build(const qsd_ham *h, int64_t *d_indptr, void *d_indice
 extern "C" int qsd_ham_work_counts(const qsd_ham *h, int64_t *probes, int64_t *hits, void *stream) {
     clear_error();
     if (!h) return fail(QSD_ERR_INVALID_ARG, "ham is NULL");
+    AllocScope scope(&h->alloc, stream);
     hipStream_t st = (hipStream_t)stream;
     unsigned long long *acc = nullptr;
     QSD_TRY(dev_alloc(&acc, 2));
@@ -515,6 +523,7 @@ __global__ __launch_bounds__(256) void k_min_above(const double *__restrict__ d,
 extern "C" int qsd_ham_diag_splitting(const qsd_ham *h, double *lowest, double *splitting, void *stream) {
     clear_error();
     if (!h) return fail(QSD_ERR_INVALID_ARG, "NULL handle");
+    AllocScope scope(&h->alloc, stream);
     hipStream_t st = (hipStream_t)stream;
     constexpr int kParts = 1024;
     double *part = nullptr;
@@ -575,6 +584,7 @@ extern "C" int qsd_ham_set_schedule(qsd_ham *h, uint32_t schedule) {
         // no caller stream here: wait for all work on the device (the tables may still be
         // being written on another stream), then build on the default stream
         if (hipDeviceSynchronize() != hipSuccess) return fail(QSD_ERR_HIP, "device synchronize failed");
+        AllocScope scope(&h->alloc, nullptr);
         QSD_TRY(ensure_rowbits(h, nullptr));
     }
     h->schedule = schedule;
@@ -596,6 +606,7 @@ extern "C" int qsd_ham_autotune(qsd_ham *h, int32_t nvec, int32_t dtype, int32_t
     if (reps < 1) return fail(QSD_ERR_INVALID_ARG, "reps must be >= 1");
     if (flags & ~(QSD_TUNE_SCHEDULE | QSD_TUNE_LOAD | QSD_TUNE_SPLIT)) return fail(QSD_ERR_INVALID_ARG, "unknown tuning flags");
     QSD_TRY(check_dtype(h, dtype));
+    AllocScope scope(&h->alloc, stream);
     hipStream_t st = (hipStream_t)stream;
     qsd_subspace *sub = const_cast<qsd_subspace *>(h->s);
     const size_t esz = dtype == QSD_F64 ? 8 : dtype == QSD_F32 ? 4 : dtype == QSD_C128 ? 16 : 8;

@@ -435,6 +435,7 @@ extern "C" void qsd_lanczos_default_opts(qsd_lanczos_opts *o) {
     o->check_every = 5;
     o->want_vector = 0;
     o->use_graph = 0;
+    o->alloc = nullptr;
 }
 
 namespace {
@@ -458,6 +459,8 @@ int lanczos_impl(const SpmvOp &op, const qsd_lanczos_opts *opts, double *eval_ou
         return fail(QSD_ERR_INVALID_ARG, "d_evec is required for QSD_V0_USER / want_vector");
     if (o.check_every < 1) o.check_every = 1;
     hipStream_t st = (hipStream_t)stream;
+    // basis and work vectors from the caller's allocator or the operator's (the scope outlives S)
+    AllocScope scope(o.alloc ? o.alloc : op.allocator(), stream);
     const int64_t N = op.N();
     const int64_t NR = cplx ? 2 * N : N;  // doubles per vector
     LzState S;

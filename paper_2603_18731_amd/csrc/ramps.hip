@@ -108,6 +108,7 @@ extern "C" int qsd_ramps(const qsd_ham *h, const int64_t *s0, int64_t n0, double
     for (int64_t i = 0; i < n0; ++i)
         if (s0[i] < 0 || s0[i] >= h->N) return fail(QSD_ERR_INVALID_ARG, "initial index %lld out of range", (long long)s0[i]);
     hipStream_t st = (hipStream_t)stream;
+    AllocScope scope(&h->alloc, stream);
     const int64_t N = h->N;
     uint8_t *in_s0 = nullptr;
     int64_t *fi[2] = {nullptr, nullptr};

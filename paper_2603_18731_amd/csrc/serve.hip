@@ -365,6 +365,7 @@ __global__ __launch_bounds__(kBlock) void kbm_matvec(const MvReq *__restrict__ r
 using namespace qsd;
 
 struct qsd_batch {
+    qsd_allocator alloc{nullptr, nullptr, nullptr};  // tables and library-owned workspaces
     int max_slots = 0;
     int max_iter = 0;
     bool f32 = false;
@@ -373,8 +374,9 @@ struct qsd_batch {
         bool used = false;
         const qsd_ham *h = nullptr;
         ReqDev d{};
-        void *mem = nullptr;  // the request's workspace
-        bool owned = false;   // allocated by the library (else the caller's)
+        void *mem = nullptr;      // the request's workspace
+        bool owned = false;       // allocated by the library (else the caller's)
+        void *stream = nullptr;   // stream of the request's add (an owned workspace is released on it)
         double tol = 1e-10;
         int steps = 0;
     };
@@ -390,8 +392,11 @@ struct qsd_batch {
 
 namespace {
 
-void free_slot(qsd_batch::Slot &S) {
-    if (S.owned) dev_free(S.mem);
+void free_slot(const qsd_batch *b, qsd_batch::Slot &S) {
+    if (S.owned) {
+        AllocScope scope(&b->alloc, S.stream);
+        dev_free(S.mem);
+    }
     S = qsd_batch::Slot();
 }
 
@@ -426,6 +431,7 @@ Layout layout_of(int64_t N, int m, bool f32) {
 
 int sync_tables(qsd_batch *b, hipStream_t st) {
     if (!b->dirty) return QSD_OK;
+    AllocScope scope(&b->alloc, st);
     std::vector<ReqDev> host(b->max_slots);
     std::vector<Tile> mv, bl;
     for (int i = 0; i < b->max_slots; ++i) {
@@ -470,7 +476,8 @@ void launch_bmv(qsd_batch *b, hipStream_t st) {
 
 }  // namespace
 
-extern "C" int qsd_batch_create(int32_t max_requests, int32_t max_iter, int32_t spmv_dtype, qsd_batch **out) {
+extern "C" int qsd_batch_create(int32_t max_requests, int32_t max_iter, int32_t spmv_dtype, const qsd_allocator *alloc,
+                                qsd_batch **out) {
     clear_error();
     if (!out) return fail(QSD_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -479,6 +486,8 @@ extern "C" int qsd_batch_create(int32_t max_requests, int32_t max_iter, int32_t 
     if (spmv_dtype != QSD_F64 && spmv_dtype != QSD_F32) return fail(QSD_ERR_DTYPE, "spmv_dtype must be F64 or F32");
     auto *b = new (std::nothrow) qsd_batch();
     if (!b) return fail(QSD_ERR_OUT_OF_MEMORY, "host allocation failed");
+    b->alloc = keep_allocator(alloc);
+    AllocScope scope(&b->alloc, nullptr);
     b->max_slots = max_requests;
     b->max_iter = max_iter;
     b->f32 = spmv_dtype == QSD_F32;
@@ -570,6 +579,7 @@ int add_impl(qsd_batch *b, const qsd_ham *h, const qsd_csr *c, int32_t v0_mode, 
         S.mem = workspace;
         S.owned = false;
     } else {
+        AllocScope scope(&b->alloc, stream);
         uint8_t *p = nullptr;
         if ((rc = dev_alloc(&p, (size_t)L.total)) != QSD_OK) {
             S = qsd_batch::Slot();
@@ -577,6 +587,7 @@ int add_impl(qsd_batch *b, const qsd_ham *h, const qsd_csr *c, int32_t v0_mode, 
         }
         S.mem = p;
         S.owned = true;
+        S.stream = stream;
     }
     uint8_t *base = (uint8_t *)S.mem;
     d.V = (double *)(base + L.V);
@@ -596,7 +607,7 @@ int add_impl(qsd_batch *b, const qsd_ham *h, const qsd_csr *c, int32_t v0_mode, 
     if (h) b->Wp = h->Wp;
     b->dirty = true;
     if ((rc = sync_tables(b, st)) != QSD_OK) {
-        free_slot(S);
+        free_slot(b, S);
         b->dirty = true;
         return rc;
     }
@@ -613,7 +624,7 @@ int add_impl(qsd_batch *b, const qsd_ham *h, const qsd_csr *c, int32_t v0_mode, 
         if (hipGetLastError() != hipSuccess) rc = fail(QSD_ERR_HIP, "request start failed");
     }
     if (rc != QSD_OK) {
-        free_slot(S);
+        free_slot(b, S);
         b->dirty = true;
         return rc;
     }
@@ -709,9 +720,10 @@ extern "C" int qsd_batch_poll(qsd_batch *b, int32_t *status, double *energy, int
 extern "C" int qsd_batch_remove(qsd_batch *b, int32_t slot) {
     clear_error();
     if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(QSD_ERR_INVALID_ARG, "bad slot");
-    // device work that reads the slot was enqueued before; hipFree of an owned workspace waits
-    // for the device, a caller's workspace must stay valid until that work has finished
-    free_slot(b->slots[slot]);
+    // device work that reads the slot was enqueued before: an owned workspace is released
+    // stream-ordered (or by hipFree, which waits for the device); a caller's workspace must
+    // stay valid until that work has finished
+    free_slot(b, b->slots[slot]);
     b->dirty = true;
     return QSD_OK;
 }
@@ -720,7 +732,8 @@ extern "C" int qsd_batch_destroy(qsd_batch *b) {
     clear_error();
     if (!b) return QSD_OK;
     for (auto &S : b->slots)
-        if (S.used) free_slot(S);
+        if (S.used) free_slot(b, S);
+    AllocScope scope(&b->alloc, nullptr);
     dev_free(b->d_reqs);
     dev_free(b->d_mv);
     dev_free(b->d_bl);
@@ -807,13 +820,24 @@ extern "C" int qsd_matvec_batched(int32_t n, const qsd_ham *const *hams, const v
     }
     if (launches.empty()) return QSD_OK;
     if (tiles.size() > (size_t)INT32_MAX) return fail(QSD_ERR_CAPACITY, "too many row tiles");
-    // Stream-ordered tables: allocated, filled, used and released in order on `stream`.
+    // Stream-ordered tables: allocated, filled, used and released in order on `stream`, by the
+    // first operator's allocator (stream-ordered by contract) or hipMallocAsync.
+    AllocScope scope(&hams[0]->alloc, stream);
+    const bool own_alloc = custom_allocator();
     MvReq *d_reqs = nullptr;
     Tile *d_tiles = nullptr;
-    QSD_CHECK_HIP(hipMallocAsync((void **)&d_reqs, reqs.size() * sizeof(MvReq), st));
-    if (hipMallocAsync((void **)&d_tiles, tiles.size() * sizeof(Tile), st) != hipSuccess) {
-        (void)hipFreeAsync(d_reqs, st);
-        return fail(QSD_ERR_OUT_OF_MEMORY, "tile table allocation failed");
+    if (own_alloc) {
+        QSD_TRY(dev_alloc(&d_reqs, reqs.size()));
+        if (dev_alloc(&d_tiles, tiles.size()) != QSD_OK) {
+            dev_free(d_reqs);
+            return QSD_ERR_OUT_OF_MEMORY;
+        }
+    } else {
+        QSD_CHECK_HIP(hipMallocAsync((void **)&d_reqs, reqs.size() * sizeof(MvReq), st));
+        if (hipMallocAsync((void **)&d_tiles, tiles.size() * sizeof(Tile), st) != hipSuccess) {
+            (void)hipFreeAsync(d_reqs, st);
+            return fail(QSD_ERR_OUT_OF_MEMORY, "tile table allocation failed");
+        }
     }
     int rc = QSD_OK;
     // pageable sources: the copies return once the host data is staged
@@ -832,7 +856,12 @@ extern "C" int qsd_matvec_batched(int32_t n, const qsd_ham *const *hams, const v
         }
         if (hipGetLastError() != hipSuccess) rc = fail(QSD_ERR_HIP, "batched matvec launch failed");
     }
-    (void)hipFreeAsync(d_tiles, st);
-    (void)hipFreeAsync(d_reqs, st);
+    if (own_alloc) {
+        dev_free(d_tiles);
+        dev_free(d_reqs);
+    } else {
+        (void)hipFreeAsync(d_tiles, st);
+        (void)hipFreeAsync(d_reqs, st);
+    }
     return rc;
 }

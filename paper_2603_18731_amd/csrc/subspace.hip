@@ -552,7 +552,7 @@ int exclusive_scan_i64(const int64_t *d_in, int64_t *d_out, int64_t n, hipStream
 using namespace qsd;
 
 extern "C" int qsd_subspace_build(const uint64_t *d_bits, int64_t n_in, int32_t n_qubits, uint32_t flags,
-                                  double max_load, void *stream, qsd_subspace **out) {
+                                  double max_load, const qsd_allocator *alloc, void *stream, qsd_subspace **out) {
     clear_error();
     if (!out) return fail(QSD_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -563,6 +563,9 @@ extern "C" int qsd_subspace_build(const uint64_t *d_bits, int64_t n_in, int32_t 
     if (!(max_load > 0.0 && max_load <= 0.5)) return fail(QSD_ERR_INVALID_ARG, "max_load must be in (0, 0.5]");
     auto *sub = new (std::nothrow) qsd_subspace();
     if (!sub) return fail(QSD_ERR_OUT_OF_MEMORY, "host allocation failed");
+    sub->alloc = keep_allocator(alloc);
+    sub->stream = stream;
+    AllocScope scope(&sub->alloc, stream);
     sub->n_qubits = n_qubits;
     sub->W = (n_qubits + 63) / 64;
     sub->Wp = padded_words(n_qubits);
@@ -661,6 +664,7 @@ int rehash_impl(qsd_subspace *sub, int64_t C, int split, hipStream_t st) {
     std::vector<std::vector<uint32_t>> gp(nb);
     for (size_t k = 0; k < nb && rc == QSD_OK; ++k) {
         const qsd_op *op = sub->bound[k]->op;
+        AllocScope hscope(&sub->bound[k]->alloc, st);
         if (new_words) {
             gh[k] = group_hashes(op, z);
             rc = dev_alloc(&ghash[k], gh[k].size());
@@ -678,8 +682,11 @@ int rehash_impl(qsd_subspace *sub, int64_t C, int split, hipStream_t st) {
     }
     if (rc == QSD_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(QSD_ERR_HIP, "operator update failed");
     if (rc != QSD_OK) {
-        for (auto *p : ghash) dev_free(p);
-        for (auto *p : gparts) dev_free(p);
+        for (size_t k = 0; k < nb; ++k) {
+            AllocScope hscope(&sub->bound[k]->alloc, st);
+            dev_free(ghash[k]);
+            dev_free(gparts[k]);
+        }
         free_rows(rows);
         if (new_words) {
             dev_free(ztab);
@@ -720,6 +727,7 @@ int rehash_impl(qsd_subspace *sub, int64_t C, int split, hipStream_t st) {
     sub->split = split;
     for (size_t k = 0; k < nb; ++k) {
         qsd_ham *h = sub->bound[k];
+        AllocScope hscope(&h->alloc, st);
         if (new_words) {
             dev_free(h->g_hash);
             h->g_hash = ghash[k];
@@ -736,6 +744,7 @@ int rehash_impl(qsd_subspace *sub, int64_t C, int split, hipStream_t st) {
 extern "C" int qsd_subspace_rehash(qsd_subspace *s, double max_load, int32_t split, void *stream) {
     clear_error();
     if (!s) return fail(QSD_ERR_INVALID_ARG, "subspace is NULL");
+    AllocScope scope(&s->alloc, stream);
     if (max_load == 0.0) max_load = 0.125;
     if (!(max_load > 0.0 && max_load <= 0.5)) return fail(QSD_ERR_INVALID_ARG, "max_load must be in (0, 0.5]");
     if (split < 0 || split >= s->n_qubits)
@@ -803,6 +812,7 @@ extern "C" int qsd_subspace_select(const qsd_subspace *s, const uint8_t *d_mask,
     clear_error();
     if (!s || !d_mask || !out) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
     *out = nullptr;
+    AllocScope scope(&s->alloc, stream);
     hipStream_t st = (hipStream_t)stream;
     const int64_t N = s->N;
     int64_t *flag = nullptr, *pos = nullptr;
@@ -822,7 +832,8 @@ extern "C" int qsd_subspace_select(const qsd_subspace *s, const uint8_t *d_mask,
     if (rc == QSD_OK) {
         k_select_rows<<<grid_for(N, kBlock), kBlock, 0, st>>>(s->keys, N, s->W, d_mask, pos, rows);
         // the rows stay in ascending order and distinct
-        rc = qsd_subspace_build(rows, n, s->n_qubits, QSD_SUB_ASSUME_SORTED_UNIQUE, max_load, stream, out);
+        rc = qsd_subspace_build(rows, n, s->n_qubits, QSD_SUB_ASSUME_SORTED_UNIQUE, max_load, &s->alloc, stream,
+                                out);
     }
     dev_free(flag);
     dev_free(pos);
@@ -862,6 +873,7 @@ extern "C" int qsd_subspace_lookup(const qsd_subspace *s, const uint64_t *d_q, i
 extern "C" int qsd_subspace_probe_stats(const qsd_subspace *s, double *mean_probe, int64_t *max_probe, void *stream) {
     clear_error();
     if (!s) return fail(QSD_ERR_INVALID_ARG, "subspace is NULL");
+    AllocScope scope(&s->alloc, stream);
     hipStream_t st = (hipStream_t)stream;
     unsigned long long *acc = nullptr;
     QSD_TRY(dev_alloc(&acc, 2));
@@ -882,6 +894,8 @@ extern "C" int qsd_subspace_probe_stats(const qsd_subspace *s, double *mean_prob
 
 extern "C" int qsd_subspace_destroy(qsd_subspace *s) {
     clear_error();
+    if (!s) return QSD_OK;
+    AllocScope scope(&s->alloc, s->stream);
     free_sub(s);
     return QSD_OK;
 }

@@ -39,7 +39,7 @@ def _oracle_e0(keys, tl):
     return e
 
 
-@pytest.mark.parametrize("block", [4, 8])
+@pytest.mark.parametrize("block", [4, 8, 16])
 def test_block_tfim12_closed_form(block):
     c1 = wl.c1_tfim12()
     H = _ham(c1.keys, c1.ops)
@@ -47,8 +47,8 @@ def test_block_tfim12_closed_form(block):
     side = torch.cuda.Stream()  # graph capture needs a non-default stream
     for use_graph in (False, True):
         with torch.cuda.stream(side):
-            e, vec, info = H.lanczos(max_iter=60, tol=1e-11, block=block, want_vector=True, use_graph=use_graph,
-                                     check_every=2)
+            e, vec, info = H.lanczos(max_iter=60 if block < 16 else 40, tol=1e-11, block=block, want_vector=True,
+                                     use_graph=use_graph, check_every=2)
         torch.cuda.synchronize()
         say("block", block, "graph", use_graph, e, info)
         assert info["converged"]
@@ -56,25 +56,36 @@ def test_block_tfim12_closed_form(block):
         assert info["explicit_residual"] < 1e-5
 
 
-def test_block_vs_oracle_xxz():
+@pytest.mark.parametrize("block", [8, 16])
+def test_block_vs_oracle_xxz(block):
+    """FP64 within 1e-10 of the oracle's energy, FP32 SpMM within 1e-5."""
     keys = c2_keys(20_000)
     tl = wl.xxz_grid_6x6()
     H = _ham(keys, tl)
     e_o = _oracle_e0(keys, tl)
-    e, _, info = H.lanczos(max_iter=80, tol=1e-11, block=8, v0="min_diag")
-    say("block xxz20k", e, e_o, info)
+    steps = 80 if block == 8 else 40
+    e, _, info = H.lanczos(max_iter=steps, tol=1e-11, block=block, v0="min_diag")
+    e32, _, info32 = H.lanczos(max_iter=steps, tol=1e-7, block=block, spmv_dtype="f32", v0="min_diag")
+    say("block", block, "xxz20k", e, e32, e_o, info["iterations"], info32["iterations"])
     assert abs(e - e_o) / abs(e_o) < 1e-10
+    assert abs(e32 - e_o) / abs(e_o) < 1e-5
 
 
-def test_block_heavy_hex_four_words():
+@pytest.mark.parametrize("block", [8, 16])
+def test_block_heavy_hex_four_words(block):
+    """200 qubits (four key words): single-vector and block Lanczos within 1e-10 of the oracle's
+    energy in FP64, block with FP32 SpMM within 1e-5."""
     tl, keys = heavy_hex_small(20_000)
     H = _ham(keys, tl)
     e_o = _oracle_e0(keys, tl)
+    steps = 80 if block == 8 else 40
     e1, _, i1 = H.lanczos(tol=1e-11, max_iter=600)
-    e8, _, i8 = H.lanczos(max_iter=80, tol=1e-11, block=8)
-    say("heavy-hex 20k: oracle", e_o, "single", e1, i1["iterations"], "block", e8, i8["iterations"])
-    assert abs(e8 - e_o) / abs(e_o) < 1e-10
+    eb, _, ib = H.lanczos(max_iter=steps, tol=1e-11, block=block)
+    eb32, _, _ = H.lanczos(max_iter=steps, tol=1e-7, block=block, spmv_dtype="f32")
+    say("heavy-hex 20k: oracle", e_o, "single", e1, i1["iterations"], "block", block, eb, ib["iterations"], eb32)
+    assert abs(eb - e_o) / abs(e_o) < 1e-10
     assert abs(e1 - e_o) / abs(e_o) < 1e-10
+    assert abs(eb32 - e_o) / abs(e_o) < 1e-5
 
 
 def test_block_f32_spmm():
@@ -102,8 +113,8 @@ def test_block_invariant_subspace():
     and T is exact."""
     tl = wl.TermList.from_terms(12, [(1.0, [(0, 0)]), (0.5, [])])
     H = _ham(wl.full_space(12), tl)
-    for block in (4, 8):
-        e, _, info = H.lanczos(max_iter=40, tol=1e-12, block=block, check_every=1)
+    for block in (4, 8, 16):
+        e, _, info = H.lanczos(max_iter=24, tol=1e-12, block=block, check_every=1)
         say("invariant", block, e, info)
         assert info["converged"] and info["ritz_residual"] == 0.0 and info["iterations"] == 2
         assert abs(e + 0.5) < 1e-13
@@ -116,6 +127,8 @@ def test_block_errors():
         H.lanczos(block=3)
     with pytest.raises(qsd.QsdError, match="INVALID_ARG"):
         H.lanczos(block=8, max_iter=81)
+    with pytest.raises(qsd.QsdError, match="INVALID_ARG"):
+        H.lanczos(block=16, max_iter=41)
     tiny = _ham(wl.full_space(3), wl.tfim_chain(3, 1.0, 1.0, True))  # 8 strings < 2 blocks of 8
     with pytest.raises(qsd.QsdError, match="INVALID_ARG"):
         tiny.lanczos(block=8)

@@ -170,6 +170,10 @@ def test_matvec_exact_dyadic(case):
     np.testing.assert_array_equal(Y, Y_o)
     Y1 = np.stack([H.matvec(torch.from_numpy(np.ascontiguousarray(X[:, v])).cuda()).cpu().numpy() for v in range(8)], 1)
     np.testing.assert_array_equal(Y, Y1)
+    # the widest SpMM kernels: 12 and 16 interleaved vectors
+    for nv in (12, 16):
+        X = dyadic_vector(rng, sub.N, nvec=nv)
+        np.testing.assert_array_equal(H.matvec(torch.from_numpy(X).cuda()).cpu().numpy(), orw.matvec_c(ck, tl, X).real)
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
@@ -306,26 +310,77 @@ def test_c2_full_sampled_rows():
 
 
 def test_c3_full_sampled_rows():
+    """The 2.25M-determinant fermionic workload, 400 sampled rows, in the default launch and in
+    the one bench.py times (part filters split at the first beta qubit, load 1/32, filter-first
+    schedule; also the slot-order lockstep schedule under filters).  FP64 with 20-bit dyadic
+    coefficients is exact; FP32 elements and vectors with 16-bit dyadic coefficients give the
+    exact value rounded once (every element and every partial sum fits FP32 / FP64 exactly)."""
     ops, keys = c3_parts(1500, 1500)
     tl = dyadic(ops)
+    tl16 = dyadic(ops, bits=16)
     say("c3 full 1500x1500")
     sub, op, H = _ham(keys, tl)
+    H16 = qsd.SubspaceHamiltonian(sub, qsd.operator_from_termlist(tl16))
     assert sub.N == 2_250_000
     ck_o = osub.canonical_keys(keys)
     rng = np.random.default_rng(9)
     rows = np.sort(rng.choice(sub.N, size=400, replace=False))
+    rows[0], rows[-1] = 0, sub.N - 1
     x = dyadic_vector(rng, sub.N)
-    H.schedule = qsd.SCHED_FILTER_FIRST  # the autotuner's choice on this workload (load 1/8)
-    y = H.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    xd, x32 = torch.from_numpy(x).cuda(), torch.from_numpy(x.astype(np.float32)).cuda()
     y_o = orw.matvec_c(ck_o, tl, x, rows).real
-    np.testing.assert_array_equal(y[rows], y_o)
-    x32 = x.astype(np.float32)
-    y32 = H.matvec(torch.from_numpy(x32).cuda()).cpu().numpy()
-    rel = np.abs(y32[rows] - y_o) / (np.abs(y_o) + 1e-30)
-    say("c3 fp32 max rel err", float(np.median(rel)), float(rel.max()))
+    y16_o = orw.matvec_c(ck_o, tl16, x, rows).real.astype(np.float32)
+    launches = [(0.125, 0, qsd.SCHED_FILTER_FIRST), (1 / 32, 16, qsd.SCHED_FILTER_FIRST), (1 / 32, 16, qsd.SCHED_ALL)]
+    for load, split, sched in launches:
+        say("c3 launch", load, split, sched)
+        sub.rehash(load, split)
+        H.schedule = H16.schedule = sched
+        np.testing.assert_array_equal(H.matvec(xd).cpu().numpy()[rows], y_o)
+        np.testing.assert_array_equal(H16.matvec(x32).cpu().numpy()[rows], y16_o)
+
+
+def test_c3_full_csr_sampled_rows():
+    """CSR of the full fermionic workload (1.74e9 entries, int32 columns): the two-pass build
+    under part filters and the stored lower-triangle (mirrored) matrix, 300 sampled rows against
+    the oracle's rows: structure exact, dyadic values exact."""
+    ops, keys = c3_parts(1500, 1500)
+    tl = dyadic(ops)
+    say("c3 full CSR")
+    sub, op, H = _ham(keys, tl)
+    ck_o = osub.canonical_keys(keys)
+    rng = np.random.default_rng(19)
+    rows = np.sort(rng.choice(sub.N, size=300, replace=False))
+    ipo, co, vo = orw.rows_c(ck_o, tl, rows)
+    rows_t = torch.from_numpy(rows).cuda()
+
+    def check(ip, ix, dv, label):
+        a, b = ip[rows_t].cpu().numpy(), ip[rows_t + 1].cpu().numpy()
+        for k in range(len(rows)):
+            np.testing.assert_array_equal(ix[a[k]:b[k]].cpu().numpy().astype(np.int64), co[ipo[k]:ipo[k + 1]],
+                                          err_msg=label)
+            np.testing.assert_array_equal(dv[a[k]:b[k]].cpu().numpy(), vo[ipo[k]:ipo[k + 1]].real, err_msg=label)
+
+    sub.rehash(1 / 32, 16)
+    ip, ix, dv = H.to_csr(qsd.INDEX_I32)
+    assert int(ip[-1]) == 1_738_419_792
+    check(ip, ix, dv, "two-pass")
+    del ip, ix, dv
+    torch.cuda.empty_cache()
+    A = qsd.CsrMatrix(H, qsd.INDEX_I32, lower_mirror=True)
+    assert A.nnz == 1_738_419_792
+    ip, ix, dv = A.export()
+    del A
+    check(ip, ix, dv, "lower-triangle")
+    del ip, ix, dv
+    torch.cuda.empty_cache()
 
 
 def test_c4_full_sampled_rows():
+    """The 5M-string 200-qubit heavy-hex workload (four key words), 5000 sampled rows: FP64
+    8-vector SpMM and single vector, and FP32 (the coefficients 2 and 0.5 and 10-bit dyadic
+    vectors are exact in FP32: the result is the exact value rounded once), in the default
+    launch and in the launches the autotuner picks for it (load 1/32, slot order + lockstep +
+    filter first, with and without the XCD remap)."""
     tl, keys = heavy_hex_small(5_000_000)
     say("c4 full 5M")
     tld = dyadic(tl)
@@ -336,15 +391,17 @@ def test_c4_full_sampled_rows():
     rows = np.sort(rng.choice(sub.N, size=5000, replace=False))
     X = dyadic_vector(rng, sub.N, nvec=8)
     Y_o = orw.matvec_c(ck_o, tld, X, rows).real
-    Y = H.matvec(torch.from_numpy(X).cuda()).cpu().numpy()
+    Xd, X32 = torch.from_numpy(X).cuda(), torch.from_numpy(X.astype(np.float32)).cuda()
+    x1, x132 = Xd[:, 0].contiguous(), X32[:, 0].contiguous()
+    Y = H.matvec(Xd).cpu().numpy()
     np.testing.assert_array_equal(Y[rows], Y_o)
-    # the launch bench.py times: load 1/32, slot order, lockstep, filter first, XCD remap
-    sub.rehash(1 / 32)
-    H.schedule = qsd.SCHED_ALL
-    Y15 = H.matvec(torch.from_numpy(X).cuda()).cpu().numpy()
-    np.testing.assert_array_equal(Y15, Y)
-    y1 = H.matvec(torch.from_numpy(np.ascontiguousarray(X[:, 0])).cuda()).cpu().numpy()
-    np.testing.assert_array_equal(y1[rows], Y_o[:, 0])
+    for sched in (qsd.SCHED_ALL, qsd.SCHED_ALL & ~qsd.SCHED_XCD_REMAP):
+        sub.rehash(1 / 32)
+        H.schedule = sched
+        np.testing.assert_array_equal(H.matvec(Xd).cpu().numpy(), Y)
+        np.testing.assert_array_equal(H.matvec(x1).cpu().numpy()[rows], Y_o[:, 0])
+        np.testing.assert_array_equal(H.matvec(X32).cpu().numpy()[rows], Y_o.astype(np.float32))
+        np.testing.assert_array_equal(H.matvec(x132).cpu().numpy()[rows], Y_o[:, 0].astype(np.float32))
 
 
 # ---------------------------------------------------------------------------- Lanczos

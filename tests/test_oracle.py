@@ -290,6 +290,37 @@ def test_commuting_two_body_molecular_terms():
     assert abs(e - ocf.commuting_two_body_e0_spin(eps, lam, na, nb)) < 1e-11
 
 
+def test_commuting_two_body_spinless():
+    """Spinless commuting parts: ``sum h_pq f+_p f_q + 1/2 sum (pq|rs) f+_p f+_r f_s f_q`` with
+    ``h = V diag(eps) V^T`` and ``(pq|rs) = u_pq u_rs``, ``u = V diag(lam) V^T``, restricted to
+    N particles by the oracle's direct action: its lowest eigenvalue is the closed form's minimum
+    over occupations of the columns of V."""
+    rng = np.random.default_rng(19)
+    n, N = 6, 3
+    V, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    eps = rng.normal(size=n)
+    lam = rng.normal(size=n)
+    h = V @ np.diag(eps) @ V.T
+    u = V @ np.diag(lam) @ V.T
+    terms = [(h[p, q], [(p, 6), (q, 5)]) for p in range(n) for q in range(n)]
+    terms += [(0.5 * u[p, q] * u[r, s_], [(p, 6), (r, 6), (s_, 5), (q, 5)])
+              for p in range(n) for q in range(n) for r in range(n) for s_ in range(n)]
+    sector = [v for v in range(1 << n) if bin(v).count("1") == N]
+    M = np.zeros((len(sector), len(sector)), dtype=complex)
+    for i, row in enumerate(orw.rows_python(sector, terms, True)):
+        for j, v in row:
+            M[i, j] = v
+    np.testing.assert_allclose(M, M.conj().T, atol=1e-12)
+    e = np.linalg.eigvalsh(M)
+    assert abs(e[0] - ocf.commuting_two_body_e0(eps, lam, N)) < 1e-11
+    # every occupation is an eigenvalue: the closed form reproduces the whole spectrum
+    from itertools import combinations
+
+    spec = sorted(sum(eps[k] for k in occ) + sum(lam[a] * lam[b] for a, b in combinations(occ, 2))
+                  for occ in combinations(range(n), N))
+    np.testing.assert_allclose(e, spec, atol=1e-11)
+
+
 # ---------------------------------------------------------------------------- Lanczos
 
 def test_oracle_lanczos_tfim12():
