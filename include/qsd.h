@@ -348,6 +348,23 @@ int qsd_matvec(const qsd_ham *h, int32_t nvec, const void *d_x, int64_t ldx, voi
 int qsd_matvec_batched(int32_t n, const qsd_ham *const *hams, const void *const *xs, void *const *ys,
                        const int32_t *nvecs, int32_t dtype, void *stream);
 
+/* qsd_matvec_batched_noalloc - for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): qsd_matvec_batched with
+ * the same arguments, kernels and results (bitwise), but its request and tile tables go to a
+ * fixed device array of the library (under 1 MiB) instead of stream-ordered memory.  The call makes no
+ * hipMalloc, hipFree, hipMallocAsync or allocator call.  Limits: at most
+ * QSD_NOALLOC_MAX_REQUESTS request chunks (one per request and launch: a real request of up to 16
+ * vectors is one chunk, a complex request one per four vectors) and QSD_NOALLOC_MAX_TILES row
+ * tiles of 256 rows in total; beyond either it returns CAPACITY before touching the GPU.
+ * Each GPU holds its own array until the process ends, and every call on that GPU shares it:
+ * calls that overlap on one GPU (different streams or host threads without ordering between
+ * them) race on the tables.  Calls in order on one stream are safe; the array keeps the last
+ * call's tables, and each call rewrites all it reads before its kernels start. */
+#define QSD_NOALLOC_MAX_REQUESTS 256
+#define QSD_NOALLOC_MAX_TILES 65536
+int qsd_matvec_batched_noalloc(int32_t n, const qsd_ham *const *hams, const void *const *xs, void *const *ys,
+                               const int32_t *nvecs, int32_t dtype, void *stream);
+
 /* ============================================================================= CSR
  *
  * qsd_csr_build - Methods, Matrix evaluation (two-pass CSR).

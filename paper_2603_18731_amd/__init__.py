@@ -31,6 +31,7 @@ SCHED_XCD_REMAP, SCHED_SLOT_ORDER, SCHED_LOCKSTEP, SCHED_FILTER_FIRST = 1, 2, 4,
 SCHED_ALL = 15
 TUNE_SCHEDULE, TUNE_LOAD, TUNE_SPLIT = 1, 2, 4
 CSR_LOWER_MIRROR = 1
+NOALLOC_MAX_REQUESTS, NOALLOC_MAX_TILES = 256, 65536  # limits of qsd_matvec_batched_noalloc
 ERR_NAMES = {-1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "HIP", -4: "CAPACITY", -5: "NOT_HERMITIAN",
              -6: "NOT_CONVERGED", -7: "DTYPE", -8: "UNSUPPORTED"}
 
@@ -40,7 +41,8 @@ EXPORTED = [
     "qsd_op_compile", "qsd_op_info", "qsd_op_export", "qsd_op_destroy", "qsd_ham_create", "qsd_ham_diagonal",
     "qsd_ham_destroy", "qsd_ham_info", "qsd_ham_work_counts", "qsd_matvec", "qsd_csr_build", "qsd_lanczos_default_opts", "qsd_lanczos",
     "qsd_batch_create", "qsd_batch_footprint", "qsd_batch_add", "qsd_batch_step",
-    "qsd_batch_poll", "qsd_batch_remove", "qsd_batch_destroy", "qsd_matvec_batched", "qsd_block_lanczos",
+    "qsd_batch_poll", "qsd_batch_remove", "qsd_batch_destroy", "qsd_matvec_batched", "qsd_matvec_batched_noalloc",
+    "qsd_block_lanczos",
     "qsd_ham_set_schedule", "qsd_ham_get_schedule", "qsd_ham_autotune", "qsd_subspace_rehash",
     "qsd_csr_create", "qsd_csr_info", "qsd_csr_export", "qsd_csr_matvec", "qsd_csr_lanczos", "qsd_csr_block_lanczos",
     "qsd_csr_destroy", "qsd_subspace_select", "qsd_ramps",
@@ -181,6 +183,7 @@ def lib():
         "qsd_batch_footprint": ([P, I32, I32, P], ctypes.c_int),
         "qsd_batch_add": ([P, P, I32, ctypes.c_uint64, D, P, I64, P, P], ctypes.c_int),
         "qsd_matvec_batched": ([I32, P, P, P, P, I32, P], ctypes.c_int),
+        "qsd_matvec_batched_noalloc": ([I32, P, P, P, P, I32, P], ctypes.c_int),
         "qsd_ham_set_schedule": ([P, U32], ctypes.c_int),
         "qsd_ham_get_schedule": ([P, P], ctypes.c_int),
         "qsd_ham_autotune": ([P, I32, I32, I32, U32, P, P], ctypes.c_int),
@@ -650,10 +653,7 @@ def torch_empty_like(x):
     return torch.empty_like(x)
 
 
-def matvec_batched(hams, xs, ys=None, stream=None):
-    """``ys[i] = hams[i] @ xs[i]`` for every request in one launch per key width
-    (``qsd_matvec_batched``); vectors are ``[N]`` or ``[N][nvec]`` contiguous device tensors of
-    one dtype."""
+def _matvec_batched(entry, hams, xs, ys, stream):
     import torch
 
     n = len(hams)
@@ -669,9 +669,26 @@ def matvec_batched(hams, xs, ys=None, stream=None):
     X = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
     Y = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ys])
     nv = np.array([1 if x.dim() == 1 else x.shape[1] for x in xs], dtype=np.int32)
-    _check(lib().qsd_matvec_batched(n, ctypes.cast(H, ctypes.c_void_p), ctypes.cast(X, ctypes.c_void_p),
-                                    ctypes.cast(Y, ctypes.c_void_p), _ptr(nv), code, _stream(stream)))
+    _check(entry(n, ctypes.cast(H, ctypes.c_void_p), ctypes.cast(X, ctypes.c_void_p), ctypes.cast(Y, ctypes.c_void_p),
+                 _ptr(nv), code, _stream(stream)))
     return ys
+
+
+def matvec_batched(hams, xs, ys=None, stream=None):
+    """``ys[i] = hams[i] @ xs[i]`` for every request in one launch per key width
+    (``qsd_matvec_batched``); vectors are ``[N]`` or ``[N][nvec]`` contiguous device tensors of
+    one dtype."""
+    return _matvec_batched(lib().qsd_matvec_batched, hams, xs, ys, stream)
+
+
+def matvec_batched_noalloc(hams, xs, ys, stream=None):
+    """``matvec_batched`` through ``qsd_matvec_batched_noalloc``: the library allocates nothing
+    (its tables live in a fixed per-GPU device array), so ``ys`` must be given.  At most
+    ``NOALLOC_MAX_REQUESTS`` request chunks and ``NOALLOC_MAX_TILES`` row tiles of 256 rows;
+    calls that overlap on one GPU race on the shared array."""
+    if ys is None:
+        raise ValueError("matvec_batched_noalloc writes into caller-provided ys")
+    return _matvec_batched(lib().qsd_matvec_batched_noalloc, hams, xs, ys, stream)
 
 
 class LanczosBatch:

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -768,9 +769,22 @@ void launch_bmv_w(int Wp, int nv_max, int tiles, const MvReq *reqs, const Tile *
 
 }  // namespace
 
-extern "C" int qsd_matvec_batched(int32_t n, const qsd_ham *const *hams, const void *const *xs, void *const *ys,
-                                  const int32_t *nvecs, int32_t dtype, void *stream) {
-    clear_error();
+namespace {
+
+// The plan of a batched SpMV: request table, tile list (request, row tile) and one launch per
+// (key width, vector chunk); complex vectors go in chunks of four.
+struct BatchedPlan {
+    struct Launch {
+        int Wp, nv_max;
+        size_t t0, nt;
+    };
+    std::vector<MvReq> reqs;
+    std::vector<Tile> tiles;
+    std::vector<Launch> launches;
+};
+
+int plan_batched(int32_t n, const qsd_ham *const *hams, const void *const *xs, void *const *ys, const int32_t *nvecs,
+                 int32_t dtype, BatchedPlan &P) {
     if (n < 0 || (n > 0 && (!hams || !xs || !ys || !nvecs))) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
     if (dtype < QSD_F64 || dtype > QSD_C64) return fail(QSD_ERR_INVALID_ARG, "unknown dtype %d", dtype);
     const bool cplx = dtype == QSD_C128 || dtype == QSD_C64;
@@ -783,19 +797,10 @@ extern "C" int qsd_matvec_batched(int32_t n, const qsd_ham *const *hams, const v
             return fail(QSD_ERR_DTYPE, "dtype %d does not match the %s operator of request %d", dtype,
                         hams[i]->is_complex ? "complex" : "real", i);
     }
-    hipStream_t st = (hipStream_t)stream;
-    // One launch per (key width, vector chunk); complex vectors go in chunks of four.
     const int chunk = cplx ? 4 : 16;
-    std::vector<MvReq> reqs;
-    std::vector<Tile> tiles;
-    struct Launch {
-        int Wp, nv_max;
-        size_t t0, nt;
-    };
-    std::vector<Launch> launches;
     for (int Wp : {1, 2, 4, 8, 16}) {
         for (int c0 = 0; c0 < 16; c0 += chunk) {
-            Launch L{Wp, 0, tiles.size(), 0};
+            BatchedPlan::Launch L{Wp, 0, P.tiles.size(), 0};
             for (int i = 0; i < n; ++i) {
                 const qsd_ham *h = hams[i];
                 if (h->Wp != Wp || nvecs[i] <= c0 || h->N == 0) continue;
@@ -810,16 +815,77 @@ extern "C" int qsd_matvec_batched(int32_t n, const qsd_ham *const *hams, const v
                 R.nv = std::min(chunk, nvecs[i] - c0);
                 R.sched = h->schedule;
                 L.nv_max = std::max(L.nv_max, R.nv);
-                const int slot = (int)reqs.size();
-                reqs.push_back(R);
-                for (int64_t t = 0; t < (h->N + kBlock - 1) / kBlock; ++t) tiles.push_back({slot, (int)t});
+                const int slot = (int)P.reqs.size();
+                P.reqs.push_back(R);
+                for (int64_t t = 0; t < (h->N + kBlock - 1) / kBlock; ++t) P.tiles.push_back({slot, (int)t});
             }
-            L.nt = tiles.size() - L.t0;
-            if (L.nt > 0) launches.push_back(L);
+            L.nt = P.tiles.size() - L.t0;
+            if (L.nt > 0) P.launches.push_back(L);
         }
     }
-    if (launches.empty()) return QSD_OK;
-    if (tiles.size() > (size_t)INT32_MAX) return fail(QSD_ERR_CAPACITY, "too many row tiles");
+    if (P.tiles.size() > (size_t)INT32_MAX) return fail(QSD_ERR_CAPACITY, "too many row tiles");
+    return QSD_OK;
+}
+
+// Uploads the plan's tables to d_reqs / d_tiles and enqueues its launches on st.
+int run_batched(const BatchedPlan &P, int32_t dtype, MvReq *d_reqs, Tile *d_tiles, hipStream_t st) {
+    // pageable sources: the copies return once the host data is staged
+    if (hipMemcpyAsync(d_reqs, P.reqs.data(), P.reqs.size() * sizeof(MvReq), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d_tiles, P.tiles.data(), P.tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, st) != hipSuccess)
+        return fail(QSD_ERR_HIP, "table upload failed");
+    for (const auto &L : P.launches) {
+        const Tile *tl = d_tiles + L.t0;
+        switch (dtype) {
+            case QSD_F64: launch_bmv_w<double, false>(L.Wp, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
+            case QSD_F32: launch_bmv_w<float, false>(L.Wp, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
+            case QSD_C128: launch_bmv_w<double, true>(L.Wp, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
+            case QSD_C64: launch_bmv_w<float, true>(L.Wp, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
+        }
+    }
+    if (hipGetLastError() != hipSuccess) return fail(QSD_ERR_HIP, "batched matvec launch failed");
+    return QSD_OK;
+}
+
+// Fixed device scratch of qsd_matvec_batched_noalloc: the request table, then the tile list.
+// Every GPU the library runs on holds one until the process ends.  In host code the name is only
+// a symbol: its device address comes from hipGetSymbolAddress, once per device.
+constexpr int kScratchReqs = QSD_NOALLOC_MAX_REQUESTS;
+constexpr size_t kScratchTiles = QSD_NOALLOC_MAX_TILES;
+constexpr size_t kScratchTileOff = (kScratchReqs * sizeof(MvReq) + 255) / 256 * 256;
+constexpr size_t kScratchBytes = kScratchTileOff + kScratchTiles * sizeof(Tile);
+static_assert(kScratchBytes <= (size_t(1) << 20), "the fixed scratch stays under 1 MiB");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (resolved at the device's first call).
+int scratch_address(void **out) {
+    int dev = -1;
+    QSD_CHECK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(QSD_ERR_UNSUPPORTED, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(QSD_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return QSD_OK;
+}
+
+}  // namespace
+
+extern "C" int qsd_matvec_batched(int32_t n, const qsd_ham *const *hams, const void *const *xs, void *const *ys,
+                                  const int32_t *nvecs, int32_t dtype, void *stream) {
+    clear_error();
+    BatchedPlan P;
+    QSD_TRY(plan_batched(n, hams, xs, ys, nvecs, dtype, P));
+    if (P.launches.empty()) return QSD_OK;
+    hipStream_t st = (hipStream_t)stream;
     // Stream-ordered tables: allocated, filled, used and released in order on `stream`, by the
     // first operator's allocator (stream-ordered by contract) or hipMallocAsync.
     AllocScope scope(&hams[0]->alloc, stream);
@@ -827,35 +893,19 @@ extern "C" int qsd_matvec_batched(int32_t n, const qsd_ham *const *hams, const v
     MvReq *d_reqs = nullptr;
     Tile *d_tiles = nullptr;
     if (own_alloc) {
-        QSD_TRY(dev_alloc(&d_reqs, reqs.size()));
-        if (dev_alloc(&d_tiles, tiles.size()) != QSD_OK) {
+        QSD_TRY(dev_alloc(&d_reqs, P.reqs.size()));
+        if (dev_alloc(&d_tiles, P.tiles.size()) != QSD_OK) {
             dev_free(d_reqs);
             return QSD_ERR_OUT_OF_MEMORY;
         }
     } else {
-        QSD_CHECK_HIP(hipMallocAsync((void **)&d_reqs, reqs.size() * sizeof(MvReq), st));
-        if (hipMallocAsync((void **)&d_tiles, tiles.size() * sizeof(Tile), st) != hipSuccess) {
+        QSD_CHECK_HIP(hipMallocAsync((void **)&d_reqs, P.reqs.size() * sizeof(MvReq), st));
+        if (hipMallocAsync((void **)&d_tiles, P.tiles.size() * sizeof(Tile), st) != hipSuccess) {
             (void)hipFreeAsync(d_reqs, st);
             return fail(QSD_ERR_OUT_OF_MEMORY, "tile table allocation failed");
         }
     }
-    int rc = QSD_OK;
-    // pageable sources: the copies return once the host data is staged
-    if (hipMemcpyAsync(d_reqs, reqs.data(), reqs.size() * sizeof(MvReq), hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, st) != hipSuccess)
-        rc = fail(QSD_ERR_HIP, "table upload failed");
-    if (rc == QSD_OK) {
-        for (const auto &L : launches) {
-            const Tile *tl = d_tiles + L.t0;
-            switch (dtype) {
-                case QSD_F64: launch_bmv_w<double, false>(L.Wp, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
-                case QSD_F32: launch_bmv_w<float, false>(L.Wp, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
-                case QSD_C128: launch_bmv_w<double, true>(L.Wp, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
-                case QSD_C64: launch_bmv_w<float, true>(L.Wp, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
-            }
-        }
-        if (hipGetLastError() != hipSuccess) rc = fail(QSD_ERR_HIP, "batched matvec launch failed");
-    }
+    const int rc = run_batched(P, dtype, d_reqs, d_tiles, st);
     if (own_alloc) {
         dev_free(d_tiles);
         dev_free(d_reqs);
@@ -864,4 +914,24 @@ extern "C" int qsd_matvec_batched(int32_t n, const qsd_ham *const *hams, const v
         (void)hipFreeAsync(d_reqs, st);
     }
     return rc;
+}
+
+extern "C" int qsd_matvec_batched_noalloc(int32_t n, const qsd_ham *const *hams, const void *const *xs,
+                                          void *const *ys, const int32_t *nvecs, int32_t dtype, void *stream) {
+    clear_error();
+    BatchedPlan P;
+    QSD_TRY(plan_batched(n, hams, xs, ys, nvecs, dtype, P));
+    if (P.launches.empty()) return QSD_OK;
+    if (P.reqs.size() > (size_t)kScratchReqs)
+        return fail(QSD_ERR_CAPACITY, "%zu request chunks exceed the %d the fixed scratch holds", P.reqs.size(),
+                    kScratchReqs);
+    if (P.tiles.size() > kScratchTiles)
+        return fail(QSD_ERR_CAPACITY, "%zu row tiles exceed the %zu the fixed scratch holds", P.tiles.size(),
+                    (size_t)kScratchTiles);
+    void *base = nullptr;
+    QSD_TRY(scratch_address(&base));
+    MvReq *d_reqs = (MvReq *)base;
+    Tile *d_tiles = (Tile *)((unsigned char *)base + kScratchTileOff);
+    // nothing in the scratch must start at zero: the call uploads its whole table first
+    return run_batched(P, dtype, d_reqs, d_tiles, (hipStream_t)stream);
 }
