@@ -217,20 +217,39 @@ def serve_bench(args):
     tol = 1e-10 if args.dtype == "f64" else 1e-7
     max_iter = 300
 
-    # FIFO baseline: plain FP64 single-vector Lanczos, one request at a time
-    service = np.zeros(n)
-    e_fifo = np.zeros(n)
-    iters_fifo = np.zeros(n, dtype=np.int64)
-    for i, H in enumerate(hams):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        e, _, info = H.lanczos(tol=1e-10, max_iter=max_iter, v0="uniform", raise_on_nonconv=False)
-        service[i] = time.perf_counter() - t0
-        e_fifo[i], iters_fifo[i] = e, info["iterations"]
-        if (i + 1) % 32 == 0:
-            print("# fifo %d/%d solved (%.1f s of service so far)" % (i + 1, n, service.sum()), file=sys.stderr,
-                  flush=True)
+    # FIFO baselines, one request at a time: the plain FP64 single-vector matrix-free Lanczos, and
+    # (with stored-CSR serving) the same solver on the CSR matrix, built inside the request's
+    # service time, for every request the server would serve from CSR
+    def fifo_solve(i, use_csr):
+        H = hams[i]
+        if use_csr and csr_min is not None and H.N >= csr_min:
+            A = qsd.CsrMatrix(H, qsd.INDEX_I32, lower_mirror=True)
+            r = A.lanczos(tol=1e-10, max_iter=max_iter, v0="uniform", raise_on_nonconv=False)
+            del A
+            return r
+        return H.lanczos(tol=1e-10, max_iter=max_iter, v0="uniform", raise_on_nonconv=False)
+
+    def fifo_service(use_csr, label):
+        service = np.zeros(n)
+        e_fifo = np.zeros(n)
+        iters = np.zeros(n, dtype=np.int64)
+        for i in range(n):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, _, info = fifo_solve(i, use_csr)
+            torch.cuda.synchronize()
+            service[i] = time.perf_counter() - t0
+            e_fifo[i], iters[i] = e, info["iterations"]
+            if (i + 1) % 64 == 0:
+                print("# fifo %s %d/%d solved (%.1f s of service so far)" % (label, i + 1, n, service.sum()),
+                      file=sys.stderr, flush=True)
+        return service, e_fifo, iters
+
+    service, e_fifo, iters_fifo = fifo_service(False, "matrix-free")
     mu_fifo = n / service.sum()
+    service_csr = None
+    if csr_min is not None:
+        service_csr, e_fifo_csr, _ = fifo_service(True, "csr")
 
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.85 * free)
@@ -258,10 +277,30 @@ def serve_bench(args):
     fifo_closed_lat = serve.fifo_latencies(np.zeros(n), service)
     out_open = {}
     fifo_open = {}
+    fifo_csr = None
+    if service_csr is not None:
+        fifo_csr = {"solves_per_s": n / service_csr.sum(), "service_s_total": float(service_csr.sum()),
+                    "closed_loop": serve.percentiles(serve.fifo_latencies(np.zeros(n), service_csr)),
+                    "energy_max_rel_diff_vs_matrix_free": float(np.max(np.abs(e_fifo_csr - e_fifo) / np.abs(e_fifo)))}
+    arrivals = {}
     for f in (0.7, 0.9):
         arr = serve.poisson_arrivals(n, f * mu, seed=5 + int(f * 10))
+        arrivals[f] = arr
         out_open["lambda_%.1f_mu" % f] = dict(run(arr, "open loop %.1f mu" % f), rate_per_s=f * mu)
         fifo_open["lambda_%.1f_mu" % f] = serve.percentiles(serve.fifo_latencies(arr, service))
+        if fifo_csr is not None:
+            fifo_csr["lambda_%.1f_mu" % f] = serve.percentiles(serve.fifo_latencies(arr, service_csr))
+    # one FIFO open-loop pass run for real (the like-for-like baseline: from stored CSR when the
+    # server uses it), beside the latencies its measured service times predict
+    real_csr = fifo_csr is not None
+    arr = arrivals[0.9]
+    print("# real FIFO pass (%s) at 0.9 mu arrivals" % ("csr" if real_csr else "matrix-free"), file=sys.stderr,
+          flush=True)
+    lat_real = serve.fifo_run(arr, lambda i: (fifo_solve(i, real_csr), torch.cuda.synchronize()))
+    fifo_real = {"baseline": "csr" if real_csr else "matrix_free", "arrivals": "lambda_0.9_mu",
+                 **serve.percentiles(lat_real),
+                 "predicted": serve.percentiles(serve.fifo_latencies(arr, service_csr if real_csr else service))}
+    print("# real FIFO pass: %s" % json.dumps(fifo_real), file=sys.stderr, flush=True)
     out = {
         "metric": "serve p50/p99 ms; solves/s",
         "value": mu,
@@ -282,7 +321,10 @@ def serve_bench(args):
         "fifo_fp64_single_vector": {"solves_per_s": mu_fifo, "service_s_total": float(service.sum()),
                                     "closed_loop": serve.percentiles(fifo_closed_lat), **fifo_open,
                                     "iterations_mean": float(iters_fifo.mean())},
+        "fifo_run_for_real": fifo_real,
     }
+    if fifo_csr is not None:
+        out["fifo_fp64_single_vector_csr"] = fifo_csr
     print(json.dumps(out), flush=True)
 
 

@@ -13,12 +13,15 @@ The host loop never blocks on a running lane: each lane's steps end with an even
 is polled (convergence test, retire, admit) only once its event has completed.
 
 Optionally (``csr_min_rows``) a request of at least that many rows whose stored-matrix size is
-known (``Request.nnz``) is served from its CSR matrix, built when it is admitted (lower
-triangle, mirrored) and freed when it finishes: the matrix and the build's transient scratch
-count against the HBM budget, and its SpMV then streams the matrix instead of re-evaluating it.
+known (``Request.nnz``) is served from its CSR matrix (lower triangle, mirrored), freed when it
+finishes: the matrix and the build's transient scratch count against the HBM budget, and its
+SpMV then streams the matrix instead of re-evaluating it.  The build runs on a worker thread and
+a stream of its own (it synchronizes once, to size the matrix), so the host loop keeps polling
+and stepping every lane meanwhile; the request joins its lane's batch once its matrix is built.
 """
 import math
 import time
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import List, Optional
 
@@ -46,6 +49,7 @@ class Request:
     nnz: int = 0  # stored entries of H on the subspace, when known (enables CSR serving)
     csr: Optional[object] = None
     used_csr: bool = False
+    build_s: float = 0.0  # seconds of its CSR build (worker thread)
 
     @property
     def latency(self) -> float:
@@ -58,6 +62,7 @@ class _Lane:
     stream: object
     active: dict = field(default_factory=dict)  # slot -> Request
     event: Optional[object] = None
+    building: list = field(default_factory=list)  # [(Request, future, reserved bytes)]
 
 
 class Server:
@@ -86,6 +91,9 @@ class Server:
         self.used = 0
         self.peak_used = 0
         self.peak_active = 0
+        self._builder = ThreadPoolExecutor(max_workers=1) if csr_min_rows is not None else None
+        self._build_stream = torch.cuda.Stream() if csr_min_rows is not None else None
+        self.steps_during_builds = 0  # lane steps enqueued while some CSR build was running
 
     def lane_of(self, req: Request) -> int:
         for i, b in enumerate(self.bounds):
@@ -100,31 +108,58 @@ class Server:
         return (self.csr_min_rows is not None and req.nnz > 0 and req.ham.N >= self.csr_min_rows
                 and not req.ham.is_complex)
 
-    def _admit(self, lane: _Lane, li: int, req: Request, now: float) -> bool:
+    def _build_csr(self, req: Request):
         import torch
 
-        fp = lane.batch.footprint(req.ham)
-        if len(lane.active) >= lane.batch.max_requests:
-            return False
-        use_csr = self._wants_csr(req)
-        need = fp + (self.BUILD_BYTES_PER_NNZ * req.nnz + 8 * (req.ham.N + 1) if use_csr else 0)
-        if self.used + need > self.budget:
-            return False
-        op = req.ham
-        if use_csr:
-            dt = torch.float32 if self.spmv_dtype == "f32" else torch.float64
-            req.csr = CsrMatrix(req.ham, INDEX_I32, dtype=dt, lower_mirror=True, stream=lane.stream)
-            fp += req.csr.bytes
-            op = req.csr
-            req.used_csr = True
+        dt = torch.float32 if self.spmv_dtype == "f32" else torch.float64
+        t0 = time.perf_counter()
+        csr = CsrMatrix(req.ham, INDEX_I32, dtype=dt, lower_mirror=True, stream=self._build_stream)
+        self._build_stream.synchronize()
+        req.build_s = time.perf_counter() - t0
+        return csr
+
+    def _join(self, lane: _Lane, li: int, req: Request, op, fp: int, now: float):
+        import torch
+
         with torch.cuda.stream(lane.stream):
             ws = torch.empty(lane.batch.footprint(req.ham), dtype=torch.uint8, device="cuda")
         slot = lane.batch.add(op, v0=req.v0, seed=req.seed, tol=req.tol, workspace=ws, stream=lane.stream)
         req.admitted, req.footprint, req.lane = now, fp, li
         lane.active[slot] = req
-        self.used += fp
+
+    def _admit(self, lane: _Lane, li: int, req: Request, now: float) -> bool:
+        """Admits ``req`` into ``lane`` if a slot and its bytes are free; a CSR request starts its
+        build instead and joins the batch when the build is done (``_finish_builds``)."""
+        fp = lane.batch.footprint(req.ham)
+        if len(lane.active) + len(lane.building) >= lane.batch.max_requests:
+            return False
+        use_csr = self._wants_csr(req)
+        need = fp + (self.BUILD_BYTES_PER_NNZ * req.nnz + 8 * (req.ham.N + 1) if use_csr else 0)
+        if self.used + need > self.budget:
+            return False
+        self.used += need
         self.peak_used = max(self.peak_used, self.used)
+        if use_csr:
+            lane.building.append((req, self._builder.submit(self._build_csr, req), need))
+        else:
+            self._join(lane, li, req, req.ham, fp, now)
         return True
+
+    def _finish_builds(self, lane: _Lane, li: int, now: float) -> bool:
+        """Joins the requests of ``lane`` whose CSR build has finished (the lane is idle)."""
+        joined = False
+        for item in list(lane.building):
+            req, fut, reserved = item
+            if not fut.done():
+                continue
+            lane.building.remove(item)
+            req.csr = fut.result()  # a failed build raises here
+            req.used_csr = True
+            fp = lane.batch.footprint(req.ham) + req.csr.bytes
+            self.used += fp - reserved
+            self._join(lane, li, req, req.csr, fp, now)
+            joined = True
+        return joined
 
     def run(self, requests: List[Request], clock=time.perf_counter, progress=None) -> List[Request]:
         """Serves ``requests`` (arrival times relative to the start) to completion in real time;
@@ -167,6 +202,8 @@ class Server:
                             if progress is not None:
                                 progress(len(done))
                 # admissions into this lane happen while it is idle, in arrival order
+                if lane.building and self._finish_builds(lane, li, now):
+                    progressed = True
                 for r in list(waiting):
                     if self.lane_of(r) == li and self._admit(lane, li, r, now):
                         waiting.remove(r)
@@ -176,8 +213,10 @@ class Server:
                     lane.batch.step(self.steps_per_poll, stream=lane.stream)
                     lane.event = torch.cuda.Event()
                     lane.event.record(lane.stream)
+                    if any(not f.done() for l in self.lanes for _, f, _ in l.building):
+                        self.steps_during_builds += 1
             if not progressed:
-                busy = any(l.event is not None for l in self.lanes)
+                busy = any(l.event is not None or l.building for l in self.lanes)
                 if not busy and nxt < len(pending):
                     time.sleep(max(0.0, min(pending[nxt].arrival - (clock() - t0), 0.01)))
                 elif busy:
@@ -194,6 +233,22 @@ def fifo_latencies(arrivals: np.ndarray, service: np.ndarray) -> np.ndarray:
     for i in order:
         t = max(t, arrivals[i]) + service[i]
         lat[i] = t - arrivals[i]
+    return lat
+
+
+def fifo_run(arrivals: np.ndarray, solve, clock=time.perf_counter) -> np.ndarray:
+    """Serves the requests for real, one at a time in arrival order: request i waits for its
+    arrival time and for the previous request to finish, then ``solve(i)`` runs it to completion
+    (it must synchronize).  Returns the latencies in request order."""
+    order = np.argsort(arrivals, kind="stable")
+    lat = np.empty(len(arrivals), dtype=np.float64)
+    t0 = clock()
+    for i in order:
+        wait = arrivals[i] - (clock() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        solve(int(i))
+        lat[i] = clock() - t0 - arrivals[i]
     return lat
 
 

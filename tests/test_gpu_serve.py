@@ -305,3 +305,31 @@ def test_server_csr_mode(hams):
         assert r.used_csr == (hams[n].N >= 3500)
         assert abs(r.energy - singles[n]) / abs(singles[n]) < 1e-10
     assert srv.used == 0 and srv.peak_used <= 4 << 30
+
+
+def test_server_csr_build_does_not_block_other_lanes(hams):
+    """A request served from stored CSR is built on a worker thread and a stream of its own:
+    while the build of a 10^6-row fermionic matrix runs, the host loop keeps stepping the small
+    lane, whose requests finish meanwhile; then the CSR request joins its lane and converges."""
+    from paper_2603_18731_amd import serve
+
+    ops, keys = c3_parts(1000, 1000)
+    big = _ham(keys, ops)
+    _, hcount = big.work_counts()
+    small = ["tfim12", "xxz3k", "xxz20k", "tfim12"]
+    reqs = [serve.Request(0, big, arrival=0.0, nnz=big.N + hcount)]
+    reqs += [serve.Request(i + 1, hams[n], arrival=0.0) for i, n in enumerate(small)]
+    srv = serve.Server(hbm_budget=120 << 30, max_iter=300, lane_bounds=(100_000,), lane_slots=(8, 2),
+                       csr_min_rows=100_000)
+    done = {r.rid: r for r in srv.run(reqs)}
+    rb = done[0]
+    say("csr build %.3f s, big admitted at %.3f s, small finished at" % (rb.build_s, rb.admitted),
+        [round(done[i + 1].finished, 3) for i in range(len(small))], "steps during builds", srv.steps_during_builds)
+    assert rb.used_csr and rb.status == 2
+    assert srv.steps_during_builds > 0
+    assert srv.used == 0
+    e_mf = big.lanczos(tol=1e-10)[0]
+    assert abs(rb.energy - e_mf) / abs(e_mf) < 1e-10
+    for i, n in enumerate(small):
+        r = done[i + 1]
+        assert r.status == 2 and not r.used_csr
