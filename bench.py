@@ -646,7 +646,7 @@ def measure_spmv(w, nvec, dtype_name, steps, warmup, max_load, schedule, split=0
             sub.rehash(max_load, max(split, 0))
         H.schedule = int(schedule)
     sched = H.schedule
-    hsplit, exact = sub.hash_info()
+    hsplit, exact, product = sub.hash_info()
     setup_s = time.perf_counter() - t_setup
     print("# setup %.1f s: N=%d nnz=%d probes=%d hits=%d groups=%d" % (setup_s, N, nnz, probes, hits, op.n_groups),
           file=sys.stderr, flush=True)
@@ -681,7 +681,7 @@ def measure_spmv(w, nvec, dtype_name, steps, warmup, max_load, schedule, split=0
         "config": {"workload": w.name, "n_qubits": w.ops.n_qubits, "subspace_dim": N, "nnz": nnz,
                    "groups": op.n_groups, "terms": op.n_terms, "nvec": nvec, "kernel": "k_matvec",
                    "schedule": sched, "hash_capacity": sub.capacity, "part_filter_split": hsplit,
-                   "exact_slots": exact, "groups_by_mask": bool(order_by_mask),
+                   "exact_slots": exact, "product_map": product, "groups_by_mask": bool(order_by_mask),
                    "autotune": tune},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -127,6 +127,10 @@ int qsd_version(void);
  *             stop at an empty occupancy bit).
  *   alloc     device memory of the handle and of the build's scratch (NULL: hipMalloc).
  *   out       receives the new handle.
+ *   A subspace of 2 to 32 qubits that is the Cartesian product of the distinct strings of its
+ *   lower n_qubits / 2 qubits and those of its upper qubits (an alpha x beta product) is given
+ *   part filters split there and the product map (qsd_subspace_hash_info); otherwise no part
+ *   filters.  qsd_subspace_rehash changes either.
  *   Synchronizes `stream` (the unique count N is read back).  Errors: INVALID_ARG if n_in < 1,
  *   n_qubits < 1, a bit >= n_qubits is set, or max_load is out of range; CAPACITY if
  *   N >= 2^32 - 1; UNSUPPORTED if W exceeds the widest compiled key (see qsd_max_qubits).
@@ -159,9 +163,14 @@ int qsd_subspace_info(const qsd_subspace *s, int64_t *N, int32_t *n_qubits, int3
  * Synchronizes.  INVALID_ARG for max_load or split out of range. */
 int qsd_subspace_rehash(qsd_subspace *s, double max_load, int32_t split, void *stream);
 
-/* Split qubit of the part filters (0 = none) and whether slots use the exact layout (one-word
- * keys whose (home slot, tag) pair is injective).  Either output pointer may be NULL. */
-int qsd_subspace_hash_info(const qsd_subspace *s, int32_t *split, int32_t *exact);
+/* Split qubit of the part filters (0 = none), whether slots use the exact layout (one-word
+ * keys whose (home slot, tag) pair is injective), and whether the subspace has a product map.
+ * A product map exists when both parts have at most 16 qubits and the subspace is exactly the
+ * Cartesian product of its distinct low parts and its distinct high parts (the alpha x beta
+ * product subspaces of Results, fermionic examples): then a string (l, h) has the canonical
+ * index rank(h) * |low parts| + rank(l), which the SpMV reads off the part filters instead of
+ * probing the table.  Any output pointer may be NULL. */
+int qsd_subspace_hash_info(const qsd_subspace *s, int32_t *split, int32_t *exact, int32_t *product);
 
 /* New subspace of the strings whose byte in d_mask[N] (device) is nonzero, in the same order
  * (indices renumbered consecutively), with a table for max_load (0 = default).  INVALID_ARG when
@@ -253,9 +262,10 @@ int qsd_ham_destroy(qsd_ham *h);
 int qsd_ham_info(const qsd_ham *h, int64_t *N, int64_t *G, int32_t *is_complex);
 
 /* Work of one SpMV, counted by a separate pass (synchronizes): `probes` = (row, group) pairs
- * that reach the hash table (a live ladder-integer range with at least one term whose
- * projector bits match), `hits` = those whose column is in the subspace (the off-diagonal
- * stored entries).  Host outputs; either may be NULL. */
+ * that the group filter leaves live (a non-empty ladder-integer range): the subspace lookups of
+ * the method, whether the hash table, the part filters or the product map answers them;
+ * `hits` = those whose column is in the subspace and whose range has a term passing the row's
+ * projector bits (the off-diagonal stored entries).  Host outputs; either may be NULL. */
 int qsd_ham_work_counts(const qsd_ham *h, int64_t *probes, int64_t *hits, void *stream);
 
 /* Lowest diagonal element of H over the subspace and the smallest diagonal energy splitting,
@@ -284,6 +294,10 @@ int qsd_ham_diag_splitting(const qsd_ham *h, double *lowest, double *splitting, 
  *   QSD_SCHED_FILTER_FIRST  a lane first reads the occupancy bits of all its live groups'
  *                         home slots (8 loads in flight), then the slots of the occupied ones
  *                         (4 in flight), instead of reading bit and slot group by group.
+ *   QSD_SCHED_HASH_LOOKUP  columns are looked up in the hash table even when the subspace has a
+ *                         product map (qsd_subspace_hash_info); without it they take their
+ *                         index from the map and the table is not read.  Not swept by the
+ *                         autotuner (the map needs no memory access).
  * A new operator starts with XCD_REMAP | FILTER_FIRST (faster than the plain schedule on every
  * workload measured; slot order pays off when most probes miss, which qsd_ham_autotune finds).
  * The batched entries (qsd_batch_*, qsd_matvec_batched) use each operator's schedule too.
@@ -292,6 +306,7 @@ int qsd_ham_diag_splitting(const qsd_ham *h, double *lowest, double *splitting, 
 #define QSD_SCHED_SLOT_ORDER 2u
 #define QSD_SCHED_LOCKSTEP 4u
 #define QSD_SCHED_FILTER_FIRST 8u
+#define QSD_SCHED_HASH_LOOKUP 16u
 int qsd_ham_set_schedule(qsd_ham *h, uint32_t schedule);
 int qsd_ham_get_schedule(const qsd_ham *h, uint32_t *schedule);
 

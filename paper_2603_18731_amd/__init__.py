@@ -29,6 +29,7 @@ SUB_ASSUME_SORTED_UNIQUE = 1
 V0_UNIFORM, V0_MIN_DIAG, V0_RANDOM, V0_USER = 0, 1, 2, 3
 SCHED_XCD_REMAP, SCHED_SLOT_ORDER, SCHED_LOCKSTEP, SCHED_FILTER_FIRST = 1, 2, 4, 8
 SCHED_ALL = 15
+SCHED_HASH_LOOKUP = 16  # look columns up in the hash table even with a product map
 TUNE_SCHEDULE, TUNE_LOAD, TUNE_SPLIT = 1, 2, 4
 CSR_LOWER_MIRROR = 1
 NOALLOC_MAX_REQUESTS, NOALLOC_MAX_TILES = 256, 65536  # limits of qsd_matvec_batched_noalloc
@@ -188,7 +189,7 @@ def lib():
         "qsd_ham_get_schedule": ([P, P], ctypes.c_int),
         "qsd_ham_autotune": ([P, I32, I32, I32, U32, P, P], ctypes.c_int),
         "qsd_subspace_rehash": ([P, D, I32, P], ctypes.c_int),
-        "qsd_subspace_hash_info": ([P, P, P], ctypes.c_int),
+        "qsd_subspace_hash_info": ([P, P, P, P], ctypes.c_int),
         "qsd_csr_create": ([P, I32, I32, U32, P, P, PP], ctypes.c_int),
         "qsd_csr_info": ([P, P, P, P], ctypes.c_int),
         "qsd_csr_export": ([P, P, P, P, P], ctypes.c_int),
@@ -330,10 +331,10 @@ class Subspace:
         self._refresh()
 
     def hash_info(self):
-        """``(split qubit of the part filters, exact slot layout)``."""
-        sp_, ex = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().qsd_subspace_hash_info(self._h, ctypes.byref(sp_), ctypes.byref(ex)))
-        return sp_.value, bool(ex.value)
+        """``(split qubit of the part filters, exact slot layout, product map)``."""
+        sp_, ex, pm = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().qsd_subspace_hash_info(self._h, ctypes.byref(sp_), ctypes.byref(ex), ctypes.byref(pm)))
+        return sp_.value, bool(ex.value), bool(pm.value)
 
     def probe_stats(self, stream=None):
         m, x = ctypes.c_double(), ctypes.c_int64()

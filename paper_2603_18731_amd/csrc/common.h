@@ -35,6 +35,7 @@ constexpr int kMaxLadder = 4;   // ladder-integer ranges for groups of up to 4 l
 constexpr int kMaxWords = 16;   // widest compiled key: 16 x 64 = 1024 qubits
 constexpr int kBlock = 256;     // threads per workgroup for row kernels
 constexpr uint32_t kSchedAll = QSD_SCHED_XCD_REMAP | QSD_SCHED_SLOT_ORDER | QSD_SCHED_LOCKSTEP | QSD_SCHED_FILTER_FIRST;
+constexpr uint32_t kSchedBits = kSchedAll | QSD_SCHED_HASH_LOOKUP;  // every valid schedule bit
 
 // Padded word count used by the kernels: 1, 2, 4, 8 or 16.
 inline int padded_words(int n_qubits) {
@@ -144,6 +145,10 @@ struct qsd_subspace {
     std::vector<uint32_t> pz;
     uint32_t *pfilt = nullptr;   // [kPartWords] low-part filter, then high-part filter
     uint32_t *pkey = nullptr;    // [N] packed part indices of the rows (canonical order)
+    // Product map (parts of at most 16 qubits, and N = (low parts) x (high parts), so that the
+    // subspace is the Cartesian product of its parts): word prefix counts of both filters.
+    uint16_t *prank = nullptr;   // [kPartWords]
+    uint32_t pna = 0;            // number of distinct low parts
     // operators bound to this subspace: their group hashes follow the hash words on a rehash
     mutable std::vector<qsd_ham *> bound;
 };

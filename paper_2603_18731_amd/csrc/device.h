@@ -27,6 +27,12 @@ struct SubView {
     const uint32_t *__restrict__ pfilt;
     const uint32_t *__restrict__ pkey;
     const uint32_t *__restrict__ opkey;
+    // product map (NULL when the subspace is not the Cartesian product of its two parts, or a
+    // part has more than 16 qubits): prank[w] = set bits of pfilt's words before word w of the
+    // same filter, and pna = the number of low parts.  Then the string (low l, high h) has
+    // canonical index rank_high(h) * pna + rank_low(l).
+    const uint16_t *__restrict__ prank;
+    uint32_t pna;
 };
 
 constexpr int kPartBits = 16;                        // index bits of each part filter
@@ -37,6 +43,21 @@ constexpr int kPartWords = 2 << (kPartBits - 5);     // both filters, in 32-bit 
 __device__ __forceinline__ bool part_pass(const uint32_t *pf, uint32_t p) {
     const uint32_t lo = p & 0xFFFFu, hi = p >> 16;
     return ((pf[lo >> 5] >> (lo & 31u)) & (pf[(kPartWords / 2) + (hi >> 5)] >> (hi & 31u)) & 1u) != 0u;
+}
+
+// Product map: the canonical index of the string with packed part indices p, or -1 when either
+// part is absent.  Strings ascend by high part, then by low part, so when the subspace is the
+// product of its low parts (pna of them) and high parts, the string (l, h) sits at
+// rank(h) * pna + rank(l), each rank read off a filter as the set bits below the part's own.
+// pf / pr are the filters and their word prefix counts (LDS or global copies).
+__device__ __forceinline__ int64_t product_index(const uint32_t *pf, const uint16_t *pr, uint32_t pna, uint32_t p) {
+    const uint32_t lo = p & 0xFFFFu, hi = p >> 16;
+    const uint32_t wl = pf[lo >> 5], wh = pf[(kPartWords / 2) + (hi >> 5)];
+    const uint32_t bl = lo & 31u, bh = hi & 31u;
+    if (!((wl >> bl) & (wh >> bh) & 1u)) return -1;
+    const uint32_t rl = (uint32_t)pr[lo >> 5] + (uint32_t)__popc(wl & ((1u << bl) - 1u));
+    const uint32_t rh = (uint32_t)pr[(kPartWords / 2) + (hi >> 5)] + (uint32_t)__popc(wh & ((1u << bh) - 1u));
+    return (int64_t)rh * pna + rl;
 }
 
 // Slot layout.  Default: tag (high 32 bits of the hash) | index (32 bits).  Exact mode (one-word

@@ -95,7 +95,7 @@ __device__ __forceinline__ uint32_t term_parity(const uint64_t (&k)[Wp], const u
 }
 
 // 4-bit ladder integer of a row from a scan record: bit j = row bit at qubit p_j = shift_j + j.
-// One-word keys are shifted in registers (one funnel shift per bit); wider keys read the
+// One-word keys are shifted in registers (one 64-bit shift per bit); wider keys read the
 // wave's bit planes in LDS (plane p_j, bit = the lane), which avoids indexing a register array
 // with a run-time word number.  Unused positions are don't-cares of the replicated live table.
 template <int Wp>
@@ -103,12 +103,10 @@ __device__ __forceinline__ uint32_t row_lint(const uint64_t (&key)[Wp], uint64_t
                                              int lane) {
     uint32_t L = 0;
     if (Wp == 1) {
-        const uint32_t lo = (uint32_t)key[0], hi = (uint32_t)(key[0] >> 32);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const uint32_t sh = (uint32_t)(rec >> (16 + 12 * j)) & 0xFFFu;
-            const uint32_t t = sh < 32u ? __builtin_amdgcn_alignbit(hi, lo, sh) : (hi >> (sh - 32u));
-            L |= t & (1u << j);
+            const uint32_t sh = (uint32_t)(rec >> (16 + 12 * j)) & 63u;
+            L |= (uint32_t)(key[0] >> sh) & (1u << j);
         }
     } else {
 #pragma unroll
@@ -171,6 +169,8 @@ struct ChunkLds {
     uint8_t clist[kBlock / 64][kChunk];  // lockstep filter-first: the wave's k-th live group
     uint32_t gpart[kChunk];              // the chunk's groups' packed part indices
     uint32_t pf[PartLds<Wp>::words];     // part filters (one- and two-word keys)
+    uint32_t whi[kBlock / 64];           // each wave's shared high part (see row_engine)
+    uint16_t pr[Wp == 1 ? kPartWords : 1];  // their word prefix counts (product map, one-word keys)
 };
 
 // Sum of the terms [t0, t0 + len) that match the row's projector bits, with popcount-parity
@@ -183,18 +183,46 @@ __device__ __forceinline__ bool range_value(const HamView &h, const ChunkLds<Wp>
     bool any = false;
     vre = 0;
     vim = 0;
-    for (uint32_t t = t0; t < t0 + len; ++t) {
-        const uint64_t *cws = h.t_cws + (int64_t)t * 3 * Wp;
-        if (!term_pass<Wp>(key, cws)) continue;
-        any = true;
-        const CT c = coef[t];
-        if (term_parity<Wp>(key, cws)) {
-            vre -= c.x;
-            vim -= c.y;
-        } else {
-            vre += c.x;
-            vim += c.y;
+    // A term that fails the projector test adds +0, which changes no sum (the sums start at +0
+    // and are never -0), so terms are summed without branches, in increasing t as before; the
+    // masks and coefficients of two terms are requested before either is tested.
+    auto add = [&](const uint64_t(&m)[3][Wp], const CT &c) {
+        bool ok = true;
+        uint32_t par = 0;
+#pragma unroll
+        for (int w = 0; w < Wp; ++w) {
+            ok &= (key[w] & m[0][w]) == m[1][w];
+            par += (uint32_t)__popcll(key[w] & m[2][w]);
         }
+        const ET re = (par & 1u) ? -c.x : c.x, im = (par & 1u) ? -c.y : c.y;
+        vre += ok ? re : (ET)0;
+        vim += ok ? im : (ET)0;
+        any |= ok;
+    };
+    const uint32_t t1 = t0 + len;
+    uint32_t t = t0;
+    for (; t + 1u < t1; t += 2u) {
+        uint64_t a[3][Wp], b[3][Wp];
+        const uint64_t *ca = h.t_cws + (int64_t)t * 3 * Wp;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int w = 0; w < Wp; ++w) {
+                a[k][w] = ca[k * Wp + w];
+                b[k][w] = ca[(3 + k) * Wp + w];
+            }
+        const CT xa = coef[t], xb = coef[t + 1u];
+        add(a, xa);
+        add(b, xb);
+    }
+    if (t < t1) {
+        uint64_t a[3][Wp];
+        const uint64_t *ca = h.t_cws + (int64_t)t * 3 * Wp;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int w = 0; w < Wp; ++w) a[k][w] = ca[k * Wp + w];
+        add(a, coef[t]);
     }
     return any;
 }
@@ -278,11 +306,20 @@ __device__ __forceinline__ void deliver(const ChunkLds<Wp> &lds, const uint64_t 
 // Probes NB groups for the lane's row: c[b] = chunk-local group, act[b] = whether the lane
 // probes it.  All occupancy-bit loads are issued before the slot loads, and the slots before any
 // hit is fetched; hits go to on_hit in increasing b (the caller passes increasing groups).
-template <int Wp, int NB, class OnHit>
+template <int Wp, int NB, bool PM, class OnHit>
 __device__ __forceinline__ void probe_groups(const SubView &s, const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp],
                                              uint64_t hrow, uint32_t prow, const uint32_t *pf,
                                              const uint64_t *planes, int lane, const int (&c)[NB],
                                              const bool (&act)[NB], OnHit &on_hit) {
+    if (PM) {
+        // product map: the column's index comes from its parts' ranks, no table access
+        int64_t j[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            j[b] = act[b] ? product_index(pf, lds.pr, s.pna, prow ^ lds.gpart[c[b] & (kChunk - 1)]) : -1;
+        deliver<Wp, NB>(lds, key, planes, lane, c, j, on_hit);
+        return;
+    }
     // unconditional loads: idle lanes read word 0 / slot 0 and ignore them
     uint64_t hh[NB];
     uint32_t pos[NB], word[NB];
@@ -364,10 +401,20 @@ __device__ __forceinline__ void occupancy(const SubView &s, const uint64_t *lhas
 // Filter-first mode, phase 2: resolves NB groups whose home slot is occupied: reads the slots,
 // follows the run when the home slot holds another string and the next slot may be occupied
 // (next[b]), and hands hits to on_hit in increasing b.
-template <int Wp, int NB, class OnHit>
+template <int Wp, int NB, bool PM, class OnHit>
 __device__ __forceinline__ void resolve_groups(const SubView &s, const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp],
-                                               uint64_t hrow, const uint64_t *planes, int lane, const int (&c)[NB],
+                                               uint64_t hrow, uint32_t prow, const uint32_t *pf,
+                                               const uint64_t *planes, int lane, const int (&c)[NB],
                                                const bool (&act)[NB], const bool (&next)[NB], OnHit &on_hit) {
+    if (PM) {
+        // product map: a group marked here passed both part filters, so its column is present
+        int64_t j[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            j[b] = act[b] ? product_index(pf, lds.pr, s.pna, prow ^ lds.gpart[c[b] & (kChunk - 1)]) : -1;
+        deliver<Wp, NB>(lds, key, planes, lane, c, j, on_hit);
+        return;
+    }
     uint64_t hh[NB], slot[NB];
     uint32_t pos[NB];
 #pragma unroll
@@ -409,7 +456,7 @@ __device__ __forceinline__ void resolve_groups(const SubView &s, const ChunkLds<
 // h(b_i) ^ h(M_g), land in one stretch as well, and the wave's occupancy-bit loads for the group
 // touch one or two cache lines instead of one line per lane.  Each lane still meets its hits in
 // increasing group order, so both modes give bitwise the same sums.
-template <int Wp, bool LOWER = false, bool PF = true, class OnHit>
+template <int Wp, bool LOWER = false, int PF = 1, class OnHit>
 __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, const uint64_t (&key)[Wp],
                                            uint64_t hrow, uint32_t prow, bool valid, ChunkLds<Wp> &lds,
                                            OnHit &&on_hit, unsigned long long *probes = nullptr,
@@ -421,8 +468,10 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
     const uint64_t vrows = __ballot(valid);
     // part filters: one- and two-word keys read an LDS copy (visible after the first chunk's
     // barrier, before any probe)
-    // PF = false compiles the engine without part filters (the launch checks that the subspace
-    // has none); PF = true tests them when the subspace has them
+    // PF = 0 compiles the engine without part filters (the launch checks that the subspace has
+    // none); PF = 1 tests them when the subspace has them; PF = 2 is for subspaces with a product
+    // map (one-word keys; the launch checks), whose columns take their index from it
+    constexpr bool PM = PF == 2 && Wp == 1;
     const uint32_t *pf = nullptr;
     if (PF && s.pfilt) {
         if (PartLds<Wp>::words == kPartWords) {
@@ -432,6 +481,8 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
             pf = s.pfilt;
         }
     }
+    if (PM)
+        for (int k = threadIdx.x; k < kPartWords; k += kBlock) lds.pr[k] = s.prank[k];
     // When every row of the wave has the same high (or low) part, as consecutive rows of an
     // alpha x beta product do, that part's filter test depends on the group only: the scan
     // applies it to the whole wave's live word before any lane probes.
@@ -443,9 +494,40 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
         if (__all(!valid || ((prow ^ p0) & 0xFFFFu) == 0u)) uni_mask |= 0x0000FFFFu;
         uni_part = p0;
     }
+    // When all rows of the block share their high part (an alpha x beta product in canonical
+    // order: 256 rows of one beta string, mostly), a chunk whose groups all flip it to a high
+    // part that does not occur holds no live group for any row, and the whole block skips it
+    // (bulk group rejection).  Each wave posts its shared high part; every wave then takes the
+    // same decision per chunk, so the barriers stay matched.  Not for the work counter, which
+    // counts the method's lookups.
+    constexpr uint32_t kMixed = 0xFFFFFFFFu, kEmpty = 0xFFFFFFFEu;
+    const bool bulk = pf && !probes;
+    if (bulk && lane == 0)
+        lds.whi[threadIdx.x >> 6] = vrows == 0ull ? kEmpty : ((uni_mask >> 16) ? (uni_part >> 16) : kMixed);
+    uint32_t blk_hi = kMixed;
     for (int64_t g0 = 0; g0 < h.G; g0 += kChunk) {
         const int nc = (int)((h.G - g0) < kChunk ? (h.G - g0) : kChunk);
         __syncthreads();
+        if (bulk) {
+            if (g0 == 0) {
+                uint32_t v = kEmpty;
+#pragma unroll
+                for (int w = 0; w < kBlock / 64; ++w) {
+                    const uint32_t u = lds.whi[w];
+                    v = u == kEmpty ? v : ((v == kEmpty || v == u) ? u : kMixed);
+                }
+                blk_hi = v;
+            }
+            if (blk_hi == kEmpty) break;  // a block without rows
+            if (blk_hi != kMixed) {
+                bool lv = false;
+                if (lane < nc) {
+                    const uint32_t q = blk_hi ^ (h.g_part[g0 + lane] >> 16);
+                    lv = ((pf[kPartWords / 2 + (q >> 5)] >> (q & 31u)) & 1u) != 0u;
+                }
+                if (__ballot(lv) == 0ull) continue;
+            }
+        }
         for (int c = threadIdx.x; c < nc; c += kBlock) {
             const int64_t g = g0 + c;
             lds.hash[c] = h.g_hash[g];
@@ -462,7 +544,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
         }
         // scan: lane l evaluates group g0 + l for the wave's 64 rows, then the masks are
         // transposed to one live-group mask per row
-        uint64_t live = 0;
+        uint64_t live = 0, live_method = 0;
         if (lane < nc) {
             const uint64_t rec = h.g_scan[g0 + lane];
             uint64_t P[4];
@@ -470,6 +552,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
             for (int j = 0; j < 4; ++j) P[j] = planes[((uint32_t)(rec >> (16 + 12 * j)) & 0xFFFu) + (uint32_t)j];
             live = sliced_table((uint32_t)rec & 0xFFFFu, P[0], P[1], P[2], P[3]) & vrows;
             if (LOWER) live &= planes[group_msob<Wp>(h.g_mask + (g0 + lane) * Wp)];
+            live_method = live;  // the method's lookups, before the part filters answer some
             if (uni_mask) {
                 // the part shared by the whole wave, through this group's flips
                 const uint32_t q = uni_part ^ h.g_part[g0 + lane];
@@ -482,7 +565,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
         uint64_t todo = __ballot(live != 0ull);  // groups live for some row of the wave
         live = wave_transpose64(live, lane);
         uint32_t mlo = (uint32_t)live, mhi = (uint32_t)(live >> 32);
-        if (probes) *probes += (unsigned long long)(__popc(mlo) + __popc(mhi));
+        if (probes) *probes += (unsigned long long)__popcll(live_method);
         __syncthreads();
         if (filter_first && lockstep) {
             // phase 1, wave-uniform groups: bit k of occ / occn is for the wave's k-th live group,
@@ -546,7 +629,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                     c[b] = act[b] ? (int)clist[k] : 0;
                     nxt[b] = act[b] && ((occn >> k) & 1ull);
                 }
-                resolve_groups<Wp, kSlotBatch>(s, lds, key, hrow, planes, lane, c, act, nxt, on_hit);
+                resolve_groups<Wp, kSlotBatch, PM>(s, lds, key, hrow, prow, pf, planes, lane, c, act, nxt, on_hit);
             }
             continue;
         }
@@ -579,7 +662,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                     act[b] = c[b] >= 0;
                     nxt[b] = act[b] && ((occn >> c[b]) & 1ull);
                 }
-                resolve_groups<Wp, kSlotBatch>(s, lds, key, hrow, planes, lane, c, act, nxt, on_hit);
+                resolve_groups<Wp, kSlotBatch, PM>(s, lds, key, hrow, prow, pf, planes, lane, c, act, nxt, on_hit);
             }
             continue;
         }
@@ -593,7 +676,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                     todo &= todo - 1ull;
                     act[b] = c[b] >= 0 && ((live >> c[b]) & 1ull);
                 }
-                probe_groups<Wp, kLockBatch>(s, lds, key, hrow, prow, pf, planes, lane, c, act, on_hit);
+                probe_groups<Wp, kLockBatch, PM>(s, lds, key, hrow, prow, pf, planes, lane, c, act, on_hit);
             }
             continue;
         }
@@ -610,7 +693,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
             bool act[kProbeBatch];
 #pragma unroll
             for (int b = 0; b < kProbeBatch; ++b) act[b] = c[b] >= 0;
-            probe_groups<Wp, kProbeBatch>(s, lds, key, hrow, prow, pf, planes, lane, c, act, on_hit);
+            probe_groups<Wp, kProbeBatch, PM>(s, lds, key, hrow, prow, pf, planes, lane, c, act, on_hit);
         }
     }
 }

@@ -579,7 +579,7 @@ int ensure_rowbits(qsd_ham *h, hipStream_t st) {
 extern "C" int qsd_ham_set_schedule(qsd_ham *h, uint32_t schedule) {
     clear_error();
     if (!h) return fail(QSD_ERR_INVALID_ARG, "NULL handle");
-    if (schedule & ~kSchedAll) return fail(QSD_ERR_INVALID_ARG, "unknown schedule bits 0x%x", schedule);
+    if (schedule & ~kSchedBits) return fail(QSD_ERR_INVALID_ARG, "unknown schedule bits 0x%x", schedule);
     if ((schedule & QSD_SCHED_SLOT_ORDER) && !h->rowbits) {
         // no caller stream here: wait for all work on the device (the tables may still be
         // being written on another stream), then build on the default stream

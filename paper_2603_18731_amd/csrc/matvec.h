@@ -15,7 +15,7 @@ inline HamView ham_view(const qsd_ham *h, bool f32) {
 inline SubView sub_view(const qsd_subspace *s) {
     return SubView{s->keys,       s->hkey,      s->slots,     s->bitmap, s->N, (uint32_t)(s->C - 1),
                    s->exact ? 1u : 0u, s->rows.order, s->rows.keys, s->rows.hkey, s->pfilt, s->pkey,
-                   s->rows.pkey};
+                   s->rows.pkey, s->prank,  s->pna};
 }
 
 // Row tile of workgroup b out of G.  Workgroups are dispatched round-robin over the 8 XCDs, so
@@ -94,7 +94,7 @@ __device__ __forceinline__ void diag_rows_block(const ET *__restrict__ dre, cons
 // its first off-diagonal element and writes y only if it has one (diag_rows_block writes the
 // others), so rows without elements cost no random access to x, d or y.  Either way the sum is
 // formed with the same operations in the same order.
-template <int Wp, int NV, class ET, bool CPLX, bool PF = true>
+template <int Wp, int NV, class ET, bool CPLX, int PF = 1>
 __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h, const ET *__restrict__ dre,
                                              const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
                                              ET *__restrict__ y, int64_t ldy, int nvec, int64_t row0,

@@ -23,7 +23,7 @@ inline unsigned grid_for(int64_t n, int per_block) { return (unsigned)((n + per_
 // the rest take the slot-order tiles and write only the rows with elements; no row is written
 // twice, and each row's value is formed with the same operations as in every other schedule.
 // (Single-vector kernels for up to four key words are held to five waves per SIMD.)
-template <int Wp, int NV, class ET, bool CPLX, bool PF>
+template <int Wp, int NV, class ET, bool CPLX, int PF>
 __global__ __launch_bounds__(kBlock, Wp <= 4 && NV == 1 ? 5 : 1) void k_matvec(
     SubView s, HamView h, const ET *__restrict__ dre,
                                                    const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
@@ -49,15 +49,20 @@ void launch_mv(const qsd_ham *h, const void *x, int64_t ldx, void *y, int64_t ld
     const bool split = (h->schedule & QSD_SCHED_SLOT_ORDER) && h->rowbits;
     const unsigned nd = split ? (tiles + 7u) & ~7u : 0u;
     // the part-filter variant only for subspaces that have filters (the other one carries no
-    // filter code, so it keeps its registers)
-    if (h->s->pfilt)
-        k_matvec<Wp, NV, ET, CPLX, true><<<nd + tiles, kBlock, 0, st>>>(sub_view(h->s), ham_view(h, f32), dre, dim,
-                                                                       (const ET *)x, ldx, (ET *)y, ldy, nvec,
-                                                                       h->schedule, h->rowbits, nd);
+    // filter code, so it keeps its registers), the product-map variant for one-word product
+    // subspaces
+    if (Wp == 1 && h->s->prank && !(h->schedule & QSD_SCHED_HASH_LOOKUP))
+        k_matvec<Wp, NV, ET, CPLX, 2><<<nd + tiles, kBlock, 0, st>>>(sub_view(h->s), ham_view(h, f32), dre, dim,
+                                                                    (const ET *)x, ldx, (ET *)y, ldy, nvec,
+                                                                    h->schedule, h->rowbits, nd);
+    else if (h->s->pfilt)
+        k_matvec<Wp, NV, ET, CPLX, 1><<<nd + tiles, kBlock, 0, st>>>(sub_view(h->s), ham_view(h, f32), dre, dim,
+                                                                    (const ET *)x, ldx, (ET *)y, ldy, nvec,
+                                                                    h->schedule, h->rowbits, nd);
     else
-        k_matvec<Wp, NV, ET, CPLX, false><<<nd + tiles, kBlock, 0, st>>>(sub_view(h->s), ham_view(h, f32), dre, dim,
-                                                                        (const ET *)x, ldx, (ET *)y, ldy, nvec,
-                                                                        h->schedule, h->rowbits, nd);
+        k_matvec<Wp, NV, ET, CPLX, 0><<<nd + tiles, kBlock, 0, st>>>(sub_view(h->s), ham_view(h, f32), dre, dim,
+                                                                    (const ET *)x, ldx, (ET *)y, ldy, nvec,
+                                                                    h->schedule, h->rowbits, nd);
 }
 
 template <int Wp, class ET, bool CPLX>

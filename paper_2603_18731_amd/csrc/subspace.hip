@@ -517,6 +517,7 @@ void free_sub(qsd_subspace *s) {
     dev_free(s->ztab);
     dev_free(s->pfilt);
     dev_free(s->pkey);
+    dev_free(s->prank);
     free_rows(s->rows);
     delete s;
 }
@@ -524,7 +525,7 @@ void free_sub(qsd_subspace *s) {
 SubView view_of(const qsd_subspace *s) {
     return SubView{s->keys,       s->hkey,      s->slots,     s->bitmap, s->N, (uint32_t)(s->C - 1),
                    s->exact ? 1u : 0u, s->rows.order, s->rows.keys, s->rows.hkey, s->pfilt, s->pkey,
-                   s->rows.pkey};
+                   s->rows.pkey, s->prank,  s->pna};
 }
 
 }  // namespace
@@ -548,6 +549,10 @@ int exclusive_scan_i64(const int64_t *d_in, int64_t *d_out, int64_t n, hipStream
 }
 
 }  // namespace qsd
+
+namespace qsd {
+int rehash_split(qsd_subspace *sub, int split, hipStream_t st);
+}
 
 using namespace qsd;
 
@@ -579,6 +584,12 @@ extern "C" int qsd_subspace_build(const uint64_t *d_bits, int64_t n_in, int32_t 
         case 16: rc = build_impl<16>(sub, d_bits, n_in, flags, max_load, st); break;
         default: rc = fail(QSD_ERR_UNSUPPORTED, "unsupported width");
     }
+    // a string of at most 32 qubits split in halves: when the subspace is the product of its
+    // halves (an alpha x beta product), keep the part filters and the product map
+    if (rc == QSD_OK && n_qubits >= 2 && n_qubits <= 32) {
+        rc = rehash_split(sub, n_qubits / 2, st);
+        if (rc == QSD_OK && !sub->prank) rc = rehash_split(sub, 0, st);
+    }
     if (rc != QSD_OK) {
         free_sub(sub);
         return rc;
@@ -604,6 +615,8 @@ int rehash_impl(qsd_subspace *sub, int64_t C, int split, hipStream_t st) {
     uint32_t *bitmap = sub->bitmap;
     bool exact = sub->exact;
     uint32_t *pfilt = nullptr, *pkey = nullptr, *ptab_d = nullptr;
+    uint16_t *prank = nullptr;
+    uint32_t pna = 0;
     std::vector<uint32_t> pz;
     std::vector<uint64_t> tab;
     int rc = QSD_OK;
@@ -651,6 +664,30 @@ int rehash_impl(qsd_subspace *sub, int64_t C, int split, hipStream_t st) {
         // the host tables must outlive their copies
         if (rc == QSD_OK && hipStreamSynchronize(st) != hipSuccess)
             rc = fail(QSD_ERR_HIP, "part filter build failed: %s", hipGetErrorString(hipGetLastError()));
+        // product map: with parts of at most 16 qubits the filters are exact (a part's index is
+        // its own bits), and the subspace is the product of its parts exactly when their counts
+        // multiply to N (every row is one (low, high) pair, and rows are distinct)
+        if (rc == QSD_OK && split <= 16 && sub->n_qubits - split <= 16) {
+            std::vector<uint32_t> hf(kPartWords);
+            if (hipMemcpyAsync(hf.data(), pfilt, kPartWords * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                rc = fail(QSD_ERR_HIP, "copy failed");
+            std::vector<uint16_t> pre(kPartWords);
+            uint64_t cnt[2] = {0, 0};
+            for (int f = 0; f < 2 && rc == QSD_OK; ++f)
+                for (int w = 0; w < kPartWords / 2; ++w) {
+                    pre[(size_t)f * (kPartWords / 2) + w] = (uint16_t)cnt[f];
+                    cnt[f] += (uint64_t)__builtin_popcount(hf[(size_t)f * (kPartWords / 2) + w]);
+                }
+            if (rc == QSD_OK && cnt[0] * cnt[1] == (uint64_t)sub->N) {
+                rc = dev_alloc(&prank, kPartWords);
+                if (rc == QSD_OK &&
+                    (hipMemcpyAsync(prank, pre.data(), kPartWords * 2, hipMemcpyHostToDevice, st) != hipSuccess ||
+                     hipStreamSynchronize(st) != hipSuccess))
+                    rc = fail(QSD_ERR_HIP, "copy failed");
+                pna = (uint32_t)cnt[0];
+            }
+        }
     }
     if (rc == QSD_OK && hipStreamSynchronize(st) != hipSuccess)
         rc = fail(QSD_ERR_HIP, "hash rebuild failed: %s", hipGetErrorString(hipGetLastError()));
@@ -698,6 +735,7 @@ int rehash_impl(qsd_subspace *sub, int64_t C, int split, hipStream_t st) {
         }
         dev_free(pfilt);
         dev_free(pkey);
+        dev_free(prank);
         dev_free(ptab_d);
         return rc;
     }
@@ -712,6 +750,7 @@ int rehash_impl(qsd_subspace *sub, int64_t C, int split, hipStream_t st) {
     }
     dev_free(sub->pfilt);
     dev_free(sub->pkey);
+    dev_free(sub->prank);
     free_rows(sub->rows);
     sub->z = z;
     sub->ztab = ztab;
@@ -723,6 +762,8 @@ int rehash_impl(qsd_subspace *sub, int64_t C, int split, hipStream_t st) {
     sub->rows = rows;
     sub->pfilt = pfilt;
     sub->pkey = pkey;
+    sub->prank = prank;
+    sub->pna = pna;
     sub->pz = pz;
     sub->split = split;
     for (size_t k = 0; k < nb; ++k) {
@@ -739,6 +780,12 @@ int rehash_impl(qsd_subspace *sub, int64_t C, int split, hipStream_t st) {
 }
 
 }  // namespace
+
+// New part filters (split 0: none) on the current table of a one-word subspace.
+int rehash_split(qsd_subspace *sub, int split, hipStream_t st) {
+    return rehash_impl<1>(sub, sub->C, split, st);
+}
+
 }  // namespace qsd
 
 extern "C" int qsd_subspace_rehash(qsd_subspace *s, double max_load, int32_t split, void *stream) {
@@ -764,11 +811,12 @@ extern "C" int qsd_subspace_rehash(qsd_subspace *s, double max_load, int32_t spl
     return fail(QSD_ERR_UNSUPPORTED, "unsupported width");
 }
 
-extern "C" int qsd_subspace_hash_info(const qsd_subspace *s, int32_t *split, int32_t *exact) {
+extern "C" int qsd_subspace_hash_info(const qsd_subspace *s, int32_t *split, int32_t *exact, int32_t *product) {
     clear_error();
     if (!s) return fail(QSD_ERR_INVALID_ARG, "subspace is NULL");
     if (split) *split = s->split;
     if (exact) *exact = s->exact ? 1 : 0;
+    if (product) *product = s->prank ? 1 : 0;
     return QSD_OK;
 }
 

@@ -310,9 +310,9 @@ def test_c2_full_sampled_rows():
 
 
 def test_c3_full_sampled_rows():
-    """The 2.25M-determinant fermionic workload, 400 sampled rows, in the default launch and in
-    the one bench.py times (part filters split at the first beta qubit, load 1/32, filter-first
-    schedule; also the slot-order lockstep schedule under filters).  FP64 with 20-bit dyadic
+    """The 2.25M-determinant fermionic workload, 400 sampled rows, without part filters, with
+    them (split at the first beta qubit) through the product map and through the hash table,
+    and in the launch bench.py times (the product map, filter-first schedule, XCD remap).  FP64 with 20-bit dyadic
     coefficients is exact; FP32 elements and vectors with 16-bit dyadic coefficients give the
     exact value rounded once (every element and every partial sum fits FP32 / FP64 exactly)."""
     ops, keys = c3_parts(1500, 1500)
@@ -330,7 +330,10 @@ def test_c3_full_sampled_rows():
     xd, x32 = torch.from_numpy(x).cuda(), torch.from_numpy(x.astype(np.float32)).cuda()
     y_o = orw.matvec_c(ck_o, tl, x, rows).real
     y16_o = orw.matvec_c(ck_o, tl16, x, rows).real.astype(np.float32)
-    launches = [(0.125, 0, qsd.SCHED_FILTER_FIRST), (1 / 32, 16, qsd.SCHED_FILTER_FIRST), (1 / 32, 16, qsd.SCHED_ALL)]
+    assert sub.hash_info()[2]  # an alpha x beta product: the map is found at build
+    launches = [(0.125, 0, qsd.SCHED_FILTER_FIRST), (1 / 32, 16, qsd.SCHED_FILTER_FIRST),
+                (1 / 32, 16, qsd.SCHED_FILTER_FIRST | qsd.SCHED_HASH_LOOKUP), (1 / 32, 16, qsd.SCHED_ALL),
+                (0.125, 16, qsd.SCHED_FILTER_FIRST | qsd.SCHED_XCD_REMAP)]
     for load, split, sched in launches:
         say("c3 launch", load, split, sched)
         sub.rehash(load, split)
