@@ -510,8 +510,9 @@ def main():
     ap.add_argument("--schedule", default="auto", help="SpMV schedule bits, or 'auto' for the autotuner")
     ap.add_argument("--split", type=int, default=-1, help="hash split qubit (0 = none; -1 = the autotuner "
                     "decides, or none with a fixed schedule)")
-    ap.add_argument("--order-by-mask", type=int, default=0, help="order groups by flip mask (1) instead of by "
-                    "weight, then mask (0)")
+    ap.add_argument("--group-order", default="default", choices=["default", "weight", "mask", "parts"],
+                    help="group order: weight then flip mask, flip mask, halves flipped (alpha / beta) then "
+                    "mask; default = parts for fermionic operators, weight for qubit operators")
     ap.add_argument("--no-extra", action="store_true", help="skip the XXZ and heavy-hex extra measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
@@ -568,9 +569,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     w = make_workload(args.workload)
-    by_mask = args.order_by_mask
     r = measure_spmv(w, args.nvec, args.dtype, args.steps, args.warmup, args.max_load, args.schedule,
-                     split=args.split, solve=not args.no_solve, order_by_mask=bool(by_mask))
+                     split=args.split, solve=not args.no_solve, group_order=args.group_order)
     out = {
         "metric": METRIC,
         "value": r["value"],
@@ -595,7 +595,7 @@ def main():
         for name, nvec in (("xxz6x6", 1), ("heavyhex200", 8)):
             we = make_workload(name)
             re_ = measure_spmv(we, nvec, args.dtype, max(5, args.steps), args.warmup, 0.0, "auto", split=-1,
-                               solve=False, order_by_mask=False)
+                               solve=False)
             out["extra_%s_nvec%d" % (we.name, nvec)] = {
                 "value": re_["value"], "unit": "matrix elements/s", "ms_per_step": re_["ms_per_step"],
                 "config": re_["config"], "roofline": re_["roofline"], "work": re_["work"]}
@@ -609,7 +609,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def measure_spmv(w, nvec, dtype_name, steps, warmup, max_load, schedule, split=0, solve=True, order_by_mask=False):
+def measure_spmv(w, nvec, dtype_name, steps, warmup, max_load, schedule, split=0, solve=True, group_order="default"):
     """Builds workload ``w`` on the device, counts its work, tunes (``schedule`` = "auto") and
     times ``steps`` SpMVs after ``warmup`` with HIP events on the launch stream."""
     import ctypes
@@ -623,7 +623,12 @@ def measure_spmv(w, nvec, dtype_name, steps, warmup, max_load, schedule, split=0
     print("# workload %s: %d strings, %d qubits" % (w.name, w.keys.shape[0], w.ops.n_qubits), file=sys.stderr,
           flush=True)
     sub = qsd.Subspace(w.keys, w.ops.n_qubits, max_load=max_load)
-    op = qsd.operator_from_termlist(w.ops, order_by_mask=order_by_mask)
+    kw = {} if group_order == "default" else {"order_by_mask": group_order == "mask",
+                                                "order_by_parts": group_order == "parts"}
+    op = qsd.operator_from_termlist(w.ops, **kw)
+    if group_order == "default":
+        group_order = "parts" if w.ops.fermionic else "weight"
+
     H = qsd.SubspaceHamiltonian(sub, op)
     N, W = sub.N, sub.W
     # structural nonzeros (CSR count pass) and work counters, outside the timed region
@@ -681,7 +686,7 @@ def measure_spmv(w, nvec, dtype_name, steps, warmup, max_load, schedule, split=0
         "config": {"workload": w.name, "n_qubits": w.ops.n_qubits, "subspace_dim": N, "nnz": nnz,
                    "groups": op.n_groups, "terms": op.n_terms, "nvec": nvec, "kernel": "k_matvec",
                    "schedule": sched, "hash_capacity": sub.capacity, "part_filter_split": hsplit,
-                   "exact_slots": exact, "product_map": product, "groups_by_mask": bool(order_by_mask),
+                   "exact_slots": exact, "product_map": product, "group_order": group_order,
                    "autotune": tune},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -78,6 +78,12 @@ extern "C" {
 #define QSD_OP_FORCE_COMPLEX 4u   /* treat the matrix as complex even if every element is real */
 #define QSD_OP_NO_LADDER_INT 8u   /* evaluate every group without ladder-integer ranges (ablation) */
 #define QSD_OP_ORDER_BY_MASK 16u  /* order groups by flip mask only (default: weight, then mask) */
+/* order groups by the halves of the qubits (below / from n_qubits / 2) they flip: low half only,
+ * both, high half only; groups that flip both by the high half's flip, then weight, then the
+ * low half's; the others by weight, then flip mask.  Groups that flip the high part of a string
+ * alike then sit together, which lets a block of rows that share their high part (an alpha x
+ * beta product subspace split at n_qubits / 2) reject them in bulk. */
+#define QSD_OP_ORDER_BY_PARTS 32u
 
 typedef struct qsd_subspace qsd_subspace;
 typedef struct qsd_op qsd_op;
@@ -343,7 +349,8 @@ int qsd_ham_autotune(qsd_ham *h, int32_t nvec, int32_t dtype, int32_t reps, uint
  *   every row evaluates each group once (ladder-integer range, column by XOR with the group
  *   mask, one hash probe, projector refinement, popcount-parity signs) and applies the element
  *   to all nvec vectors.
- *   Layout: interleaved, element (row j, vector v) at X[j * ldx + v] (ldx >= nvec), likewise Y.
+ *   Layout: interleaved, element (row j, vector v) at X[j * ldx + v] (nvec <= ldx < 2^31),
+ *   likewise Y.
  *   dtype: QSD_F64 / QSD_F32 for a real matrix, QSD_C128 / QSD_C64 for a complex one
  *   (ld counts complex elements).  F32/C64 store elements and vectors in single precision and
  *   accumulate each row in double.

@@ -25,6 +25,7 @@ QSD_OK = 0
 F64, F32, C128, C64 = 0, 1, 2, 3
 INDEX_I32, INDEX_I64 = 0, 1
 OP_FERMIONIC, OP_CHECK_HERMITIAN, OP_FORCE_COMPLEX, OP_NO_LADDER_INT, OP_ORDER_BY_MASK = 1, 2, 4, 8, 16
+OP_ORDER_BY_PARTS = 32
 SUB_ASSUME_SORTED_UNIQUE = 1
 V0_UNIFORM, V0_MIN_DIAG, V0_RANDOM, V0_USER = 0, 1, 2, 3
 SCHED_XCD_REMAP, SCHED_SLOT_ORDER, SCHED_LOCKSTEP, SCHED_FILTER_FIRST = 1, 2, 4, 8
@@ -353,7 +354,11 @@ class _Operator:
 
     def __init__(self, n_qubits: int, term_ptr, op_idx, op_code, coef, check_hermitian: bool = False,
                  force_complex: bool = False, ladder_ints: bool = True, trim_tol: float = 0.0,
-                 order_by_mask: bool = False):
+                 order_by_mask: bool = False, order_by_parts=None):
+        # fermionic operators order their groups by the alpha / beta halves they flip (unless
+        # another order is asked for): blocks of rows sharing a beta string reject them in bulk
+        if order_by_parts is None:
+            order_by_parts = self.fermionic and not order_by_mask
         tp = np.ascontiguousarray(term_ptr, dtype=np.int64)
         oi = np.ascontiguousarray(op_idx, dtype=np.int32)
         oc = np.ascontiguousarray(op_code, dtype=np.uint8)
@@ -361,7 +366,7 @@ class _Operator:
         cr = np.ascontiguousarray(np.stack([c.real, c.imag], axis=1)).astype(np.float64)
         flags = (OP_FERMIONIC if self.fermionic else 0) | (OP_CHECK_HERMITIAN if check_hermitian else 0) | \
                 (OP_FORCE_COMPLEX if force_complex else 0) | (0 if ladder_ints else OP_NO_LADDER_INT) | \
-                (OP_ORDER_BY_MASK if order_by_mask else 0)
+                (OP_ORDER_BY_MASK if order_by_mask else 0) | (OP_ORDER_BY_PARTS if order_by_parts else 0)
         h = ctypes.c_void_p()
         _check(lib().qsd_op_compile(int(n_qubits), tp.shape[0] - 1, _ptr(tp), _ptr(oi), _ptr(oc), _ptr(cr), flags,
                                     float(trim_tol), ctypes.byref(h)))

@@ -224,6 +224,7 @@ struct qsd_ham {
     uint32_t *g_nterm = nullptr;
     uint16_t *g_iptr = nullptr;
     uint64_t *t_cws = nullptr;
+    uint32_t *t_cw32 = nullptr;   // [To][4] care, want, sign as 32-bit words, 0 (n_qubits <= 32)
     double *t_coef = nullptr;     // [To][2]
     float *t_coef32 = nullptr;    // [To][2]
     float *diag32 = nullptr;      // [N]

@@ -33,9 +33,7 @@ __global__ __launch_bounds__(kBlock) void k_count_lower(SubView s, HamView h, un
     bool valid;
     const int64_t r = load_row<Wp>(s, (int64_t)blockIdx.x * kBlock, key, hrow, prow, valid);
     unsigned long long own = 1;  // diagonal
-    row_engine<Wp, true>(s, h, key, hrow, prow, valid, lds, sink([&](int64_t j, uint32_t t0, uint32_t len, int) {
-        double vre, vim;
-        if (!range_value<Wp, double>(h, lds, key, t0, len, vre, vim)) return;
+    row_engine<Wp, true>(s, h, key, hrow, prow, valid, lds, sink<double>([&](int64_t j, double, double, int) {
         ++own;
         atomicAdd(&counts[j], 1ull);  // the mirrored entry (r, j) -> (j, r)
     }), nullptr, false, true);
@@ -60,9 +58,10 @@ __global__ __launch_bounds__(kBlock) void k_fill_lower(SubView s, HamView h, con
         cols[o] = r;
         vals[o] = d;
     }
-    row_engine<Wp, true>(s, h, key, hrow, prow, valid, lds, sink([&](int64_t j, uint32_t t0, uint32_t len, int) {
+    row_engine<Wp, true>(s, h, key, hrow, prow, valid, lds, sink<ET>([&](int64_t j, ET vre, ET vim, int) {
         typename C2<ET>::T v;
-        if (!range_value<Wp, ET>(h, lds, key, t0, len, v.x, v.y)) return;
+        v.x = vre;
+        v.y = vim;
         const int64_t o1 = indptr[r] + (int64_t)atomicAdd(&cursor[r], 1ull);
         cols[o1] = j;
         vals[o1] = v;

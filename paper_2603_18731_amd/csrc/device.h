@@ -54,10 +54,12 @@ __device__ __forceinline__ int64_t product_index(const uint32_t *pf, const uint1
     const uint32_t lo = p & 0xFFFFu, hi = p >> 16;
     const uint32_t wl = pf[lo >> 5], wh = pf[(kPartWords / 2) + (hi >> 5)];
     const uint32_t bl = lo & 31u, bh = hi & 31u;
-    if (!((wl >> bl) & (wh >> bh) & 1u)) return -1;
+    // no branch: the prefix counts are read whether or not both parts occur (N < 2^32, so the
+    // index fits 32 bits)
     const uint32_t rl = (uint32_t)pr[lo >> 5] + (uint32_t)__popc(wl & ((1u << bl) - 1u));
     const uint32_t rh = (uint32_t)pr[(kPartWords / 2) + (hi >> 5)] + (uint32_t)__popc(wh & ((1u << bh) - 1u));
-    return (int64_t)rh * pna + rl;
+    const bool ok = ((wl >> bl) & (wh >> bh) & 1u) != 0u;
+    return ok ? (int64_t)(rh * pna + rl) : (int64_t)-1;
 }
 
 // Slot layout.  Default: tag (high 32 bits of the hash) | index (32 bits).  Exact mode (one-word

@@ -65,6 +65,7 @@ struct HamView {
     int64_t G;
     int coef_f32;                          // t_coef holds float2 (1) or double2 (0)
     const uint32_t *__restrict__ g_part;   // [G] packed part indices of the flip masks (with filters)
+    const uint4 *__restrict__ t_cw32;      // [T] care, want, sign masks as 32-bit words (n <= 32), or NULL
 };
 
 template <class ET>
@@ -78,21 +79,6 @@ struct C2<float> {
     using T = float2;
 };
 
-template <int Wp>
-__device__ __forceinline__ bool term_pass(const uint64_t (&k)[Wp], const uint64_t *__restrict__ cws) {
-    bool ok = true;
-#pragma unroll
-    for (int w = 0; w < Wp; ++w) ok &= (k[w] & cws[w]) == cws[Wp + w];
-    return ok;
-}
-
-template <int Wp>
-__device__ __forceinline__ uint32_t term_parity(const uint64_t (&k)[Wp], const uint64_t *__restrict__ cws) {
-    uint32_t c = 0;
-#pragma unroll
-    for (int w = 0; w < Wp; ++w) c += (uint32_t)__popcll(k[w] & cws[2 * Wp + w]);
-    return c & 1u;
-}
 
 // 4-bit ladder integer of a row from a scan record: bit j = row bit at qubit p_j = shift_j + j.
 // One-word keys are shifted in registers (one 64-bit shift per bit); wider keys read the
@@ -170,59 +156,132 @@ struct ChunkLds {
     uint32_t gpart[kChunk];              // the chunk's groups' packed part indices
     uint32_t pf[PartLds<Wp>::words];     // part filters (one- and two-word keys)
     uint32_t whi[kBlock / 64];           // each wave's shared high part (see row_engine)
-    uint16_t pr[Wp == 1 ? kPartWords : 1];  // their word prefix counts (product map, one-word keys)
 };
 
-// Sum of the terms [t0, t0 + len) that match the row's projector bits, with popcount-parity
-// signs.  Returns false when no term matches (no stored entry).
+// Whether the row's bits under a term's care mask equal its want mask (projector and ladder
+// bits), and the parity of the row's bits under its sign mask; cws = [care][want][sign] words.
+template <int Wp>
+__device__ __forceinline__ bool term_pass(const uint64_t (&k)[Wp], const uint64_t *__restrict__ cws) {
+    bool ok = true;
+#pragma unroll
+    for (int w = 0; w < Wp; ++w) ok &= (k[w] & cws[w]) == cws[Wp + w];
+    return ok;
+}
+
+template <int Wp>
+__device__ __forceinline__ uint32_t term_parity(const uint64_t (&k)[Wp], const uint64_t *__restrict__ cws) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < Wp; ++w) c += (uint32_t)__popcll(k[w] & cws[2 * Wp + w]);
+    return c & 1u;
+}
+
+// Sum over the terms [t0, t0 + len) that match the row's projector bits, with popcount-parity
+// signs, in increasing t; wide keys: the care and want masks are read first, the sign mask and
+// the coefficient only for a matching term.  Returns false when no term matches (no stored
+// entry).
 template <int Wp, class ET>
-__device__ __forceinline__ bool range_value(const HamView &h, const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp],
-                                            uint32_t t0, uint32_t len, ET &vre, ET &vim) {
+__device__ __forceinline__ bool range_value(const HamView &h, const uint64_t (&key)[Wp], uint32_t t0, uint32_t len,
+                                            ET &vre, ET &vim) {
     using CT = typename C2<ET>::T;
     const CT *__restrict__ coef = (const CT *)h.t_coef;
     bool any = false;
     vre = 0;
     vim = 0;
-    // A term that fails the projector test adds +0, which changes no sum (the sums start at +0
-    // and are never -0), so terms are summed without branches, in increasing t as before; the
-    // masks and coefficients of two terms are requested before either is tested.
-    auto add = [&](const uint64_t(&m)[3][Wp], const CT &c) {
-        bool ok = true;
-        uint32_t par = 0;
+    for (uint32_t t = t0; t < t0 + len; ++t) {
+        const uint64_t *cws = h.t_cws + (int64_t)t * 3 * Wp;
+        if (!term_pass<Wp>(key, cws)) continue;
+        any = true;
+        const CT c = coef[t];
+        if (term_parity<Wp>(key, cws)) {
+            vre -= c.x;
+            vim -= c.y;
+        } else {
+            vre += c.x;
+            vim += c.y;
+        }
+    }
+    return any;
+}
+
+// One term's care, want and sign masks and its coefficient c' (Methods, Matrix evaluation: a
+// term contributes c' (-1)^{popcount(b & S)} to a row b whose bits under `care` equal `want`).
+// NARROW: strings of at most 32 qubits, masks as 32-bit words (one 16-byte load).
+template <int Wp, bool NARROW, class ET>
+struct TermRec {
+    uint64_t m[3][Wp];
+    typename C2<ET>::T c;
+};
+template <int Wp, class ET>
+struct TermRec<Wp, true, ET> {
+    uint4 m;  // care, want, sign, unused
+    typename C2<ET>::T c;
+};
+
+template <int Wp, bool NARROW, class ET>
+__device__ __forceinline__ void load_term(const HamView &h, uint32_t t, TermRec<Wp, NARROW, ET> &r) {
+    if constexpr (NARROW) {
+        r.m = h.t_cw32[t];
+    } else {
+        const uint64_t *cw = h.t_cws + (int64_t)t * 3 * Wp;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int w = 0; w < Wp; ++w) r.m[k][w] = cw[k * Wp + w];
+    }
+    r.c = ((const typename C2<ET>::T *)h.t_coef)[t];
+}
+
+// Adds the term to (vre, vim) if the row's projector bits match.  A term that fails adds +0,
+// which changes no sum (the sums start at +0 and are never -0), so there is no branch.
+template <int Wp, bool NARROW, class ET>
+__device__ __forceinline__ void add_term(const uint64_t (&key)[Wp], const TermRec<Wp, NARROW, ET> &r, ET &vre,
+                                         ET &vim, bool &any) {
+    bool ok;
+    uint32_t par;
+    if constexpr (NARROW) {
+        const uint32_t k = (uint32_t)key[0];
+        ok = (k & r.m.x) == r.m.y;
+        par = (uint32_t)__popc(k & r.m.z);
+    } else {
+        ok = true;
+        par = 0;
 #pragma unroll
         for (int w = 0; w < Wp; ++w) {
-            ok &= (key[w] & m[0][w]) == m[1][w];
-            par += (uint32_t)__popcll(key[w] & m[2][w]);
+            ok &= (key[w] & r.m[0][w]) == r.m[1][w];
+            par += (uint32_t)__popcll(key[w] & r.m[2][w]);
         }
-        const ET re = (par & 1u) ? -c.x : c.x, im = (par & 1u) ? -c.y : c.y;
-        vre += ok ? re : (ET)0;
-        vim += ok ? im : (ET)0;
-        any |= ok;
-    };
+    }
+    const ET re = (par & 1u) ? -r.c.x : r.c.x, im = (par & 1u) ? -r.c.y : r.c.y;
+    vre += ok ? re : (ET)0;
+    vim += ok ? im : (ET)0;
+    any |= ok;
+}
+
+// Sum over the terms [t0, t0 + len), len >= 1, whose projector bits match the row, with
+// popcount-parity signs, in increasing t; `first` holds term t0, already loaded.  The rest are
+// loaded two at a time, both before either is tested.  Returns false when no term matches (no
+// stored entry).
+template <int Wp, bool NARROW, class ET>
+__device__ __forceinline__ bool range_sum(const HamView &h, const uint64_t (&key)[Wp], uint32_t t0, uint32_t len,
+                                          const TermRec<Wp, NARROW, ET> &first, ET &vre, ET &vim) {
+    bool any = false;
+    vre = 0;
+    vim = 0;
+    add_term<Wp, NARROW, ET>(key, first, vre, vim, any);
     const uint32_t t1 = t0 + len;
-    uint32_t t = t0;
+    uint32_t t = t0 + 1u;
     for (; t + 1u < t1; t += 2u) {
-        uint64_t a[3][Wp], b[3][Wp];
-        const uint64_t *ca = h.t_cws + (int64_t)t * 3 * Wp;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int w = 0; w < Wp; ++w) {
-                a[k][w] = ca[k * Wp + w];
-                b[k][w] = ca[(3 + k) * Wp + w];
-            }
-        const CT xa = coef[t], xb = coef[t + 1u];
-        add(a, xa);
-        add(b, xb);
+        TermRec<Wp, NARROW, ET> a, b;
+        load_term<Wp, NARROW, ET>(h, t, a);
+        load_term<Wp, NARROW, ET>(h, t + 1u, b);
+        add_term<Wp, NARROW, ET>(key, a, vre, vim, any);
+        add_term<Wp, NARROW, ET>(key, b, vre, vim, any);
     }
     if (t < t1) {
-        uint64_t a[3][Wp];
-        const uint64_t *ca = h.t_cws + (int64_t)t * 3 * Wp;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int w = 0; w < Wp; ++w) a[k][w] = ca[k * Wp + w];
-        add(a, coef[t]);
+        TermRec<Wp, NARROW, ET> a;
+        load_term<Wp, NARROW, ET>(h, t, a);
+        add_term<Wp, NARROW, ET>(key, a, vre, vim, any);
     }
     return any;
 }
@@ -255,24 +314,28 @@ __device__ __forceinline__ uint32_t group_msob(const uint64_t *__restrict__ mask
 }
 
 // A hit consumer: fetch(j) issues the loads a hit on column j needs (x_j, say) and returns them;
-// use(j, t0, len, pre) consumes the hit with what fetch returned.  The engine resolves a batch of
-// groups, then fetches for all of the batch's hits, then uses them in increasing group order, so
-// the fetch latencies overlap while every row's sum keeps its fixed order.
-template <class Use, class Fetch>
+// use(j, vre, vim, pre) consumes a stored element H_ij = vre + i vim (the sum in ET of the
+// row's matching terms) with what fetch returned.  The engine resolves a batch of groups, then
+// fetches for all of the batch's hits and loads the first term of each, then evaluates and
+// uses them in increasing group order, so the load latencies overlap while every row's sum
+// keeps its fixed order.  Probes whose column is present but where no term matches the row's
+// projector bits are not stored entries and are not handed over.
+template <class ET, class Use, class Fetch>
 struct HitSink {
+    using value_type = ET;
     Use use;
     Fetch fetch;
 };
 struct NoFetch {
     __device__ __forceinline__ int operator()(int64_t) const { return 0; }
 };
-template <class Use>
-__device__ __forceinline__ HitSink<Use, NoFetch> sink(Use u) {
-    return HitSink<Use, NoFetch>{u, NoFetch{}};
+template <class ET, class Use>
+__device__ __forceinline__ HitSink<ET, Use, NoFetch> sink(Use u) {
+    return HitSink<ET, Use, NoFetch>{u, NoFetch{}};
 }
-template <class Use, class Fetch>
-__device__ __forceinline__ HitSink<Use, Fetch> sink(Use u, Fetch f) {
-    return HitSink<Use, Fetch>{u, f};
+template <class ET, class Use, class Fetch>
+__device__ __forceinline__ HitSink<ET, Use, Fetch> sink(Use u, Fetch f) {
+    return HitSink<ET, Use, Fetch>{u, f};
 }
 
 // Term range [t0, t0 + len) of chunk group cc for the row (its ladder integer selects it).
@@ -287,19 +350,51 @@ __device__ __forceinline__ void hit_range(const ChunkLds<Wp> &lds, const uint64_
     len = hi - lo;
 }
 
-// Fetch then use for a batch whose columns are resolved (j[b] < 0: no hit).
-template <int Wp, int NB, class Sink>
-__device__ __forceinline__ void deliver(const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp], const uint64_t *planes,
-                                        int lane, const int (&c)[NB], const int64_t (&j)[NB], Sink &on_hit) {
+// Fetch, evaluate and use a batch whose columns are resolved (j[b] < 0: no hit).  A lane
+// without a hit in the batch loads nothing.  Otherwise x_j (or what the sink fetches) is
+// requested for every slot; with NARROW (32-bit term masks, strings of at most 32 qubits) the
+// term ranges of all slots are read and the first term of each is loaded before any is summed
+// (term 0 for a slot without a hit, so no load needs a branch; an off-diagonal group always has
+// a term).  The slots are summed and used in increasing b.
+template <int Wp, int NB, bool NARROW, class Sink>
+__device__ __forceinline__ void deliver(const HamView &h, const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp],
+                                        const uint64_t *planes, int lane, const int (&c)[NB], const int64_t (&j)[NB],
+                                        Sink &on_hit) {
+    using ET = typename Sink::value_type;
+    bool any = false;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) any |= j[b] >= 0;
+    if (!any) return;  // most probes miss on sparse samples: no loads at all for them
     decltype(on_hit.fetch(0)) pre[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) pre[b] = on_hit.fetch(j[b]);  // fetch(-1) loads nothing
+    for (int b = 0; b < NB; ++b) pre[b] = on_hit.fetch(j[b]);
+    if constexpr (NARROW) {
+        // 32-bit masks: the records are small enough to hold one per slot
+        uint32_t t0[NB], len[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        if (j[b] < 0) continue;
-        uint32_t t0, len;
-        hit_range<Wp>(lds, key, planes, lane, c[b], t0, len);
-        on_hit.use(j[b], t0, len, pre[b]);
+        for (int b = 0; b < NB; ++b) {
+            hit_range<Wp>(lds, key, planes, lane, c[b] & (kChunk - 1), t0[b], len[b]);
+            if (j[b] < 0) len[b] = 0u;
+        }
+        TermRec<Wp, NARROW, ET> first[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) load_term<Wp, NARROW, ET>(h, len[b] ? t0[b] : 0u, first[b]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (!len[b]) continue;
+            ET vre, vim;
+            if (range_sum<Wp, NARROW, ET>(h, key, t0[b], len[b], first[b], vre, vim))
+                on_hit.use(j[b], vre, vim, pre[b]);
+        }
+    } else {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (j[b] < 0) continue;
+            uint32_t t0, len;
+            hit_range<Wp>(lds, key, planes, lane, c[b], t0, len);
+            ET vre, vim;
+            if (range_value<Wp, ET>(h, key, t0, len, vre, vim)) on_hit.use(j[b], vre, vim, pre[b]);
+        }
     }
 }
 
@@ -307,8 +402,9 @@ __device__ __forceinline__ void deliver(const ChunkLds<Wp> &lds, const uint64_t 
 // probes it.  All occupancy-bit loads are issued before the slot loads, and the slots before any
 // hit is fetched; hits go to on_hit in increasing b (the caller passes increasing groups).
 template <int Wp, int NB, bool PM, class OnHit>
-__device__ __forceinline__ void probe_groups(const SubView &s, const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp],
-                                             uint64_t hrow, uint32_t prow, const uint32_t *pf,
+__device__ __forceinline__ void probe_groups(const SubView &s, const HamView &h, const ChunkLds<Wp> &lds,
+                                             const uint64_t (&key)[Wp],
+                                             uint64_t hrow, uint32_t prow, const uint32_t *pf, const uint16_t *pr,
                                              const uint64_t *planes, int lane, const int (&c)[NB],
                                              const bool (&act)[NB], OnHit &on_hit) {
     if (PM) {
@@ -316,8 +412,8 @@ __device__ __forceinline__ void probe_groups(const SubView &s, const ChunkLds<Wp
         int64_t j[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b)
-            j[b] = act[b] ? product_index(pf, lds.pr, s.pna, prow ^ lds.gpart[c[b] & (kChunk - 1)]) : -1;
-        deliver<Wp, NB>(lds, key, planes, lane, c, j, on_hit);
+            j[b] = act[b] ? product_index(pf, pr, s.pna, prow ^ lds.gpart[c[b] & (kChunk - 1)]) : -1;
+        deliver<Wp, NB, PM>(h, lds, key, planes, lane, c, j, on_hit);
         return;
     }
     // unconditional loads: idle lanes read word 0 / slot 0 and ignore them
@@ -355,7 +451,7 @@ __device__ __forceinline__ void probe_groups(const SubView &s, const ChunkLds<Wp
             if ((nw >> (nxt & 31u)) & 1u) j[b] = probe_from<Wp>(s, nxt, 1u, tag, col);
         }
     }
-    deliver<Wp, NB>(lds, key, planes, lane, c, j, on_hit);
+    deliver<Wp, NB, PM>(h, lds, key, planes, lane, c, j, on_hit);
 }
 
 // Filter-first mode with part filters, phase 1: a group whose column passes both part filters
@@ -402,8 +498,9 @@ __device__ __forceinline__ void occupancy(const SubView &s, const uint64_t *lhas
 // follows the run when the home slot holds another string and the next slot may be occupied
 // (next[b]), and hands hits to on_hit in increasing b.
 template <int Wp, int NB, bool PM, class OnHit>
-__device__ __forceinline__ void resolve_groups(const SubView &s, const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp],
-                                               uint64_t hrow, uint32_t prow, const uint32_t *pf,
+__device__ __forceinline__ void resolve_groups(const SubView &s, const HamView &h, const ChunkLds<Wp> &lds,
+                                               const uint64_t (&key)[Wp],
+                                               uint64_t hrow, uint32_t prow, const uint32_t *pf, const uint16_t *pr,
                                                const uint64_t *planes, int lane, const int (&c)[NB],
                                                const bool (&act)[NB], const bool (&next)[NB], OnHit &on_hit) {
     if (PM) {
@@ -411,8 +508,8 @@ __device__ __forceinline__ void resolve_groups(const SubView &s, const ChunkLds<
         int64_t j[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b)
-            j[b] = act[b] ? product_index(pf, lds.pr, s.pna, prow ^ lds.gpart[c[b] & (kChunk - 1)]) : -1;
-        deliver<Wp, NB>(lds, key, planes, lane, c, j, on_hit);
+            j[b] = act[b] ? product_index(pf, pr, s.pna, prow ^ lds.gpart[c[b] & (kChunk - 1)]) : -1;
+        deliver<Wp, NB, PM>(h, lds, key, planes, lane, c, j, on_hit);
         return;
     }
     uint64_t hh[NB], slot[NB];
@@ -436,7 +533,7 @@ __device__ __forceinline__ void resolve_groups(const SubView &s, const ChunkLds<
         if ((uint32_t)(slot[b] >> 32) == tag) j[b] = slot_match<Wp>(s, slot[b], 0u, col);
         if (j[b] < 0 && next[b]) j[b] = probe_from<Wp>(s, (pos[b] + 1) & s.cmask, 1u, tag, col);
     }
-    deliver<Wp, NB>(lds, key, planes, lane, c, j, on_hit);
+    deliver<Wp, NB, PM>(h, lds, key, planes, lane, c, j, on_hit);
 }
 
 // Walks all groups for the lane's row and hands on_hit (a HitSink) every probe whose
@@ -481,8 +578,13 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
             pf = s.pfilt;
         }
     }
-    if (PM)
-        for (int k = threadIdx.x; k < kPartWords; k += kBlock) lds.pr[k] = s.prank[k];
+    // the product map's prefix counts: an LDS array of their own, in product-map kernels only
+    const uint16_t *pr = nullptr;
+    if constexpr (PM) {
+        __shared__ uint16_t pr_lds[kPartWords];
+        for (int k = threadIdx.x; k < kPartWords; k += kBlock) pr_lds[k] = s.prank[k];
+        pr = pr_lds;
+    }
     // When every row of the wave has the same high (or low) part, as consecutive rows of an
     // alpha x beta product do, that part's filter test depends on the group only: the scan
     // applies it to the whole wave's live word before any lane probes.
@@ -629,7 +731,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                     c[b] = act[b] ? (int)clist[k] : 0;
                     nxt[b] = act[b] && ((occn >> k) & 1ull);
                 }
-                resolve_groups<Wp, kSlotBatch, PM>(s, lds, key, hrow, prow, pf, planes, lane, c, act, nxt, on_hit);
+                resolve_groups<Wp, kSlotBatch, PM>(s, h, lds, key, hrow, prow, pf, pr, planes, lane, c, act, nxt, on_hit);
             }
             continue;
         }
@@ -662,7 +764,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                     act[b] = c[b] >= 0;
                     nxt[b] = act[b] && ((occn >> c[b]) & 1ull);
                 }
-                resolve_groups<Wp, kSlotBatch, PM>(s, lds, key, hrow, prow, pf, planes, lane, c, act, nxt, on_hit);
+                resolve_groups<Wp, kSlotBatch, PM>(s, h, lds, key, hrow, prow, pf, pr, planes, lane, c, act, nxt, on_hit);
             }
             continue;
         }
@@ -676,7 +778,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                     todo &= todo - 1ull;
                     act[b] = c[b] >= 0 && ((live >> c[b]) & 1ull);
                 }
-                probe_groups<Wp, kLockBatch, PM>(s, lds, key, hrow, prow, pf, planes, lane, c, act, on_hit);
+                probe_groups<Wp, kLockBatch, PM>(s, h, lds, key, hrow, prow, pf, pr, planes, lane, c, act, on_hit);
             }
             continue;
         }
@@ -693,7 +795,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
             bool act[kProbeBatch];
 #pragma unroll
             for (int b = 0; b < kProbeBatch; ++b) act[b] = c[b] >= 0;
-            probe_groups<Wp, kProbeBatch, PM>(s, lds, key, hrow, prow, pf, planes, lane, c, act, on_hit);
+            probe_groups<Wp, kProbeBatch, PM>(s, h, lds, key, hrow, prow, pf, pr, planes, lane, c, act, on_hit);
         }
     }
 }

@@ -59,10 +59,7 @@ __global__ __launch_bounds__(kBlock) void k_row_bits(SubView s, HamView h, uint6
     const int64_t row0 = (int64_t)blockIdx.x * kBlock;
     load_row<Wp>(s, row0, key, hrow, prow, valid);
     bool has = false;
-    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink([&](int64_t, uint32_t t0, uint32_t len, int) {
-        double vre, vim;
-        if (range_value<Wp, double>(h, lds, key, t0, len, vre, vim)) has = true;
-    }), nullptr, false, true);
+    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink<double>([&](int64_t, double, double, int) { has = true; }), nullptr, false, true);
     const uint64_t w = __ballot(has && valid);
     const int64_t word = (row0 >> 6) + (threadIdx.x >> 6);
     if ((threadIdx.x & 63) == 0 && word * 64 < s.N) bits[word] = w;
@@ -78,10 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_csr_count(SubView s, HamView h, int6
     bool valid;
     const int64_t r = load_row<Wp>(s, (int64_t)blockIdx.x * kBlock, key, hrow, prow, valid);
     int64_t cnt = 1;  // diagonal
-    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink([&](int64_t, uint32_t t0, uint32_t len, int) {
-        double vre, vim;
-        if (range_value<Wp, double>(h, lds, key, t0, len, vre, vim)) ++cnt;
-    }), nullptr, false, true);
+    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink<double>([&](int64_t, double, double, int) { ++cnt; }), nullptr, false, true);
     if (valid) counts[r] = cnt;
 }
 
@@ -95,10 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_probe_count(SubView s, HamView h, un
     bool valid;
     load_row<Wp>(s, (int64_t)blockIdx.x * kBlock, key, hrow, prow, valid);
     unsigned long long probes = 0, hits = 0;
-    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink([&](int64_t, uint32_t t0, uint32_t len, int) {
-        double vre, vim;
-        if (range_value<Wp, double>(h, lds, key, t0, len, vre, vim)) ++hits;
-    }), &probes, false, true);
+    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink<double>([&](int64_t, double, double, int) { ++hits; }), &probes, false, true);
     for (int d = 32; d >= 1; d >>= 1) {
         probes += __shfl_xor(probes, d, 64);
         hits += __shfl_xor(hits, d, 64);
@@ -128,9 +119,10 @@ __global__ __launch_bounds__(kBlock) void k_csr_fill(SubView s, HamView h, const
         vals[o] = d;
     }
     ++o;
-    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink([&](int64_t j, uint32_t t0, uint32_t len, int) {
+    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink<ET>([&](int64_t j, ET vre, ET vim, int) {
         typename C2<ET>::T v;
-        if (!range_value<Wp, ET>(h, lds, key, t0, len, v.x, v.y)) return;
+        v.x = vre;
+        v.y = vim;
         cols[o] = j;
         vals[o] = v;
         ++o;
@@ -206,6 +198,7 @@ void free_ham(qsd_ham *h) {
     dev_free(h->g_iptr);
     dev_free(h->t_cws);
     dev_free(h->t_coef);
+    dev_free(h->t_cw32);
     dev_free(h->t_coef32);
     dev_free(h->diag32);
     dev_free(h->diag32_im);
@@ -236,6 +229,15 @@ int create_impl(qsd_ham *h, hipStream_t st) {
     QSD_TRY(upload(&h->g_nterm, op->g_nterm, st));
     QSD_TRY(upload(&h->g_iptr, op->g_iptr, st));
     QSD_TRY(upload(&h->t_cws, op->t_cws, st));
+    std::vector<uint32_t> cw32;
+    if (op->n_qubits <= 32) {
+        // one-word keys of at most 32 qubits: the term masks fit 32 bits
+        const size_t To = op->t_cws.size() / 3;
+        cw32.assign(To * 4, 0u);
+        for (size_t t = 0; t < To; ++t)
+            for (int k = 0; k < 3; ++k) cw32[t * 4 + k] = (uint32_t)op->t_cws[t * 3 + k];
+        QSD_TRY(upload(&h->t_cw32, cw32, st));
+    }
     QSD_TRY(upload(&h->t_coef, op->t_coef, st));
     std::vector<float> c32(op->t_coef.size());
     for (size_t k = 0; k < c32.size(); ++k) c32[k] = (float)op->t_coef[k];
@@ -378,6 +380,7 @@ extern "C" int qsd_matvec(const qsd_ham *h, int32_t nvec, const void *d_x, int64
     if (!h || !d_x || !d_y) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
     if (nvec < 1 || nvec > 16) return fail(QSD_ERR_INVALID_ARG, "nvec must be in [1, 16]");
     if (ldx < nvec || ldy < nvec) return fail(QSD_ERR_INVALID_ARG, "leading dimension smaller than nvec");
+    if (ldx > INT32_MAX || ldy > INT32_MAX) return fail(QSD_ERR_INVALID_ARG, "leading dimension of 2^31 or more");
     QSD_TRY(check_dtype(h, dtype));
     hipStream_t st = (hipStream_t)stream;
     const int chunk = (dtype == QSD_C128 || dtype == QSD_C64) ? 4 : 16;

@@ -9,7 +9,7 @@ namespace qsd {
 inline HamView ham_view(const qsd_ham *h, bool f32) {
     return HamView{h->g_mask, h->g_hash, h->g_pos,  h->g_scan, h->g_info, h->g_term0, h->g_nterm,
                    h->g_iptr, h->t_cws,  f32 ? (const void *)h->t_coef32 : (const void *)h->t_coef, h->G,
-                   f32 ? 1 : 0, h->g_part};
+                   f32 ? 1 : 0, h->g_part, (const uint4 *)h->t_cw32};
 }
 
 inline SubView sub_view(const qsd_subspace *s) {
@@ -122,11 +122,15 @@ __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h,
             }
         }
     }
-    // one real vector: x_j is fetched for a whole batch of hits before any is consumed
-    auto fetch = [&](int64_t j) -> double { return (!CPLX && NV == 1 && j >= 0) ? (double)x[j * ldx] : 0.0; };
-    auto use = [&](int64_t j, uint32_t t0, uint32_t len, double xj) {
-        ET vre, vim;
-        if (!range_value<Wp, ET>(h, lds, key, t0, len, vre, vim)) return;
+    // one real vector: x_j is fetched for a whole batch of hits before any is consumed (a lane
+    // without a hit loads x[0] and drops it, so the loads need no branch; ldx < 2^31)
+    auto fetch = [&](int64_t j) -> double {
+        if (CPLX || NV != 1) return 0.0;
+        const uint32_t jj = j < 0 ? 0u : (uint32_t)j;
+        const double v = (double)x[(uint64_t)jj * (uint32_t)ldx];
+        return j < 0 ? 0.0 : v;
+    };
+    auto use = [&](int64_t j, ET vre, ET vim, double xj) {
         if (!have) {
             have = true;
             const double dr = (double)dre[r];
@@ -155,7 +159,7 @@ __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h,
             }
         }
     };
-    row_engine<Wp, false, PF>(s, h, key, hrow, prow, valid, lds, sink(use, fetch), nullptr, lockstep, filter_first);
+    row_engine<Wp, false, PF>(s, h, key, hrow, prow, valid, lds, sink<ET>(use, fetch), nullptr, lockstep, filter_first);
     if (!valid || !have) return;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {

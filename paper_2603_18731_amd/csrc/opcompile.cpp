@@ -364,6 +364,8 @@ extern "C" int qsd_op_compile(int32_t n_qubits, int64_t n_terms, const int64_t *
         size_t idx;
         Masks m;
         int weight;
+        int part_class = 0;                 // by parts: 0 low half only, 1 both, 2 high half only
+        std::vector<uint64_t> lo, hi;       // by parts: the flip mask's halves
     };
     std::vector<Item> diag, offd;
     for (size_t i = 0; i < comb.size(); ++i) {
@@ -375,7 +377,33 @@ extern "C" int qsd_op_compile(int32_t n_qubits, int64_t n_terms, const int64_t *
             offd.push_back({i, std::move(m), wgt});
     }
     const bool by_mask = (flags & QSD_OP_ORDER_BY_MASK) != 0;
-    std::stable_sort(offd.begin(), offd.end(), [by_mask](const Item &x, const Item &y) {
+    const bool by_parts = (flags & QSD_OP_ORDER_BY_PARTS) != 0;
+    if (by_parts) {
+        // the flip mask split at qubit n/2 into its low and high halves; groups ordered by which
+        // halves they flip (low only, both, high only); groups flipping both by the high half,
+        // then weight, then the low half (runs that flip the high part alike); the others by
+        // weight, then mask (short and long term ranges apart)
+        const int half = n_qubits / 2;
+        for (auto &it : offd) {
+            it.lo.assign(it.m.off.size(), 0);
+            it.hi.assign(it.m.off.size(), 0);
+            for (size_t w = 0; w < it.m.off.size(); ++w)
+                for (uint64_t b = it.m.off[w]; b; b &= b - 1) {
+                    const int q = 64 * (int)w + __builtin_ctzll(b);
+                    (q < half ? it.lo : it.hi)[w] |= 1ull << (q & 63);
+                }
+            const bool l = popcount_words(it.lo) > 0, h = popcount_words(it.hi) > 0;
+            it.part_class = l && h ? 1 : (h ? 2 : 0);
+        }
+    }
+    std::stable_sort(offd.begin(), offd.end(), [&](const Item &x, const Item &y) {
+        if (by_parts) {
+            if (x.part_class != y.part_class) return x.part_class < y.part_class;
+            if (x.part_class == 1 && x.hi != y.hi) return mask_less(x.hi, y.hi);
+            if (x.weight != y.weight) return x.weight < y.weight;
+            if (x.hi != y.hi) return mask_less(x.hi, y.hi);
+            return mask_less(x.lo, y.lo);
+        }
         if (!by_mask && x.weight != y.weight) return x.weight < y.weight;
         return mask_less(x.m.off, y.m.off);
     });

@@ -38,10 +38,8 @@ __global__ __launch_bounds__(kBlock) void k_ramps_level(SubView s, HamView h, co
     for (int w = 0; w < Wp; ++w) key[w] = s.keys[(int64_t)w * s.N + r];
     const uint64_t hrow = s.hkey[r];
     const uint32_t prow = s.pfilt ? s.pkey[r] : 0u;
-    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink([&](int64_t k, uint32_t t0, uint32_t len, int) {
+    row_engine<Wp>(s, h, key, hrow, prow, valid, lds, sink<double>([&](int64_t k, double vre, double vim, int) {
         if (in_s0[k]) return;  // the model space is not followed
-        double vre, vim;
-        if (!range_value<Wp, double>(h, lds, key, t0, len, vre, vim)) return;
         double amp, next;
         {
 #pragma clang fp contract(off)

@@ -51,11 +51,15 @@ void launch_mv(const qsd_ham *h, const void *x, int64_t ldx, void *y, int64_t ld
     // the part-filter variant only for subspaces that have filters (the other one carries no
     // filter code, so it keeps its registers), the product-map variant for one-word product
     // subspaces
-    if (Wp == 1 && h->s->prank && !(h->schedule & QSD_SCHED_HASH_LOOKUP))
-        k_matvec<Wp, NV, ET, CPLX, 2><<<nd + tiles, kBlock, 0, st>>>(sub_view(h->s), ham_view(h, f32), dre, dim,
-                                                                    (const ET *)x, ldx, (ET *)y, ldy, nvec,
-                                                                    h->schedule, h->rowbits, nd);
-    else if (h->s->pfilt)
+    if constexpr (Wp == 1) {
+        if (h->s->prank && !(h->schedule & QSD_SCHED_HASH_LOOKUP)) {
+            k_matvec<Wp, NV, ET, CPLX, 2><<<nd + tiles, kBlock, 0, st>>>(sub_view(h->s), ham_view(h, f32), dre, dim,
+                                                                        (const ET *)x, ldx, (ET *)y, ldy, nvec,
+                                                                        h->schedule, h->rowbits, nd);
+            return;
+        }
+    }
+    if (h->s->pfilt)
         k_matvec<Wp, NV, ET, CPLX, 1><<<nd + tiles, kBlock, 0, st>>>(sub_view(h->s), ham_view(h, f32), dre, dim,
                                                                     (const ET *)x, ldx, (ET *)y, ldy, nvec,
                                                                     h->schedule, h->rowbits, nd);

@@ -63,20 +63,25 @@ def test_product_detected():
     assert qsd.Subspace(w.keys, w.ops.n_qubits).hash_info()[2]
 
 
-@pytest.mark.parametrize("na,nb", [(37, 29), (70, 70), (128, 3), (1, 200), (300, 1)])
-def test_product_matvec_exact(na, nb):
+ORDERS = {"parts": {}, "weight": {"order_by_parts": False}, "mask": {"order_by_mask": True}}
+
+
+@pytest.mark.parametrize("na,nb,order", [(37, 29, "parts"), (70, 70, "parts"), (70, 70, "weight"), (70, 70, "mask"),
+                                         (128, 3, "parts"), (1, 200, "parts"), (300, 1, "weight")])
+def test_product_matvec_exact(na, nb, order):
     """Dyadic coefficients and vectors: every schedule, with the map and through the table,
-    equals the oracle bit for bit (one vector, three interleaved vectors, and FP32 elements and
-    vectors with FP64 accumulation, whose result is the exact value rounded once)."""
+    under each group order, equals the oracle bit for bit (one vector, three interleaved
+    vectors, and FP32 elements and vectors with FP64 accumulation, whose result is the exact
+    value rounded once)."""
     ops, keys = c3_parts(na, nb) if na > 1 and nb > 1 else (None, None)
     if ops is None:
         w = wl.c3_molecular(na, nb)
         ops, keys = w.ops, w.keys
     tl = dyadic(ops)
-    say("product matvec", na, nb)
+    say("product matvec", na, nb, order)
     sub = qsd.Subspace(keys, tl.n_qubits)
     assert sub.hash_info()[2]
-    H = qsd.SubspaceHamiltonian(sub, qsd.operator_from_termlist(tl))
+    H = qsd.SubspaceHamiltonian(sub, qsd.operator_from_termlist(tl, **ORDERS[order]))
     ck = osub.canonical_keys(keys)
     rng = np.random.default_rng(na * 1000 + nb)
     X = dyadic_vector(rng, sub.N, nvec=3)
@@ -87,7 +92,7 @@ def test_product_matvec_exact(na, nb):
     for sched, y in _all_schedules(H, torch.from_numpy(x1).cuda()):
         np.testing.assert_array_equal(y.cpu().numpy(), Y_o[:, 0], err_msg="schedule %d" % sched)
     tl8 = dyadic(ops, bits=8)
-    H8 = qsd.SubspaceHamiltonian(sub, qsd.operator_from_termlist(tl8))
+    H8 = qsd.SubspaceHamiltonian(sub, qsd.operator_from_termlist(tl8, **ORDERS[order]))
     X6 = dyadic_vector(rng, sub.N, bits=6, nvec=2)
     Y8 = orw.matvec_c(ck, tl8, X6).real.astype(np.float32)
     for sched, y in _all_schedules(H8, torch.from_numpy(X6.astype(np.float32)).cuda()):

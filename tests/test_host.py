@@ -117,11 +117,17 @@ def test_merge_rules_through_compiler():
         assert terms == [(1.0, [(0, res)])], (seq, terms)
 
 
-def test_grouping_invariants():
+@pytest.mark.parametrize("order", ["weight", "parts"])
+def test_grouping_invariants(order):
+    """Every group holds the terms of one flip mask, ladder ranges ascend inside a group, and
+    the groups follow the requested order: (weight, mask), or by parts (halves of the qubits
+    flipped: low only, both, high only; groups flipping both by high half, weight, low half;
+    the others by weight, high half, low half).  Both orders hold the same groups."""
     _lib_or_skip()
     rng = np.random.default_rng(3)
-    tl = _random_fermion_tl(rng, 8, 200)
-    op = qsd.FermionicOperator.from_termlist(tl)
+    n = 8
+    tl = _random_fermion_tl(rng, n, 200)
+    op = qsd.FermionicOperator.from_termlist(tl, order_by_parts=order == "parts")
     terms, gp, gl = _export_terms(op)
     assert gp[0] == 0 and gp[-1] == len(terms)
 
@@ -136,7 +142,10 @@ def test_grouping_invariants():
         assert len(masks) == 1
         m = masks.pop()
         assert m != 0
-        keys.append((bin(m).count("1"), m))
+        lo, hi = m & ((1 << (n // 2)) - 1), m >> (n // 2)
+        cls = 1 if lo and hi else (2 if hi else 0)
+        wt = bin(m).count("1")
+        keys.append((wt, m) if order == "weight" else ((cls, hi, wt, lo) if cls == 1 else (cls, wt, hi, lo)))
         if gl[g]:
             qs = [q for q in range(64) if m >> q & 1]
             lints = []
@@ -145,6 +154,15 @@ def test_grouping_invariants():
                 lints.append(sum((1 << k) for k, q in enumerate(qs) if w[q] == 6))
             assert lints == sorted(lints)
     assert keys == sorted(keys) and len(set(keys)) == len(keys)
+    # the other order: the same groups with the same terms
+    other = qsd.FermionicOperator.from_termlist(tl, order_by_parts=order != "parts")
+    t2, gp2, _ = _export_terms(other)
+
+    def group_set(ts, g):
+        return {frozenset((complex(ts[t][0]), tuple(ts[t][1])) for t in range(g[k], g[k + 1]))
+                for k in range(len(g) - 1)}
+
+    assert group_set(terms, gp) == group_set(t2, gp2)
 
 
 def test_compile_errors():
