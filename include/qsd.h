@@ -320,7 +320,8 @@ int qsd_ham_get_schedule(const qsd_ham *h, uint32_t *schedule);
  * with HIP events for every candidate and keeps the fastest:
  *   QSD_TUNE_SCHEDULE  every schedule above (on the current table);
  *   QSD_TUNE_LOAD      hash-table loads 1/32, 1/16, 1/8, 1/4, 1/2 (with the three fastest
- *                      schedules when both flags are set): the subspace's table is rebuilt
+ *                      schedules when both flags are set; not swept when the subspace has a
+ *                      product map, whose SpMV does not read the table): the table is rebuilt
  *                      (qsd_subspace_rehash), so the subspace must not be used meanwhile by
  *                      any other handle, batch or stream.  The best table depends on how the
  *                      occupancy bitmap and the slots fit the caches.

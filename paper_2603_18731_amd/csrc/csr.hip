@@ -441,6 +441,7 @@ extern "C" int qsd_csr_matvec(const qsd_csr *c, int32_t nvec, const void *d_x, i
     if (!c || !d_x || !d_y) return fail(QSD_ERR_INVALID_ARG, "NULL argument");
     if (nvec < 1 || nvec > 16) return fail(QSD_ERR_INVALID_ARG, "nvec must be in [1, 16]");
     if (ldx < nvec || ldy < nvec) return fail(QSD_ERR_INVALID_ARG, "leading dimension smaller than nvec");
+    if (ldx > INT32_MAX || ldy > INT32_MAX) return fail(QSD_ERR_INVALID_ARG, "leading dimension of 2^31 or more");
     if (dtype != c->dtype) return fail(QSD_ERR_DTYPE, "vectors must have the matrix dtype %d", c->dtype);
     hipStream_t st = (hipStream_t)stream;
     const int chunk = c->cplx ? 4 : 16;

@@ -669,8 +669,10 @@ extern "C" int qsd_ham_autotune(qsd_ham *h, int32_t nvec, int32_t dtype, int32_t
     std::vector<int32_t> splits{split0};
     if ((flags & QSD_TUNE_SPLIT) && h->s->n_qubits >= 2) splits.push_back(split0 ? 0 : h->s->n_qubits / 2);
     std::vector<std::pair<double, int32_t>> tables;
+    // with a product map the SpMV does not read the table: its load changes nothing
+    const bool sweep_load = (flags & QSD_TUNE_LOAD) && !(sub->prank && !(h->schedule & QSD_SCHED_HASH_LOOKUP));
     for (size_t k = 0; k < splits.size(); ++k) {
-        if (flags & QSD_TUNE_LOAD)
+        if (sweep_load)
             for (double l : {0.03125, 0.0625, 0.125, 0.25, 0.5}) tables.push_back({l, splits[k]});
         else if (k > 0)
             tables.push_back({load0, splits[k]});

@@ -94,7 +94,9 @@ def test_schedules_bitwise(case):
     r = H.autotune(nvec=x.shape[1], dtype=x.dtype, reps=2)
     say(case, "autotune ->", r)
     assert 0 <= r["schedule"] <= qsd.SCHED_ALL and H.schedule == r["schedule"] and r["ms"] > 0
-    assert r["max_load"] in (0.03125, 0.0625, 0.125, 0.25, 0.5) and H.subspace.capacity == r["capacity"]
+    # (a product subspace keeps its table: the SpMV does not read it)
+    assert r["max_load"] in (0.03125, 0.0625, 0.125, 0.25, 0.5) or H.subspace.hash_info()[2]
+    assert H.subspace.capacity == r["capacity"]
     assert torch.equal(H.matvec(x), outs[0])  # a rebuilt table gives the same output
     keys_before = H.subspace.keys()
     nq = H.subspace.n_qubits
