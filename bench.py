@@ -128,6 +128,8 @@ def make_workload(name):
         w = wl.c1_tfim12()
     elif name == "fermi16":
         w = wl.c3_molecular()
+    elif name == "fermi16_300":
+        w = wl.c3_molecular(300, 300)
     elif name == "heavyhex200":
         w = wl.c4_heavy_hex()
     else:
@@ -371,9 +373,18 @@ def precision_compare(args):
             print("# %s: %s SpMV %.3f ms, block %d: %.12f in %.3f s (%d steps)" % (
                 w.name, name, out["spmv_ms_" + name], block, e, out["solve_s_" + key], info["iterations"]),
                 file=sys.stderr, flush=True)
+    # the oracle's ground energy of this workload, where one was computed (tests/golden, written by
+    # a script that runs only the CPU oracle)
+    with open(os.path.join(ROOT, "tests", "golden", "energies.json")) as f:
+        golden = json.load(f)
+    e_or = golden.get(w.name, {}).get("energy")
+    out["energy_oracle"] = e_or
     for block in (1, 8):
         e64 = out["energy_f64_b%d" % block]
         out["energy_rel_err_f32_b%d" % block] = abs(out["energy_f32_b%d" % block] - e64) / abs(e64)
+        for name in ("f64", "f32"):
+            if e_or is not None:
+                out["energy_rel_err_vs_oracle_%s_b%d" % (name, block)] = abs(out["energy_%s_b%d" % (name, block)] - e_or) / abs(e_or)
     print(json.dumps({"precision_compare": out}), flush=True)
 
 
@@ -503,7 +514,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="fermi16")
+    ap.add_argument("--workload", default="fermi16", help="fermi16 (1500 x 1500), fermi16_300 (300 x 300), "
+                    "xxz6x6, heavyhex200 or tfim12")
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--nvec", type=int, default=1)
     ap.add_argument("--max-load", type=float, default=0.0, help="hash load factor (0 = library default)")
