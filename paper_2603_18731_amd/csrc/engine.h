@@ -44,6 +44,8 @@ constexpr int kProbeBatch = 2;  // probes in flight per lane
 constexpr int kLockBatch = 4;   // groups in flight per wave in lockstep mode
 constexpr int kOccBatch = 8;    // occupancy-bit loads in flight per lane (filter-first mode)
 constexpr int kSlotBatch = 4;   // slot loads in flight per lane (filter-first mode)
+constexpr int kSlotBatchPM = 2; // hits per batch in filter-first mode with the product map
+constexpr int kOccBatchPM = 4;  // filter tests per batch in filter-first mode with the product map
 
 // One- and two-word keys copy the part filters into LDS; wider keys read them from memory.
 template <int Wp>
@@ -84,11 +86,19 @@ struct C2<float> {
 // One-word keys are shifted in registers (one 64-bit shift per bit); wider keys read the
 // wave's bit planes in LDS (plane p_j, bit = the lane), which avoids indexing a register array
 // with a run-time word number.  Unused positions are don't-cares of the replicated live table.
-template <int Wp>
+template <int Wp, bool NARROW = false>
 __device__ __forceinline__ uint32_t row_lint(const uint64_t (&key)[Wp], uint64_t rec, const uint64_t *planes,
                                              int lane) {
     uint32_t L = 0;
-    if (Wp == 1) {
+    if (NARROW) {
+        // at most 32 qubits: the positions are below 32, one 32-bit field extract per bit
+        const uint32_t k = (uint32_t)key[0];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t p = ((uint32_t)(rec >> (16 + 12 * j)) + (uint32_t)j) & 31u;
+            L |= __builtin_amdgcn_ubfe(k, p, 1u) << j;
+        }
+    } else if (Wp == 1) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t sh = (uint32_t)(rec >> (16 + 12 * j)) & 63u;
@@ -339,11 +349,11 @@ __device__ __forceinline__ HitSink<ET, Use, Fetch> sink(Use u, Fetch f) {
 }
 
 // Term range [t0, t0 + len) of chunk group cc for the row (its ladder integer selects it).
-template <int Wp>
+template <int Wp, bool NARROW = false>
 __device__ __forceinline__ void hit_range(const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp], const uint64_t *planes,
                                           int lane, int cc, uint32_t &t0, uint32_t &len) {
     const uint32_t lm = lds.lmask[cc];
-    const uint32_t L = row_lint<Wp>(key, lds.rec[cc], planes, lane) & lm;
+    const uint32_t L = row_lint<Wp, NARROW>(key, lds.rec[cc], planes, lane) & lm;
     const uint32_t lo = lds.iptr[cc][L];
     const uint32_t hi = lm ? (uint32_t)lds.iptr[cc][L + 1] : lds.nterm[cc];
     t0 = lds.term0[cc] + lo;
@@ -373,7 +383,7 @@ __device__ __forceinline__ void deliver(const HamView &h, const ChunkLds<Wp> &ld
         uint32_t t0[NB], len[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            hit_range<Wp>(lds, key, planes, lane, c[b] & (kChunk - 1), t0[b], len[b]);
+            hit_range<Wp, true>(lds, key, planes, lane, c[b] & (kChunk - 1), t0[b], len[b]);
             if (j[b] < 0) len[b] = 0u;
         }
         TermRec<Wp, NARROW, ET> first[NB];
@@ -458,10 +468,22 @@ __device__ __forceinline__ void probe_groups(const SubView &s, const HamView &h,
 // is marked for phase 2 (occ) with the run continued past an occupied home slot (occn); no
 // occupancy bit is read (the slot itself shows whether it is empty), so a column that passes
 // costs one slot read and one that fails costs nothing beyond LDS.
+// hi_done: the wave's rows share their high part and the scan has already dropped the groups
+// that flip it to an absent one, so only the low part is tested (wave-uniform).
 template <int NB>
-__device__ __forceinline__ void part_occupancy(const uint32_t *pf, const uint32_t *lpart, uint32_t prow,
+__device__ __forceinline__ void part_occupancy(const uint32_t *pf, const uint32_t *lpart, uint32_t prow, bool hi_done,
                                                const int (&c)[NB], const bool (&act)[NB], uint64_t &occ,
                                                uint64_t &occn) {
+    if (hi_done) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const uint32_t lo = (prow ^ lpart[c[b] & (kChunk - 1)]) & 0xFFFFu;
+            const bool o = act[b] && ((pf[lo >> 5] >> (lo & 31u)) & 1u);
+            occ |= (uint64_t)o << (c[b] & (kChunk - 1));
+            occn |= (uint64_t)o << (c[b] & (kChunk - 1));
+        }
+        return;
+    }
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const bool o = act[b] && part_pass(pf, prow ^ lpart[c[b] & (kChunk - 1)]);
@@ -508,7 +530,7 @@ __device__ __forceinline__ void resolve_groups(const SubView &s, const HamView &
         int64_t j[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b)
-            j[b] = act[b] ? product_index(pf, pr, s.pna, prow ^ lds.gpart[c[b] & (kChunk - 1)]) : -1;
+            j[b] = act[b] ? (int64_t)product_rank(pf, pr, s.pna, prow ^ lds.gpart[c[b] & (kChunk - 1)]) : -1;
         deliver<Wp, NB, PM>(h, lds, key, planes, lane, c, j, on_hit);
         return;
     }
@@ -607,6 +629,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
     if (bulk && lane == 0)
         lds.whi[threadIdx.x >> 6] = vrows == 0ull ? kEmpty : ((uni_mask >> 16) ? (uni_part >> 16) : kMixed);
     uint32_t blk_hi = kMixed;
+    constexpr int kSB = PM ? kSlotBatchPM : kSlotBatch;  // filter-first phase 2 batch
     for (int64_t g0 = 0; g0 < h.G; g0 += kChunk) {
         const int nc = (int)((h.G - g0) < kChunk ? (h.G - g0) : kChunk);
         __syncthreads();
@@ -721,50 +744,51 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
             }
             // phase 2: the slots of the occupied home slots, lowest group first
             while (__any(occ != 0ull)) {
-                int c[kSlotBatch];
-                bool act[kSlotBatch], nxt[kSlotBatch];
+                int c[kSB];
+                bool act[kSB], nxt[kSB];
 #pragma unroll
-                for (int b = 0; b < kSlotBatch; ++b) {
+                for (int b = 0; b < kSB; ++b) {
                     const int k = occ ? (int)__builtin_ctzll(occ) : -1;
                     occ &= occ - 1ull;
                     act[b] = k >= 0;
                     c[b] = act[b] ? (int)clist[k] : 0;
                     nxt[b] = act[b] && ((occn >> k) & 1ull);
                 }
-                resolve_groups<Wp, kSlotBatch, PM>(s, h, lds, key, hrow, prow, pf, pr, planes, lane, c, act, nxt, on_hit);
+                resolve_groups<Wp, kSB, PM>(s, h, lds, key, hrow, prow, pf, pr, planes, lane, c, act, nxt, on_hit);
             }
             continue;
         }
         if (filter_first) {
             // phase 1: occupancy bits of the live groups' home slots (and of the slot after)
+            constexpr int kOB = PM ? kOccBatchPM : kOccBatch;
             uint64_t occ = 0, occn = 0;
             uint64_t rem = live;
             while (__any(rem != 0ull)) {
-                int c[kOccBatch];
-                bool act[kOccBatch];
+                int c[kOB];
+                bool act[kOB];
 #pragma unroll
-                for (int b = 0; b < kOccBatch; ++b) {
+                for (int b = 0; b < kOB; ++b) {
                     c[b] = rem ? (int)__builtin_ctzll(rem) : -1;
                     rem &= rem - 1ull;
                     act[b] = c[b] >= 0;
                 }
                 if (pf)
-                    part_occupancy<kOccBatch>(pf, lds.gpart, prow, c, act, occ, occn);
+                    part_occupancy<kOB>(pf, lds.gpart, prow, (uni_mask >> 16) != 0u, c, act, occ, occn);
                 else
-                    occupancy<kOccBatch>(s, lds.hash, hrow, c, act, occ, occn);
+                    occupancy<kOB>(s, lds.hash, hrow, c, act, occ, occn);
             }
             // phase 2: the slots of the occupied home slots, lowest group first
             while (__any(occ != 0ull)) {
-                int c[kSlotBatch];
-                bool act[kSlotBatch], nxt[kSlotBatch];
+                int c[kSB];
+                bool act[kSB], nxt[kSB];
 #pragma unroll
-                for (int b = 0; b < kSlotBatch; ++b) {
+                for (int b = 0; b < kSB; ++b) {
                     c[b] = occ ? (int)__builtin_ctzll(occ) : -1;
                     occ &= occ - 1ull;
                     act[b] = c[b] >= 0;
                     nxt[b] = act[b] && ((occn >> c[b]) & 1ull);
                 }
-                resolve_groups<Wp, kSlotBatch, PM>(s, h, lds, key, hrow, prow, pf, pr, planes, lane, c, act, nxt, on_hit);
+                resolve_groups<Wp, kSB, PM>(s, h, lds, key, hrow, prow, pf, pr, planes, lane, c, act, nxt, on_hit);
             }
             continue;
         }
