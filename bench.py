@@ -43,11 +43,15 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload, dtype, nvec, capacity):
-    """HBM bytes per SpMV launch from the committed counter profile of this workload, or None
-    when there is none, it was taken on other kernel sources or with another hash-table size.
-    The profile records FETCH_SIZE and WRITE_SIZE per dispatch (KiB) and the factors that scale
-    them to the bytes a plain copy of known size moves."""
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4  # wave64 VALU instructions/s: 256 CUs x 4 SIMDs, 4 cycles each
+
+
+def stored_traffic(workload, dtype, nvec, capacity, key="hbm_bytes_per_launch"):
+    """HBM bytes per SpMV launch (or, with key="valu_insts_per_launch", VALU wave instructions)
+    from the committed counter profile of this workload, or None when there is none, it was
+    taken on other kernel sources or with another hash-table size.  The profile records
+    FETCH_SIZE and WRITE_SIZE per dispatch (KiB) and the factors that scale them to the bytes a
+    plain copy of known size moves."""
     path = os.path.join(ROOT, "profiles", "k_matvec_%s_%s_nvec%d.md" % (workload, dtype, nvec))
     if not os.path.exists(path):
         return None
@@ -60,7 +64,7 @@ def stored_traffic(workload, dtype, nvec, capacity):
                     vals[k] = v
     if vals.get("source_digest") != kernel_digest() or int(vals.get("capacity", -1)) != capacity:
         return None
-    return float(vals["hbm_bytes_per_launch"])
+    return float(vals[key]) if key in vals else None
 
 
 def calibrate_copy():
@@ -598,6 +602,7 @@ def main():
         "data": "synthetic",
         "config": r["config"],
         "roofline": r["roofline"],
+        "roofline_issue": r["roofline_issue"],
         "work": r["work"],
     }
     if "ground_state" in r:
@@ -705,9 +710,16 @@ def measure_spmv(w, nvec, dtype_name, steps, warmup, max_load, schedule, split=0
                      "traffic": stored_traffic(w.name, dtype_name, nvec, sub.capacity),
                      "bytes_per_launch": balg, "kernel_ms": k_avg, "kernel_ms_min": min(kms),
                      "kernel_source_digest": kernel_digest()},
+        "roofline_issue": None,
         "work": {"probes": probes, "hits": hits, "evaluations": N * op.n_groups,
                  "probes_per_s": probes / (k_avg / 1e3), "evaluations_per_s": N * op.n_groups / (k_avg / 1e3)},
     }
+    # the instruction-issue roofline, from the profiled VALU instruction count of this kernel
+    valu = stored_traffic(w.name, dtype_name, nvec, sub.capacity, key="valu_insts_per_launch")
+    if valu is not None:
+        res["roofline_issue"] = {"bound": "valu_issue", "achieved": valu / (k_avg / 1e3), "peak": VALU_ISSUE_PEAK,
+                                 "unit": "wave instructions/s", "frac": valu / (k_avg / 1e3) / VALU_ISSUE_PEAK,
+                                 "insts_per_launch": valu}
     if solve:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
