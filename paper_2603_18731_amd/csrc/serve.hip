@@ -55,7 +55,8 @@ __device__ __forceinline__ double wsum(double v) {
     return v;
 }
 
-template <int Wp, class ET>
+// PF = 2: the tiles of matrix-free requests on product subspaces (product map); else PF = 1.
+template <int Wp, class ET, int PF = 1>
 __global__ __launch_bounds__(kBlock) void kb_matvec(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles) {
     __shared__ ChunkLds<Wp> lds;
     const Tile t = tiles[blockIdx.x];
@@ -97,9 +98,9 @@ __global__ __launch_bounds__(kBlock) void kb_matvec(const ReqDev *__restrict__ r
         return;
     }
     // the operator's schedule, with the diagonal term formed in the row kernel (no separate pass)
-    matvec_block<Wp, 1, ET, false>(R.s, R.h, dre, nullptr, x, 1, y, 1, 1, (int64_t)t.idx * kBlock, lds,
-                                   (R.sched & QSD_SCHED_SLOT_ORDER) != 0, (R.sched & QSD_SCHED_LOCKSTEP) != 0,
-                                   (R.sched & QSD_SCHED_FILTER_FIRST) != 0);
+    matvec_block<Wp, 1, ET, false, PF>(R.s, R.h, dre, nullptr, x, 1, y, 1, 1, (int64_t)t.idx * kBlock, lds,
+                                       (R.sched & QSD_SCHED_SLOT_ORDER) != 0, (R.sched & QSD_SCHED_LOCKSTEP) != 0,
+                                       (R.sched & QSD_SCHED_FILTER_FIRST) != 0);
 }
 
 // x32 = x (to_f32) or w = w32 (back), over 2048-row tiles
@@ -385,6 +386,7 @@ struct qsd_batch {
     ReqDev *d_reqs = nullptr;
     Tile *d_mv = nullptr, *d_bl = nullptr;  // 256-row and 2048-row tiles
     int n_mv = 0, n_bl = 0;
+    int n_mv_pm = 0;  // the first n_mv_pm row tiles belong to requests that take the product map
     size_t cap_mv = 0, cap_bl = 0;
     double *d_out = nullptr;  // [max_slots][4]
     int64_t *d_spike = nullptr;
@@ -434,7 +436,7 @@ int sync_tables(qsd_batch *b, hipStream_t st) {
     if (!b->dirty) return QSD_OK;
     AllocScope scope(&b->alloc, st);
     std::vector<ReqDev> host(b->max_slots);
-    std::vector<Tile> mv, bl;
+    std::vector<Tile> mv, mvo, bl;
     for (int i = 0; i < b->max_slots; ++i) {
         const auto &S = b->slots[i];
         if (!S.used) {
@@ -443,9 +445,14 @@ int sync_tables(qsd_batch *b, hipStream_t st) {
             continue;
         }
         host[i] = S.d;
-        for (int64_t t = 0; t < (S.d.N + kBlock - 1) / kBlock; ++t) mv.push_back({i, (int)t});
+        // row tiles of matrix-free requests on product subspaces first (they take the product-map
+        // kernel), then the others; no kernel depends on the order of the tiles
+        const bool pm = b->Wp == 1 && !S.d.cptr && S.d.s.prank && !(S.d.sched & QSD_SCHED_HASH_LOOKUP);
+        for (int64_t t = 0; t < (S.d.N + kBlock - 1) / kBlock; ++t) (pm ? mv : mvo).push_back({i, (int)t});
         for (int t = 0; t < S.d.nbt; ++t) bl.push_back({i, t});
     }
+    const int n_pm = (int)mv.size();
+    mv.insert(mv.end(), mvo.begin(), mvo.end());
     if (mv.size() > b->cap_mv) {
         dev_free(b->d_mv);
         b->cap_mv = mv.size() * 2;
@@ -462,17 +469,28 @@ int sync_tables(qsd_batch *b, hipStream_t st) {
     // the host vectors are staged by the runtime before the calls return (pageable copies)
     QSD_CHECK_HIP(hipStreamSynchronize(st));
     b->n_mv = (int)mv.size();
+    b->n_mv_pm = n_pm;
     b->n_bl = (int)bl.size();
     b->dirty = false;
     return QSD_OK;
 }
 
+// The batched SpMV: product-map tiles in one launch (one-word keys), the others in another.
 template <int Wp>
 void launch_bmv(qsd_batch *b, hipStream_t st) {
-    if (b->f32)
-        kb_matvec<Wp, float><<<b->n_mv, kBlock, 0, st>>>(b->d_reqs, b->d_mv);
-    else
-        kb_matvec<Wp, double><<<b->n_mv, kBlock, 0, st>>>(b->d_reqs, b->d_mv);
+    const int np = Wp == 1 ? b->n_mv_pm : 0, no = b->n_mv - np;
+    if (np > 0) {
+        if (b->f32)
+            kb_matvec<1, float, 2><<<np, kBlock, 0, st>>>(b->d_reqs, b->d_mv);
+        else
+            kb_matvec<1, double, 2><<<np, kBlock, 0, st>>>(b->d_reqs, b->d_mv);
+    }
+    if (no > 0) {
+        if (b->f32)
+            kb_matvec<Wp, float><<<no, kBlock, 0, st>>>(b->d_reqs, b->d_mv + np);
+        else
+            kb_matvec<Wp, double><<<no, kBlock, 0, st>>>(b->d_reqs, b->d_mv + np);
+    }
 }
 
 }  // namespace
