@@ -19,6 +19,7 @@
 
 #include "common.h"
 #include "matvec.h"
+#include "rowsort.h"
 
 namespace qsd {
 namespace {
@@ -74,40 +75,15 @@ __global__ __launch_bounds__(kBlock) void k_fill_lower(SubView s, HamView h, con
     }), nullptr, false, true);
 }
 
-// Sort each row's (column, value) pairs by column into the output arrays: one workgroup per
-// row, rank by counting smaller columns (distinct within a row), columns staged in LDS.
-constexpr int kSortLds = 4096;
-
+// Sort each row's entries by column (one workgroup per row; see sort_row_entries).
 template <class ET, class IT, bool CPLX>
-__global__ __launch_bounds__(kBlock) void k_sort_rows(const int64_t *__restrict__ indptr, const int64_t *__restrict__ cols,
-                                                      const typename C2<ET>::T *__restrict__ vals,
-                                                      IT *__restrict__ out_idx, ET *__restrict__ out_val) {
+__global__ __launch_bounds__(kBlock) void k_sort_rows(const int64_t *__restrict__ indptr, int64_t *__restrict__ cols,
+                                                      const typename C2<ET>::T *__restrict__ vals, IT *__restrict__ out_idx,
+                                                      ET *__restrict__ out_val) {
     __shared__ int64_t sc[kSortLds];
     const int64_t row = blockIdx.x;
     const int64_t a = indptr[row], b = indptr[row + 1];
-    const int64_t len = b - a;
-    const bool in_lds = len <= kSortLds;
-    if (in_lds) {
-        for (int64_t e = threadIdx.x; e < len; e += kBlock) sc[e] = cols[a + e];
-        __syncthreads();
-    }
-    for (int64_t e = threadIdx.x; e < len; e += kBlock) {
-        const int64_t c = cols[a + e];
-        int64_t rank = 0;
-        if (in_lds) {
-            for (int64_t f = 0; f < len; ++f) rank += sc[f] < c;
-        } else {
-            for (int64_t f = 0; f < len; ++f) rank += cols[a + f] < c;
-        }
-        out_idx[a + rank] = (IT)c;
-        const typename C2<ET>::T v = vals[a + e];
-        if (CPLX) {
-            out_val[2 * (a + rank)] = v.x;
-            out_val[2 * (a + rank) + 1] = v.y;
-        } else {
-            out_val[a + rank] = v.x;
-        }
-    }
+    sort_row_entries<ET, IT, CPLX>(a, b - a, cols, vals, out_idx, out_val, sc);
 }
 
 __global__ void k_u64_to_i64(const unsigned long long *__restrict__ a, int64_t *__restrict__ b, int64_t n) {
@@ -275,7 +251,7 @@ void free_csr(qsd_csr *c) {
 }
 
 template <class ET>
-void sort_into(qsd_csr *c, const int64_t *cols, const void *vals, hipStream_t st) {
+void sort_into(qsd_csr *c, int64_t *cols, const void *vals, hipStream_t st) {
     const unsigned grid = (unsigned)c->N;
     const auto *v = (const typename C2<ET>::T *)vals;
     if (c->index_type == QSD_INDEX_I32) {

@@ -8,6 +8,7 @@
 #include "device.h"
 #include "engine.h"
 #include "matvec.h"
+#include "rowsort.h"
 #include "spmv.h"
 
 namespace qsd {
@@ -129,42 +130,15 @@ __global__ __launch_bounds__(kBlock) void k_csr_fill(SubView s, HamView h, const
     }), nullptr, false, true);
 }
 
-// Sort each row's entries by column: one workgroup per row; for rows up to kSortLds entries
-// the columns sit in LDS and each thread ranks its elements by counting smaller columns
-// (columns within a row are distinct).  Longer rows rank against global memory.
-constexpr int kSortLds = 4096;
-
+// Sort each row's entries by column (one workgroup per row; see sort_row_entries).
 template <class ET, class IT, bool CPLX>
-__global__ __launch_bounds__(kBlock) void k_csr_sort(const int64_t *__restrict__ indptr,
-                                                     const int64_t *__restrict__ cols,
-                                                     const typename C2<ET>::T *__restrict__ vals,
-                                                     IT *__restrict__ out_idx, ET *__restrict__ out_val) {
+__global__ __launch_bounds__(kBlock) void k_csr_sort(const int64_t *__restrict__ indptr, int64_t *__restrict__ cols,
+                                                     const typename C2<ET>::T *__restrict__ vals, IT *__restrict__ out_idx,
+                                                     ET *__restrict__ out_val) {
     __shared__ int64_t sc[kSortLds];
     const int64_t row = blockIdx.x;
     const int64_t a = indptr[row], b = indptr[row + 1];
-    const int64_t len = b - a;
-    const bool in_lds = len <= kSortLds;
-    if (in_lds) {
-        for (int64_t e = threadIdx.x; e < len; e += kBlock) sc[e] = cols[a + e];
-        __syncthreads();
-    }
-    for (int64_t e = threadIdx.x; e < len; e += kBlock) {
-        const int64_t c = cols[a + e];
-        int64_t rank = 0;
-        if (in_lds) {
-            for (int64_t f = 0; f < len; ++f) rank += sc[f] < c;
-        } else {
-            for (int64_t f = 0; f < len; ++f) rank += cols[a + f] < c;
-        }
-        out_idx[a + rank] = (IT)c;
-        const typename C2<ET>::T v = vals[a + e];
-        if (CPLX) {
-            out_val[2 * (a + rank)] = v.x;
-            out_val[2 * (a + rank) + 1] = v.y;
-        } else {
-            out_val[a + rank] = v.x;
-        }
-    }
+    sort_row_entries<ET, IT, CPLX>(a, b - a, cols, vals, out_idx, out_val, sc);
 }
 
 inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }

@@ -167,3 +167,43 @@ def test_csr_errors():
     A = qsd.CsrMatrix(H)
     with pytest.raises(qsd.QsdError, match="UNSUPPORTED"):
         A.lanczos(block=4)  # block Lanczos is real only
+
+
+@pytest.mark.parametrize("n,wmax", [(13, 7), (14, 7)])
+def test_csr_rows_longer_than_lds(n, wmax):
+    """Rows of 5812 and 9908 entries (every X word of weight 1..7 on the full space of 13 or 14
+    qubits: every row reaches every column of weight distance <= 7), longer than the 4096 columns a
+    row sort holds in LDS: the two-pass and the lower-triangle builds sort them in chunks; sampled
+    rows (first, last, ragged middle) equal the oracle's, structure and dyadic values exactly."""
+    import itertools
+
+    rng = np.random.default_rng(n)
+    terms = []
+    for w in range(1, wmax + 1):
+        for qs in itertools.combinations(range(n), w):
+            terms.append((float(rng.integers(-16, 17) or 1) / 16.0, [(q, 3) for q in qs]))
+    tl = wl.TermList.from_terms(n, terms)
+    keys = osub.ints_to_keys(list(range(1 << n)), 1)
+    say("long rows", n, "qubits,", len(terms), "groups")
+    H = _ham(keys, tl)
+    ck = osub.canonical_keys(keys)
+    rows = np.array([0, 1, 777, (1 << n) // 2, (1 << n) - 1])
+    ipo, co, vo = orw.rows_c(ck, tl, rows)
+    assert (np.diff(ipo) > 4096).all()
+    rows_t = torch.from_numpy(rows).cuda()
+
+    def check(ip, ix, dv, label):
+        a, b = ip[rows_t].cpu().numpy(), ip[rows_t + 1].cpu().numpy()
+        for k in range(len(rows)):
+            np.testing.assert_array_equal(ix[a[k]:b[k]].cpu().numpy().astype(np.int64), co[ipo[k]:ipo[k + 1]],
+                                          err_msg=label)
+            np.testing.assert_array_equal(dv[a[k]:b[k]].cpu().numpy(), vo[ipo[k]:ipo[k + 1]].real, err_msg=label)
+
+    ip, ix, dv = H.to_csr(qsd.INDEX_I32)
+    check(ip, ix, dv, "two-pass")
+    del ip, ix, dv
+    A = qsd.CsrMatrix(H, qsd.INDEX_I64, lower_mirror=True)
+    ip, ix, dv = A.export()
+    check(ip, ix, dv, "lower-triangle")
+    del A, ip, ix, dv
+    torch.cuda.empty_cache()
