@@ -361,8 +361,9 @@ int qsd_matvec(const qsd_ham *h, int32_t nvec, const void *d_x, int64_t ldx, voi
                void *stream);
 
 /* Y_i = H_i X_i for n independent requests in one launch per key width (per chunk of four
- * complex vectors): the row tiles of all requests form one grid, so small subspaces share the
- * GPU instead of each under-filling it.  Per request: hams[i], device vectors xs[i] and ys[i]
+ * complex vectors; requests on product subspaces, which take the product map, in a launch of
+ * their own): the row tiles of all requests form one grid, so small subspaces share the GPU
+ * instead of each under-filling it.  Per request: hams[i], device vectors xs[i] and ys[i]
  * with nvecs[i] (1..16) interleaved vectors (leading dimension nvecs[i]); dtype as for
  * qsd_matvec, the same for all requests and matching every operator (DTYPE otherwise).  Every
  * row is evaluated exactly as by qsd_matvec, so the results are bitwise those of n separate

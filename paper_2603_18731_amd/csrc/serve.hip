@@ -351,12 +351,13 @@ struct MvReq {
     uint32_t sched;  // the operator's QSD_SCHED_* bits (row order and probe mode)
 };
 
-template <int Wp, int NV, class ET, bool CPLX>
+// PF = 2: requests on product subspaces (product map, one-word keys); else PF = 1.
+template <int Wp, int NV, class ET, bool CPLX, int PF = 1>
 __global__ __launch_bounds__(kBlock) void kbm_matvec(const MvReq *__restrict__ reqs, const Tile *__restrict__ tiles) {
     __shared__ ChunkLds<Wp> lds;
     const Tile t = tiles[blockIdx.x];
     const MvReq &R = reqs[t.slot];
-    matvec_block<Wp, NV, ET, CPLX>(R.s, R.h, (const ET *)R.dre, (const ET *)R.dim, (const ET *)R.x, R.ld, (ET *)R.y,
+    matvec_block<Wp, NV, ET, CPLX, PF>(R.s, R.h, (const ET *)R.dre, (const ET *)R.dim, (const ET *)R.x, R.ld, (ET *)R.y,
                                    R.ld, R.nv, (int64_t)t.idx * kBlock, lds, (R.sched & QSD_SCHED_SLOT_ORDER) != 0,
                                    (R.sched & QSD_SCHED_LOCKSTEP) != 0, (R.sched & QSD_SCHED_FILTER_FIRST) != 0);
 }
@@ -764,20 +765,25 @@ extern "C" int qsd_batch_destroy(qsd_batch *b) {
 
 namespace {
 
-template <int Wp, class ET, bool CPLX>
+template <int Wp, class ET, bool CPLX, int PF = 1>
 void launch_bmv_any(int nv_max, int tiles, const MvReq *reqs, const Tile *tl, hipStream_t st) {
     if (nv_max <= 1)
-        kbm_matvec<Wp, 1, ET, CPLX><<<tiles, kBlock, 0, st>>>(reqs, tl);
+        kbm_matvec<Wp, 1, ET, CPLX, PF><<<tiles, kBlock, 0, st>>>(reqs, tl);
     else if (nv_max <= 4 || CPLX)
-        kbm_matvec<Wp, 4, ET, CPLX><<<tiles, kBlock, 0, st>>>(reqs, tl);
+        kbm_matvec<Wp, 4, ET, CPLX, PF><<<tiles, kBlock, 0, st>>>(reqs, tl);
     else
-        kbm_matvec<Wp, 16, ET, CPLX><<<tiles, kBlock, 0, st>>>(reqs, tl);
+        kbm_matvec<Wp, 16, ET, CPLX, PF><<<tiles, kBlock, 0, st>>>(reqs, tl);
 }
 
 template <class ET, bool CPLX>
-void launch_bmv_w(int Wp, int nv_max, int tiles, const MvReq *reqs, const Tile *tl, hipStream_t st) {
+void launch_bmv_w(int Wp, bool pm, int nv_max, int tiles, const MvReq *reqs, const Tile *tl, hipStream_t st) {
     switch (Wp) {
-        case 1: launch_bmv_any<1, ET, CPLX>(nv_max, tiles, reqs, tl, st); break;
+        case 1:
+            if (pm)
+                launch_bmv_any<1, ET, CPLX, 2>(nv_max, tiles, reqs, tl, st);
+            else
+                launch_bmv_any<1, ET, CPLX>(nv_max, tiles, reqs, tl, st);
+            break;
         case 2: launch_bmv_any<2, ET, CPLX>(nv_max, tiles, reqs, tl, st); break;
         case 4: launch_bmv_any<4, ET, CPLX>(nv_max, tiles, reqs, tl, st); break;
         case 8: launch_bmv_any<8, ET, CPLX>(nv_max, tiles, reqs, tl, st); break;
@@ -790,11 +796,12 @@ void launch_bmv_w(int Wp, int nv_max, int tiles, const MvReq *reqs, const Tile *
 namespace {
 
 // The plan of a batched SpMV: request table, tile list (request, row tile) and one launch per
-// (key width, vector chunk); complex vectors go in chunks of four.
+// (key width, vector chunk, product map or not); complex vectors go in chunks of four.
 struct BatchedPlan {
     struct Launch {
         int Wp, nv_max;
         size_t t0, nt;
+        bool pm;  // requests on product subspaces (one-word keys): the product-map kernel
     };
     std::vector<MvReq> reqs;
     std::vector<Tile> tiles;
@@ -818,10 +825,13 @@ int plan_batched(int32_t n, const qsd_ham *const *hams, const void *const *xs, v
     const int chunk = cplx ? 4 : 16;
     for (int Wp : {1, 2, 4, 8, 16}) {
         for (int c0 = 0; c0 < 16; c0 += chunk) {
-            BatchedPlan::Launch L{Wp, 0, P.tiles.size(), 0};
+          for (int pm = (Wp == 1 ? 1 : 0); pm >= 0; --pm) {
+            BatchedPlan::Launch L{Wp, 0, P.tiles.size(), 0, pm != 0};
             for (int i = 0; i < n; ++i) {
                 const qsd_ham *h = hams[i];
                 if (h->Wp != Wp || nvecs[i] <= c0 || h->N == 0) continue;
+                const bool hpm = Wp == 1 && h->s->prank && !(h->schedule & QSD_SCHED_HASH_LOOKUP);
+                if (hpm != (pm != 0)) continue;
                 MvReq R{};
                 R.s = sub_view(h->s);
                 R.h = ham_view(h, f32);
@@ -839,6 +849,7 @@ int plan_batched(int32_t n, const qsd_ham *const *hams, const void *const *xs, v
             }
             L.nt = P.tiles.size() - L.t0;
             if (L.nt > 0) P.launches.push_back(L);
+          }
         }
     }
     if (P.tiles.size() > (size_t)INT32_MAX) return fail(QSD_ERR_CAPACITY, "too many row tiles");
@@ -854,10 +865,10 @@ int run_batched(const BatchedPlan &P, int32_t dtype, MvReq *d_reqs, Tile *d_tile
     for (const auto &L : P.launches) {
         const Tile *tl = d_tiles + L.t0;
         switch (dtype) {
-            case QSD_F64: launch_bmv_w<double, false>(L.Wp, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
-            case QSD_F32: launch_bmv_w<float, false>(L.Wp, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
-            case QSD_C128: launch_bmv_w<double, true>(L.Wp, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
-            case QSD_C64: launch_bmv_w<float, true>(L.Wp, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
+            case QSD_F64: launch_bmv_w<double, false>(L.Wp, L.pm, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
+            case QSD_F32: launch_bmv_w<float, false>(L.Wp, L.pm, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
+            case QSD_C128: launch_bmv_w<double, true>(L.Wp, L.pm, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
+            case QSD_C64: launch_bmv_w<float, true>(L.Wp, L.pm, L.nv_max, (int)L.nt, d_reqs, tl, st); break;
         }
     }
     if (hipGetLastError() != hipSuccess) return fail(QSD_ERR_HIP, "batched matvec launch failed");
