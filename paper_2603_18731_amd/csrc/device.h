@@ -50,13 +50,16 @@ __device__ __forceinline__ bool part_pass(const uint32_t *pf, uint32_t p) {
 // product of its low parts (pna of them) and high parts, the string (l, h) sits at
 // rank(h) * pna + rank(l), each rank read off a filter as the set bits below the part's own.
 // pf / pr are the filters and their word prefix counts (LDS or global copies).
+// Rank of a part among the parts that occur (the set bits of its filter below its own bit);
+// `half` 0 = low parts, 1 = high parts.
+__device__ __forceinline__ uint32_t part_rank(const uint32_t *pf, const uint16_t *pr, int half, uint32_t q) {
+    const uint32_t w = (uint32_t)half * (kPartWords / 2) + (q >> 5);
+    return (uint32_t)pr[w] + (uint32_t)__popc(pf[w] & ((1u << (q & 31u)) - 1u));
+}
+
 __device__ __forceinline__ uint32_t product_rank(const uint32_t *pf, const uint16_t *pr, uint32_t pna, uint32_t p) {
     // the index of a string known to be present (both parts occur)
-    const uint32_t lo = p & 0xFFFFu, hi = p >> 16;
-    const uint32_t rl = (uint32_t)pr[lo >> 5] + (uint32_t)__popc(pf[lo >> 5] & ((1u << (lo & 31u)) - 1u));
-    const uint32_t rh = (uint32_t)pr[(kPartWords / 2) + (hi >> 5)] +
-                        (uint32_t)__popc(pf[(kPartWords / 2) + (hi >> 5)] & ((1u << (hi & 31u)) - 1u));
-    return rh * pna + rl;
+    return part_rank(pf, pr, 1, p >> 16) * pna + part_rank(pf, pr, 0, p & 0xFFFFu);
 }
 
 __device__ __forceinline__ int64_t product_index(const uint32_t *pf, const uint16_t *pr, uint32_t pna, uint32_t p) {

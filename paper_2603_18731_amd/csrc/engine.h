@@ -86,19 +86,12 @@ struct C2<float> {
 // One-word keys are shifted in registers (one 64-bit shift per bit); wider keys read the
 // wave's bit planes in LDS (plane p_j, bit = the lane), which avoids indexing a register array
 // with a run-time word number.  Unused positions are don't-cares of the replicated live table.
-template <int Wp, bool NARROW = false>
+// (Product-map kernels take the positions decoded, see hit_range_pm.)
+template <int Wp>
 __device__ __forceinline__ uint32_t row_lint(const uint64_t (&key)[Wp], uint64_t rec, const uint64_t *planes,
                                              int lane) {
     uint32_t L = 0;
-    if (NARROW) {
-        // at most 32 qubits: the positions are below 32, one 32-bit field extract per bit
-        const uint32_t k = (uint32_t)key[0];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t p = ((uint32_t)(rec >> (16 + 12 * j)) + (uint32_t)j) & 31u;
-            L |= __builtin_amdgcn_ubfe(k, p, 1u) << j;
-        }
-    } else if (Wp == 1) {
+    if (Wp == 1) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t sh = (uint32_t)(rec >> (16 + 12 * j)) & 63u;
@@ -154,8 +147,22 @@ __device__ __forceinline__ uint64_t sliced_table(uint32_t T, uint64_t a, uint64_
 // every wave's rows.
 template <int Wp>
 struct ChunkLds {
-    uint64_t hash[kChunk];
-    uint64_t mask[kChunk][Wp];
+    // Hash-table kernels keep the groups' hashes and flip masks here.  Product-map kernels probe
+    // no table; they keep the decoded ladder positions and the ranks of the block's shared high
+    // part through each group's flips instead.
+    union alignas(16) {
+        struct {
+            uint64_t hash[kChunk];
+            uint64_t mask[kChunk][Wp];
+        } t;
+        struct {
+            // packed part indices of the flips | rank of the high part reached times the number
+            // of low parts (when the block's rows share their high part)
+            uint2 gh[kChunk];
+            // qubits of ladder bits 0..3 (5 bits each) | ladder mask << 20, first term
+            uint2 rt[kChunk];
+        } m;
+    } u;
     uint64_t rec[kChunk];                // scan records (ladder positions for the hit ranges)
     uint32_t term0[kChunk];
     uint32_t nterm[kChunk];
@@ -349,24 +356,42 @@ __device__ __forceinline__ HitSink<ET, Use, Fetch> sink(Use u, Fetch f) {
 }
 
 // Term range [t0, t0 + len) of chunk group cc for the row (its ladder integer selects it).
-template <int Wp, bool NARROW = false>
+template <int Wp>
 __device__ __forceinline__ void hit_range(const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp], const uint64_t *planes,
                                           int lane, int cc, uint32_t &t0, uint32_t &len) {
     const uint32_t lm = lds.lmask[cc];
-    const uint32_t L = row_lint<Wp, NARROW>(key, lds.rec[cc], planes, lane) & lm;
+    const uint32_t L = row_lint<Wp>(key, lds.rec[cc], planes, lane) & lm;
     const uint32_t lo = lds.iptr[cc][L];
     const uint32_t hi = lm ? (uint32_t)lds.iptr[cc][L + 1] : lds.nterm[cc];
     t0 = lds.term0[cc] + lo;
     len = hi - lo;
 }
 
+// The same in product-map kernels (strings of at most 32 qubits, k = the row's bits): the ladder
+// positions, the ladder mask and the first term come in one 8-byte record, and a group without
+// ladder bits keeps its term count in its first two range pointers; no branch.
+template <int Wp>
+__device__ __forceinline__ void hit_range_pm(const ChunkLds<Wp> &lds, uint32_t k, int cc, uint32_t &t0,
+                                             uint32_t &len) {
+    const uint2 rt = lds.u.m.rt[cc];
+    uint32_t L = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) L |= __builtin_amdgcn_ubfe(k, __builtin_amdgcn_ubfe(rt.x, 5u * j, 5u), 1u) << j;
+    const uint32_t lm = __builtin_amdgcn_ubfe(rt.x, 20u, 4u);
+    L &= lm;
+    const uint32_t a = lds.iptr[cc][L], b = lds.iptr[cc][L + 1];
+    const uint32_t lo = lm ? a : 0u, hi = lm ? b : (a | (b << 16));
+    t0 = rt.y + lo;
+    len = hi - lo;
+}
+
 // Fetch, evaluate and use a batch whose columns are resolved (j[b] < 0: no hit).  A lane
 // without a hit in the batch loads nothing.  Otherwise x_j (or what the sink fetches) is
-// requested for every slot; with NARROW (32-bit term masks, strings of at most 32 qubits) the
-// term ranges of all slots are read and the first term of each is loaded before any is summed
-// (term 0 for a slot without a hit, so no load needs a branch; an off-diagonal group always has
-// a term).  The slots are summed and used in increasing b.
-template <int Wp, int NB, bool NARROW, class Sink>
+// requested for every slot; in product-map kernels (PM: strings of at most 32 qubits, so 32-bit
+// term masks) the term ranges of all slots are read and the first term of each is loaded before
+// any is summed (term 0 for a slot without a hit, so no load needs a branch; an off-diagonal
+// group always has a term).  The slots are summed and used in increasing b.
+template <int Wp, int NB, bool PM, class Sink>
 __device__ __forceinline__ void deliver(const HamView &h, const ChunkLds<Wp> &lds, const uint64_t (&key)[Wp],
                                         const uint64_t *planes, int lane, const int (&c)[NB], const int64_t (&j)[NB],
                                         Sink &on_hit) {
@@ -378,22 +403,22 @@ __device__ __forceinline__ void deliver(const HamView &h, const ChunkLds<Wp> &ld
     decltype(on_hit.fetch(0)) pre[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) pre[b] = on_hit.fetch(j[b]);
-    if constexpr (NARROW) {
+    if constexpr (PM) {
         // 32-bit masks: the records are small enough to hold one per slot
         uint32_t t0[NB], len[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            hit_range<Wp, true>(lds, key, planes, lane, c[b] & (kChunk - 1), t0[b], len[b]);
+            hit_range_pm<Wp>(lds, (uint32_t)key[0], c[b] & (kChunk - 1), t0[b], len[b]);
             if (j[b] < 0) len[b] = 0u;
         }
-        TermRec<Wp, NARROW, ET> first[NB];
+        TermRec<Wp, true, ET> first[NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) load_term<Wp, NARROW, ET>(h, len[b] ? t0[b] : 0u, first[b]);
+        for (int b = 0; b < NB; ++b) load_term<Wp, true, ET>(h, len[b] ? t0[b] : 0u, first[b]);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             if (!len[b]) continue;
             ET vre, vim;
-            if (range_sum<Wp, NARROW, ET>(h, key, t0[b], len[b], first[b], vre, vim))
+            if (range_sum<Wp, true, ET>(h, key, t0[b], len[b], first[b], vre, vim))
                 on_hit.use(j[b], vre, vim, pre[b]);
         }
     } else {
@@ -415,14 +440,26 @@ template <int Wp, int NB, bool PM, class OnHit>
 __device__ __forceinline__ void probe_groups(const SubView &s, const HamView &h, const ChunkLds<Wp> &lds,
                                              const uint64_t (&key)[Wp],
                                              uint64_t hrow, uint32_t prow, const uint32_t *pf, const uint16_t *pr,
-                                             const uint64_t *planes, int lane, const int (&c)[NB],
+                                             bool hr, const uint64_t *planes, int lane, const int (&c)[NB],
                                              const bool (&act)[NB], OnHit &on_hit) {
     if (PM) {
-        // product map: the column's index comes from its parts' ranks, no table access
+        // product map: the column's index comes from its parts' ranks, no table access.  With
+        // hr (the block's rows share their high part) the high rank comes with the chunk and the
+        // scan has dropped the groups whose high part does not occur, so only the low part is
+        // tested here.
         int64_t j[NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-            j[b] = act[b] ? product_index(pf, pr, s.pna, prow ^ lds.gpart[c[b] & (kChunk - 1)]) : -1;
+        for (int b = 0; b < NB; ++b) {
+            const int cc = c[b] & (kChunk - 1);
+            const uint2 gh = lds.u.m.gh[cc];
+            const uint32_t p = prow ^ gh.x, lo = p & 0xFFFFu;
+            int64_t jb;
+            if (hr)
+                jb = ((pf[lo >> 5] >> (lo & 31u)) & 1u) ? (int64_t)(gh.y + part_rank(pf, pr, 0, lo)) : (int64_t)-1;
+            else
+                jb = product_index(pf, pr, s.pna, p);
+            j[b] = act[b] ? jb : -1;
+        }
         deliver<Wp, NB, PM>(h, lds, key, planes, lane, c, j, on_hit);
         return;
     }
@@ -433,7 +470,7 @@ __device__ __forceinline__ void probe_groups(const SubView &s, const HamView &h,
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         a[b] = act[b] && (!pf || part_pass(pf, prow ^ lds.gpart[c[b] & (kChunk - 1)]));
-        hh[b] = hrow ^ lds.hash[c[b] & (kChunk - 1)];
+        hh[b] = hrow ^ lds.u.t.hash[c[b] & (kChunk - 1)];
         pos[b] = (uint32_t)hh[b] & s.cmask;
         word[b] = s.bitmap[a[b] ? (pos[b] >> 5) : 0u];
     }
@@ -452,7 +489,7 @@ __device__ __forceinline__ void probe_groups(const SubView &s, const HamView &h,
         const uint32_t tag = (uint32_t)(hh[b] >> 32);
         uint64_t col[Wp];
 #pragma unroll
-        for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ lds.mask[c[b]][w];
+        for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ lds.u.t.mask[c[b]][w];
         if ((uint32_t)(slot[b] >> 32) == tag) j[b] = slot_match<Wp>(s, slot[b], 0u, col);
         if (j[b] < 0) {
             // the home slot held another string: follow the run while slots stay occupied
@@ -523,14 +560,20 @@ template <int Wp, int NB, bool PM, class OnHit>
 __device__ __forceinline__ void resolve_groups(const SubView &s, const HamView &h, const ChunkLds<Wp> &lds,
                                                const uint64_t (&key)[Wp],
                                                uint64_t hrow, uint32_t prow, const uint32_t *pf, const uint16_t *pr,
-                                               const uint64_t *planes, int lane, const int (&c)[NB],
+                                               bool hr, const uint64_t *planes, int lane, const int (&c)[NB],
                                                const bool (&act)[NB], const bool (&next)[NB], OnHit &on_hit) {
     if (PM) {
         // product map: a group marked here passed both part filters, so its column is present
+        // (with hr the high rank comes with the chunk)
         int64_t j[NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-            j[b] = act[b] ? (int64_t)product_rank(pf, pr, s.pna, prow ^ lds.gpart[c[b] & (kChunk - 1)]) : -1;
+        for (int b = 0; b < NB; ++b) {
+            const int cc = c[b] & (kChunk - 1);
+            const uint2 gh = lds.u.m.gh[cc];
+            const uint32_t p = prow ^ gh.x;
+            const uint32_t r = hr ? gh.y + part_rank(pf, pr, 0, p & 0xFFFFu) : product_rank(pf, pr, s.pna, p);
+            j[b] = act[b] ? (int64_t)r : -1;
+        }
         deliver<Wp, NB, PM>(h, lds, key, planes, lane, c, j, on_hit);
         return;
     }
@@ -538,7 +581,7 @@ __device__ __forceinline__ void resolve_groups(const SubView &s, const HamView &
     uint32_t pos[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        hh[b] = hrow ^ lds.hash[c[b] & (kChunk - 1)];
+        hh[b] = hrow ^ lds.u.t.hash[c[b] & (kChunk - 1)];
         pos[b] = (uint32_t)hh[b] & s.cmask;
         slot[b] = s.slots[act[b] ? pos[b] : 0u];  // unconditional, as above
     }
@@ -551,7 +594,7 @@ __device__ __forceinline__ void resolve_groups(const SubView &s, const HamView &
         const uint32_t tag = (uint32_t)(hh[b] >> 32);
         uint64_t col[Wp];
 #pragma unroll
-        for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ lds.mask[c[b]][w];
+        for (int w = 0; w < Wp; ++w) col[w] = key[w] ^ lds.u.t.mask[c[b]][w];
         if ((uint32_t)(slot[b] >> 32) == tag) j[b] = slot_match<Wp>(s, slot[b], 0u, col);
         if (j[b] < 0 && next[b]) j[b] = probe_from<Wp>(s, (pos[b] + 1) & s.cmask, 1u, tag, col);
     }
@@ -653,19 +696,42 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                 if (__ballot(lv) == 0ull) continue;
             }
         }
+        // product-map kernels: whether the block's rows share their high part (then every
+        // group's column has one high part for the whole block, and its rank comes with the chunk)
+        const bool hr = PM && blk_hi < (1u << kPartBits);
         for (int c = threadIdx.x; c < nc; c += kBlock) {
             const int64_t g = g0 + c;
-            lds.hash[c] = h.g_hash[g];
-#pragma unroll
-            for (int w = 0; w < Wp; ++w) lds.mask[c][w] = h.g_mask[g * Wp + w];
             const uint32_t info = h.g_info[g];
-            lds.rec[c] = h.g_scan[g];
-            lds.term0[c] = h.g_term0[g];
-            lds.nterm[c] = h.g_nterm[g];
-            lds.lmask[c] = (info & kInfoLadder) ? ((1u << (info & kInfoKMask)) - 1u) : 0u;
+            const uint32_t lm = (info & kInfoLadder) ? ((1u << (info & kInfoKMask)) - 1u) : 0u;
+            if constexpr (PM) {
+                const uint64_t rec = h.g_scan[g];
+                const uint32_t gp = h.g_part[g];
+                uint32_t pk = lm << 20;
 #pragma unroll
-            for (int q = 0; q < kIptr; ++q) lds.iptr[c][q] = h.g_iptr[g * kIptr + q];
-            lds.gpart[c] = pf ? h.g_part[g] : 0u;
+                for (int j = 0; j < 4; ++j) pk |= (((uint32_t)(rec >> (16 + 12 * j)) + (uint32_t)j) & 31u) << (5 * j);
+                lds.u.m.rt[c] = make_uint2(pk, h.g_term0[g]);
+                lds.u.m.gh[c] = make_uint2(gp, hr ? part_rank(pf, pr, 1, blk_hi ^ (gp >> 16)) * s.pna : 0u);
+                if (lm) {
+#pragma unroll
+                    for (int q = 0; q < kIptr; ++q) lds.iptr[c][q] = h.g_iptr[g * kIptr + q];
+                } else {
+                    const uint32_t nt = h.g_nterm[g];
+                    lds.iptr[c][0] = (uint16_t)(nt & 0xFFFFu);
+                    lds.iptr[c][1] = (uint16_t)(nt >> 16);
+                }
+                lds.gpart[c] = gp;
+            } else {
+                lds.u.t.hash[c] = h.g_hash[g];
+#pragma unroll
+                for (int w = 0; w < Wp; ++w) lds.u.t.mask[c][w] = h.g_mask[g * Wp + w];
+                lds.rec[c] = h.g_scan[g];
+                lds.term0[c] = h.g_term0[g];
+                lds.nterm[c] = h.g_nterm[g];
+                lds.lmask[c] = lm;
+#pragma unroll
+                for (int q = 0; q < kIptr; ++q) lds.iptr[c][q] = h.g_iptr[g * kIptr + q];
+                lds.gpart[c] = pf ? h.g_part[g] : 0u;
+            }
         }
         // scan: lane l evaluates group g0 + l for the wave's 64 rows, then the masks are
         // transposed to one live-group mask per row
@@ -726,7 +792,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                 uint32_t pos[kOccBatch], word[kOccBatch];
 #pragma unroll
                 for (int b = 0; b < kOccBatch; ++b) {
-                    pos[b] = (uint32_t)(hrow ^ lds.hash[c[b] & (kChunk - 1)]) & s.cmask;
+                    pos[b] = (uint32_t)(hrow ^ lds.u.t.hash[c[b] & (kChunk - 1)]) & s.cmask;
                     word[b] = c[b] >= 0 ? s.bitmap[pos[b] >> 5] : 0u;  // uniform condition
                 }
 #pragma unroll
@@ -754,7 +820,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                     c[b] = act[b] ? (int)clist[k] : 0;
                     nxt[b] = act[b] && ((occn >> k) & 1ull);
                 }
-                resolve_groups<Wp, kSB, PM>(s, h, lds, key, hrow, prow, pf, pr, planes, lane, c, act, nxt, on_hit);
+                resolve_groups<Wp, kSB, PM>(s, h, lds, key, hrow, prow, pf, pr, hr, planes, lane, c, act, nxt, on_hit);
             }
             continue;
         }
@@ -775,7 +841,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                 if (pf)
                     part_occupancy<kOB>(pf, lds.gpart, prow, (uni_mask >> 16) != 0u, c, act, occ, occn);
                 else
-                    occupancy<kOB>(s, lds.hash, hrow, c, act, occ, occn);
+                    occupancy<kOB>(s, lds.u.t.hash, hrow, c, act, occ, occn);
             }
             // phase 2: the slots of the occupied home slots, lowest group first
             while (__any(occ != 0ull)) {
@@ -788,7 +854,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                     act[b] = c[b] >= 0;
                     nxt[b] = act[b] && ((occn >> c[b]) & 1ull);
                 }
-                resolve_groups<Wp, kSB, PM>(s, h, lds, key, hrow, prow, pf, pr, planes, lane, c, act, nxt, on_hit);
+                resolve_groups<Wp, kSB, PM>(s, h, lds, key, hrow, prow, pf, pr, hr, planes, lane, c, act, nxt, on_hit);
             }
             continue;
         }
@@ -802,7 +868,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                     todo &= todo - 1ull;
                     act[b] = c[b] >= 0 && ((live >> c[b]) & 1ull);
                 }
-                probe_groups<Wp, kLockBatch, PM>(s, h, lds, key, hrow, prow, pf, pr, planes, lane, c, act, on_hit);
+                probe_groups<Wp, kLockBatch, PM>(s, h, lds, key, hrow, prow, pf, pr, hr, planes, lane, c, act, on_hit);
             }
             continue;
         }
@@ -819,7 +885,7 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
             bool act[kProbeBatch];
 #pragma unroll
             for (int b = 0; b < kProbeBatch; ++b) act[b] = c[b] >= 0;
-            probe_groups<Wp, kProbeBatch, PM>(s, h, lds, key, hrow, prow, pf, pr, planes, lane, c, act, on_hit);
+            probe_groups<Wp, kProbeBatch, PM>(s, h, lds, key, hrow, prow, pf, pr, hr, planes, lane, c, act, on_hit);
         }
     }
 }

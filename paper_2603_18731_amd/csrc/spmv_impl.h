@@ -22,6 +22,8 @@ inline unsigned grid_for(int64_t n, int per_block) { return (unsigned)((n + per_
 // its index mod 8) write y = d x for the rows without off-diagonal elements in canonical order,
 // the rest take the slot-order tiles and write only the rows with elements; no row is written
 // twice, and each row's value is formed with the same operations as in every other schedule.
+// Product-map kernels are never split (nd = 0: their rows find columns without the table, so a
+// slot order gains them nothing), which drops the split's per-hit test from them.
 // (Single-vector kernels for up to four key words are held to five waves per SIMD.)
 template <int Wp, int NV, class ET, bool CPLX, int PF>
 __global__ __launch_bounds__(kBlock, Wp <= 4 && NV == 1 ? 5 : 1) void k_matvec(
@@ -37,7 +39,7 @@ __global__ __launch_bounds__(kBlock, Wp <= 4 && NV == 1 ? 5 : 1) void k_matvec(
     const int64_t row0 = tile_index(blockIdx.x - nd, gridDim.x - nd, (sched & QSD_SCHED_XCD_REMAP) != 0) * kBlock;
     matvec_block<Wp, NV, ET, CPLX, PF>(s, h, dre, dim, x, ldx, y, ldy, nvec, row0, lds,
                                        (sched & QSD_SCHED_SLOT_ORDER) != 0, (sched & QSD_SCHED_LOCKSTEP) != 0,
-                                       (sched & QSD_SCHED_FILTER_FIRST) != 0, nd > 0);
+                                       (sched & QSD_SCHED_FILTER_FIRST) != 0, PF != 2 && nd > 0);
 }
 
 template <int Wp, int NV, class ET, bool CPLX>
@@ -53,9 +55,9 @@ void launch_mv(const qsd_ham *h, const void *x, int64_t ldx, void *y, int64_t ld
     // subspaces
     if constexpr (Wp == 1) {
         if (h->s->prank && !(h->schedule & QSD_SCHED_HASH_LOOKUP)) {
-            k_matvec<Wp, NV, ET, CPLX, 2><<<nd + tiles, kBlock, 0, st>>>(sub_view(h->s), ham_view(h, f32), dre, dim,
-                                                                        (const ET *)x, ldx, (ET *)y, ldy, nvec,
-                                                                        h->schedule, h->rowbits, nd);
+            k_matvec<Wp, NV, ET, CPLX, 2><<<tiles, kBlock, 0, st>>>(sub_view(h->s), ham_view(h, f32), dre, dim,
+                                                                   (const ET *)x, ldx, (ET *)y, ldy, nvec,
+                                                                   h->schedule, h->rowbits, 0u);
             return;
         }
     }
