@@ -107,24 +107,58 @@ __device__ __forceinline__ uint32_t row_lint(const uint64_t (&key)[Wp], uint64_t
     return L;
 }
 
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
-    const uint32_t lo = __shfl_xor((unsigned)v, m, 64);
-    const uint32_t hi = __shfl_xor((unsigned)(v >> 32), m, 64);
+// A 32-bit word of lane (lane ^ SH), without the LDS crossbar: half-wave and row swaps
+// (permlane swaps) for SH = 32 and 16, row rotations and quad permutations (DPP) below.
+template <int SH>
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t x, int lane) {
+    if constexpr (SH == 32) {
+        // vdst's upper half trades places with src0's lower half
+        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        return lane < 32 ? r[1] : r[0];
+    } else if constexpr (SH == 16) {
+        // vdst's odd rows of 16 trade places with src0's even rows
+        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    } else if constexpr (SH == 8) {
+        return __builtin_amdgcn_update_dpp(0u, x, 0x128, 0xF, 0xF, false);  // row_ror:8
+    } else if constexpr (SH == 4) {
+        // lane l of a row of 16 reads lane l - 4 (row_ror:4) or l + 4 (row_ror:12)
+        const uint32_t dn = __builtin_amdgcn_update_dpp(0u, x, 0x124, 0xF, 0xF, false);
+        const uint32_t up = __builtin_amdgcn_update_dpp(0u, x, 0x12C, 0xF, 0xF, false);
+        return (lane & 4) ? dn : up;
+    } else if constexpr (SH == 2) {
+        return __builtin_amdgcn_update_dpp(0u, x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    } else {
+        return __builtin_amdgcn_update_dpp(0u, x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    }
+}
+
+template <int SH>
+__device__ __forceinline__ uint64_t lane_xor64(uint64_t v, int lane) {
+    const uint32_t lo = lane_xor32<SH>((uint32_t)v, lane);
+    const uint32_t hi = lane_xor32<SH>((uint32_t)(v >> 32), lane);
     return ((uint64_t)hi << 32) | lo;
 }
 
+template <int K>
+__device__ __forceinline__ uint64_t transpose_stage(uint64_t x, int lane) {
+    constexpr int sh = 32 >> K;
+    constexpr uint64_t M[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                               0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+    const uint64_t y = lane_xor64<sh>(x, lane);
+    return (lane & sh) ? ((x & ~M[K]) | ((y & ~M[K]) >> sh)) : ((x & M[K]) | ((y & M[K]) << sh));
+}
+
 // 64 x 64 bit transpose across a wave: on return, bit j of lane i's word is bit i of lane j's
-// input word.  Six butterfly stages; every lane of the wave must take part.
+// input word.  Six butterfly stages, each exchanging words between lanes l and l ^ sh; every
+// lane of the wave must take part.
 __device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, int lane) {
-    const uint64_t M[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
-                           0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const int sh = 32 >> k;
-        const uint64_t y = shfl_xor64(x, sh);
-        x = (lane & sh) ? ((x & ~M[k]) | ((y & ~M[k]) >> sh)) : ((x & M[k]) | ((y & M[k]) << sh));
-    }
-    return x;
+    x = transpose_stage<0>(x, lane);
+    x = transpose_stage<1>(x, lane);
+    x = transpose_stage<2>(x, lane);
+    x = transpose_stage<3>(x, lane);
+    x = transpose_stage<4>(x, lane);
+    return transpose_stage<5>(x, lane);
 }
 
 // Bit-sliced live test: bit r of the result = T[L_r], L_r = (a_r, b_r, c_r, d_r) as bits 0..3,
