@@ -405,9 +405,8 @@ __device__ __forceinline__ void hit_range(const ChunkLds<Wp> &lds, const uint64_
 // positions, the ladder mask and the first term come in one 8-byte record, and a group without
 // ladder bits keeps its term count in its first two range pointers; no branch.
 template <int Wp>
-__device__ __forceinline__ void hit_range_pm(const ChunkLds<Wp> &lds, uint32_t k, int cc, uint32_t &t0,
+__device__ __forceinline__ void hit_range_rt(const ChunkLds<Wp> &lds, uint32_t k, int cc, uint2 rt, uint32_t &t0,
                                              uint32_t &len) {
-    const uint2 rt = lds.u.m.rt[cc];
     uint32_t L = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) L |= __builtin_amdgcn_ubfe(k, __builtin_amdgcn_ubfe(rt.x, 5u * j, 5u), 1u) << j;
@@ -417,6 +416,11 @@ __device__ __forceinline__ void hit_range_pm(const ChunkLds<Wp> &lds, uint32_t k
     const uint32_t lo = lm ? a : 0u, hi = lm ? b : (a | (b << 16));
     t0 = rt.y + lo;
     len = hi - lo;
+}
+template <int Wp>
+__device__ __forceinline__ void hit_range_pm(const ChunkLds<Wp> &lds, uint32_t k, int cc, uint32_t &t0,
+                                             uint32_t &len) {
+    hit_range_rt<Wp>(lds, k, cc, lds.u.m.rt[cc], t0, len);
 }
 
 // Fetch, evaluate and use a batch whose columns are resolved (j[b] < 0: no hit).  A lane
@@ -633,6 +637,69 @@ __device__ __forceinline__ void resolve_groups(const SubView &s, const HamView &
         if (j[b] < 0 && next[b]) j[b] = probe_from<Wp>(s, (pos[b] + 1) & s.cmask, 1u, tag, col);
     }
     deliver<Wp, NB, PM>(h, lds, key, planes, lane, c, j, on_hit);
+}
+
+// Filter-first phase 2 of product-map kernels, software-pipelined: while one batch's loads (x_j
+// and the first term of each hit) are in flight, the next batch's groups are popped and their
+// records and columns read from LDS.  `occ` holds the chunk's groups whose columns are present;
+// every lane still sums and uses its hits in increasing group order, exactly as resolve_groups
+// does.
+template <int Wp, int NB, class OnHit>
+__device__ __forceinline__ void pm_phase2(const SubView &s, const HamView &h, const ChunkLds<Wp> &lds,
+                                          const uint64_t (&key)[Wp], uint32_t prow, const uint32_t *pf,
+                                          const uint16_t *pr, bool hr, uint64_t occ, OnHit &on_hit) {
+    using ET = typename OnHit::value_type;
+    const uint32_t k = (uint32_t)key[0];
+    // pops the next NB groups: chunk index, column (-1: none) and term record
+    auto next = [&](int (&cb)[NB], int64_t (&jb)[NB], uint2 (&rb)[NB]) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int g = occ ? (int)__builtin_ctzll(occ) : -1;
+            occ &= occ - 1ull;
+            const int cc = g < 0 ? 0 : g;
+            const uint2 gh = lds.u.m.gh[cc];
+            rb[b] = lds.u.m.rt[cc];
+            const uint32_t p = prow ^ gh.x;
+            const uint32_t r = hr ? gh.y + part_rank(pf, pr, 0, p & 0xFFFFu) : product_rank(pf, pr, s.pna, p);
+            cb[b] = cc;
+            jb[b] = g >= 0 ? (int64_t)r : (int64_t)-1;
+        }
+    };
+    int c[NB];
+    int64_t j[NB];
+    uint2 rt[NB];
+    next(c, j, rt);
+    while (__any(j[0] >= 0)) {  // a batch's slots fill in order: slot 0 empty = nothing left
+        decltype(on_hit.fetch(0)) pre[NB];
+        uint32_t t0[NB], len[NB];
+        TermRec<Wp, true, ET> first[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) pre[b] = on_hit.fetch(j[b]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            hit_range_rt<Wp>(lds, k, c[b], rt[b], t0[b], len[b]);
+            if (j[b] < 0) len[b] = 0u;
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) load_term<Wp, true, ET>(h, len[b] ? t0[b] : 0u, first[b]);
+        int cn[NB];
+        int64_t jn[NB];
+        uint2 rn[NB];
+        next(cn, jn, rn);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (!len[b]) continue;
+            ET vre, vim;
+            if (range_sum<Wp, true, ET>(h, key, t0[b], len[b], first[b], vre, vim))
+                on_hit.use(j[b], vre, vim, pre[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            c[b] = cn[b];
+            j[b] = jn[b];
+            rt[b] = rn[b];
+        }
+    }
 }
 
 // Walks all groups for the lane's row and hands on_hit (a HitSink) every probe whose
@@ -876,6 +943,11 @@ __device__ __forceinline__ void row_engine(const SubView &s, const HamView &h, c
                     part_occupancy<kOB>(pf, lds.gpart, prow, (uni_mask >> 16) != 0u, c, act, occ, occn);
                 else
                     occupancy<kOB>(s, lds.u.t.hash, hrow, c, act, occ, occn);
+            }
+            if constexpr (PM) {
+                // phase 2: the columns of the groups that passed, lowest group first
+                pm_phase2<Wp, kSB>(s, h, lds, key, prow, pf, pr, hr, occ, on_hit);
+                continue;
             }
             // phase 2: the slots of the occupied home slots, lowest group first
             while (__any(occ != 0ull)) {
