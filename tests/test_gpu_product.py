@@ -119,3 +119,35 @@ def test_product_wide_spmm_and_solver():
     e_tab, _, _ = Hr.lanczos(tol=1e-10, max_iter=200)
     say("energies", e_map, e_tab)
     assert e_map == e_tab
+
+
+def test_product_group_over_65535_terms():
+    """A group too long for 16-bit range pointers (X0 X1 times 70 000 distinct Z strings, so no
+    ladder integer) beside ladder, projector and diagonal terms: the product-map kernel keeps such
+    a group's term count split over its first two range pointers; every schedule, with the map
+    and through the table, equals the oracle bit for bit (dyadic data)."""
+    _, keys = c3_parts(40, 30)
+    rng = np.random.default_rng(65536)
+    masks = np.unique(rng.integers(1, 1 << 30, size=72_000, dtype=np.int64))[:70_000] << 2
+    assert masks.shape[0] == 70_000
+    terms = []
+    for m in masks.tolist():
+        word = [(0, 3), (1, 3)] + [(q, 0) for q in range(2, 32) if (m >> q) & 1]
+        terms.append((float(rng.integers(-512, 512) or 1) / 1024.0, word))
+    terms += [(0.25, [(5, 6), (7, 5)]), (0.25, [(7, 6), (5, 5)]), (-0.5, [(18, 6), (20, 5), (3, 2)]),
+              (0.75, [(2, 3), (17, 3)]), (0.125, [(4, 0), (21, 0)]), (-1.0, [])]
+    tl = wl.TermList.from_terms(32, terms)
+    say("long group", len(terms), "terms")
+    sub = qsd.Subspace(keys, 32)
+    assert sub.hash_info()[2]
+    op = qsd.operator_from_termlist(tl)
+    gptr, glad = op.export()[4:]
+    big = int(np.argmax(np.diff(gptr)))
+    assert np.diff(gptr)[big] == 70_000 and glad[big] == 0
+    H = qsd.SubspaceHamiltonian(sub, op)
+    ck = osub.canonical_keys(keys)
+    x = dyadic_vector(rng, sub.N)
+    y_o = orw.matvec_c(ck, tl, x).real
+    assert np.count_nonzero(y_o) > sub.N // 2
+    for sched, y in _all_schedules(H, torch.from_numpy(x).cuda()):
+        np.testing.assert_array_equal(y.cpu().numpy(), y_o, err_msg="schedule %d" % sched)
