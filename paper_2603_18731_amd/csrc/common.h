@@ -191,6 +191,10 @@ struct qsd_op {
     std::vector<uint16_t> g_iptr;         // [G-1][kIptr] ladder ranges relative to g_term0
     std::vector<uint64_t> t_cws;          // [To][3][Wp]
     std::vector<double> t_coef;           // [To][2]
+    // strings of at most 32 qubits: at the first term of each ladder range, the qubits of the
+    // range's projector tail (its last terms, one per qubit in increasing order, each wanting
+    // its one qubit beyond the flip mask set); 0 elsewhere
+    std::vector<uint32_t> t_tail;         // [To]
     int64_t max_group_terms = 0;
 };
 

@@ -312,7 +312,10 @@ __device__ __forceinline__ void add_term(const uint64_t (&key)[Wp], const TermRe
 // Sum over the terms [t0, t0 + len), len >= 1, whose projector bits match the row, with
 // popcount-parity signs, in increasing t; `first` holds term t0, already loaded.  The rest are
 // loaded two at a time, both before either is tested.  Returns false when no term matches (no
-// stored entry).
+// stored entry).  NARROW (strings of at most 32 qubits): the range may end in a projector tail,
+// one term per qubit of the mask R that the first term carries, each wanting its qubit set and
+// stored in increasing qubit order; only the tail terms of the qubits the row has set are
+// visited (the others cannot match), so the matching terms are added in the same order.
 template <int Wp, bool NARROW, class ET>
 __device__ __forceinline__ bool range_sum(const HamView &h, const uint64_t (&key)[Wp], uint32_t t0, uint32_t len,
                                           const TermRec<Wp, NARROW, ET> &first, ET &vre, ET &vim) {
@@ -320,7 +323,15 @@ __device__ __forceinline__ bool range_sum(const HamView &h, const uint64_t (&key
     vre = 0;
     vim = 0;
     add_term<Wp, NARROW, ET>(key, first, vre, vim, any);
-    const uint32_t t1 = t0 + len;
+    uint32_t t1 = t0 + len;  // end of the terms visited one by one
+    uint32_t R = 0, m = 0;
+    if constexpr (NARROW) {
+        R = first.m.w;
+        t1 -= (uint32_t)__popc(R);
+        m = (uint32_t)key[0] & R;
+        // a range of tail terms only: its first term (the lowest qubit of R) is summed already
+        if (t1 == t0) m &= ~(R & (0u - R));
+    }
     uint32_t t = t0 + 1u;
     for (; t + 1u < t1; t += 2u) {
         TermRec<Wp, NARROW, ET> a, b;
@@ -333,6 +344,22 @@ __device__ __forceinline__ bool range_sum(const HamView &h, const uint64_t (&key
         TermRec<Wp, NARROW, ET> a;
         load_term<Wp, NARROW, ET>(h, t, a);
         add_term<Wp, NARROW, ET>(key, a, vre, vim, any);
+    }
+    if constexpr (NARROW) {
+        // the tail terms of the row's set qubits, two at a time
+        const uint32_t base = t1;  // the first tail term
+        while (m) {
+            const uint32_t r0 = (uint32_t)__builtin_ctz(m);
+            m &= m - 1u;
+            const bool two = m != 0u;
+            const uint32_t r1 = two ? (uint32_t)__builtin_ctz(m) : r0;
+            m &= two ? m - 1u : m;
+            TermRec<Wp, NARROW, ET> a, b;
+            load_term<Wp, NARROW, ET>(h, base + (uint32_t)__popc(R & ((1u << r0) - 1u)), a);
+            load_term<Wp, NARROW, ET>(h, base + (uint32_t)__popc(R & ((1u << r1) - 1u)), b);
+            add_term<Wp, NARROW, ET>(key, a, vre, vim, any);
+            if (two) add_term<Wp, NARROW, ET>(key, b, vre, vim, any);
+        }
     }
     return any;
 }

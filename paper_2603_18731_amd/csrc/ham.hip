@@ -208,8 +208,10 @@ int create_impl(qsd_ham *h, hipStream_t st) {
         // one-word keys of at most 32 qubits: the term masks fit 32 bits
         const size_t To = op->t_cws.size() / 3;
         cw32.assign(To * 4, 0u);
-        for (size_t t = 0; t < To; ++t)
+        for (size_t t = 0; t < To; ++t) {
             for (int k = 0; k < 3; ++k) cw32[t * 4 + k] = (uint32_t)op->t_cws[t * 3 + k];
+            cw32[t * 4 + 3] = op->t_tail[t];
+        }
         QSD_TRY(upload(&h->t_cw32, cw32, st));
     }
     QSD_TRY(upload(&h->t_coef, op->t_coef, st));

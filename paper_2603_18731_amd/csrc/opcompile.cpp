@@ -463,11 +463,48 @@ extern "C" int qsd_op_compile(int32_t n_qubits, int64_t n_terms, const int64_t *
         std::vector<size_t> ord(j - i);
         std::iota(ord.begin(), ord.end(), 0);
         if (ladder) std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return lint[x] < lint[y]; });
+        // Strings of at most 32 qubits: inside each ladder range, the terms whose only care bit
+        // beyond the flip mask is one qubit r that they want set (a spectator's number operator
+        // after the Jordan-Wigner transform) move behind the others, one per qubit, by r; the
+        // range's first term records those qubits.  A row then visits only the tail terms of the
+        // qubits it has set (the others cannot match), and every row's sum still adds the terms
+        // that match in the order they are stored.
+        std::vector<uint32_t> tail_at(j - i, 0u);  // by position in ord
+        if (ladder && Wp == 1 && n_qubits <= 32) {
+            auto spectator = [&](size_t a) -> int {  // r, or -1
+                const Masks &m = offd[i + a].m;
+                const uint64_t extra = m.care[0] & ~M[0];
+                if (!extra || (extra & (extra - 1)) || !(m.want[0] & extra)) return -1;
+                return __builtin_ctzll(extra);
+            };
+            for (size_t a = 0; a < ord.size();) {
+                size_t b = a;
+                while (b < ord.size() && lint[ord[b]] == lint[ord[a]]) ++b;
+                std::vector<size_t> plain, tail;
+                uint32_t R = 0;
+                for (size_t u = a; u < b; ++u) {
+                    const int r = spectator(ord[u]);
+                    if (r >= 0 && r < 32 && !((R >> r) & 1u)) {
+                        tail.push_back(ord[u]);
+                        R |= 1u << r;
+                    } else {
+                        plain.push_back(ord[u]);
+                    }
+                }
+                std::stable_sort(tail.begin(), tail.end(),
+                                 [&](size_t x, size_t y) { return spectator(x) < spectator(y); });
+                std::copy(plain.begin(), plain.end(), ord.begin() + a);
+                std::copy(tail.begin(), tail.end(), ord.begin() + a + plain.size());
+                tail_at[a] = R;
+                a = b;
+            }
+        }
 
         uint32_t term0 = (uint32_t)(op->t_coef.size() / 2);
         bool care = false;
         for (size_t r = 0; r < ord.size(); ++r) {
             const Item &it = offd[i + ord[r]];
+            op->t_tail.push_back(tail_at[r]);
             op->terms.push_back(comb[it.idx]);
             push_cws(op->t_cws, it.m);
             push_coef(op->t_coef, comb[it.idx].c, it.m.ny);
