@@ -228,9 +228,9 @@ __device__ __forceinline__ uint32_t term_parity(const uint64_t (&k)[Wp], const u
 }
 
 // Sum over the terms [t0, t0 + len) that match the row's projector bits, with popcount-parity
-// signs, in increasing t; wide keys: the care and want masks are read first, the sign mask and
-// the coefficient only for a matching term.  Returns false when no term matches (no stored
-// entry).
+// signs, in increasing t (the table kernels' walk): the care and want masks are read first, the
+// sign mask and the coefficient only for a matching term.  Returns false when no term matches
+// (no stored entry).
 template <int Wp, class ET>
 __device__ __forceinline__ bool range_value(const HamView &h, const uint64_t (&key)[Wp], uint32_t t0, uint32_t len,
                                             ET &vre, ET &vim) {
@@ -239,9 +239,9 @@ __device__ __forceinline__ bool range_value(const HamView &h, const uint64_t (&k
     bool any = false;
     vre = 0;
     vim = 0;
-    for (uint32_t t = t0; t < t0 + len; ++t) {
+    auto term = [&](uint32_t t) {
         const uint64_t *cws = h.t_cws + (int64_t)t * 3 * Wp;
-        if (!term_pass<Wp>(key, cws)) continue;
+        if (!term_pass<Wp>(key, cws)) return;
         any = true;
         const CT c = coef[t];
         if (term_parity<Wp>(key, cws)) {
@@ -251,7 +251,17 @@ __device__ __forceinline__ bool range_value(const HamView &h, const uint64_t (&k
             vre += c.x;
             vim += c.y;
         }
+    };
+    // strings of at most 32 qubits: a projector tail (see range_sum) is visited only at the
+    // qubits the row has set
+    uint32_t t1 = t0 + len, R = 0, m = 0;
+    if (Wp == 1 && h.t_cw32) {
+        R = h.t_cw32[t0].w;
+        t1 -= (uint32_t)__popc(R);
+        m = (uint32_t)key[0] & R;
     }
+    for (uint32_t t = t0; t < t1; ++t) term(t);
+    for (; m; m &= m - 1u) term(t1 + (uint32_t)__popc(R & ((1u << __builtin_ctz(m)) - 1u)));
     return any;
 }
 
