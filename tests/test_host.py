@@ -262,3 +262,63 @@ def test_host_core_under_sanitizers(tmp_path):
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
     assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr, r.stderr[-4000:]
     assert r.stdout.strip().endswith("host core clean")
+
+
+def test_projector_tails_layout():
+    """Inside every ladder range of the compiled molecular operator, the terms whose only letter
+    beyond the flipped qubits (and Z signs) is one '1' projector come last, one per qubit, in
+    increasing qubit order: the layout that lets a row visit only the tail terms of its set
+    qubits.  The compiled operator is still the input operator (dense check on 4 orbitals)."""
+    _lib_or_skip()
+    for norb in (4, 8):
+        h, eri = wl.molecular_integrals(norb, seed=3)
+        tl = wl.molecular_terms(h, eri)
+        op = qsd.FermionicOperator.from_termlist(tl)
+        terms, gp, gl = _export_terms(op)
+        tails = 0
+        for g in range(1, len(gp) - 1):
+            if not gl[g]:
+                continue
+            flip = sorted({q for t in range(gp[g], gp[g + 1]) for q, k in terms[t][1] if k in (5, 6)})
+
+            def lint(t):
+                w = dict(terms[t][1])
+                return sum(1 << i for i, q in enumerate(flip) if w[q] == 6)
+
+            def spectator(t):
+                rest = [(q, k) for q, k in terms[t][1] if q not in flip and k != 0]
+                return rest[0][0] if len(rest) == 1 and rest[0][1] == 2 else None
+
+            t = gp[g]
+            while t < gp[g + 1]:
+                u = t
+                while u < gp[g + 1] and lint(u) == lint(t):
+                    u += 1
+                qs = [spectator(v) for v in range(t, u)]
+                first = next((i for i, q in enumerate(qs) if q is not None), len(qs))
+                tail = qs[first:]
+                assert None not in tail, (g, qs)
+                assert tail == sorted(set(tail)), (g, qs)
+                tails += len(tail)
+                t = u
+        assert tails > 0
+        if norb == 4:
+            A = ofe.dense_hamiltonian(2 * norb, list(tl.terms())).toarray()
+            B = ode.qubit_hamiltonian(2 * norb, terms).toarray()
+            np.testing.assert_allclose(B, A, atol=1e-12)
+    # a qubit operator whose terms arrive with the spectators first and out of order, beside a
+    # plain term with a high Z and a term wanting a qubit clear (which stays in front)
+    ws = [[(5, 2), (1, 5), (0, 6)], [(1, 5), (0, 6), (6, 0)], [(3, 2), (0, 6), (1, 5)], [(0, 6), (1, 5), (2, 1)],
+          [(2, 2), (1, 5), (0, 6), (4, 0)], [(0, 5), (1, 6), (5, 2)], [(0, 5), (1, 6)]]
+    tl = wl.TermList.from_terms(8, [(0.5 + 0.125 * i, w) for i, w in enumerate(ws)])
+    op = qsd.QubitOperator.from_termlist(tl)
+    terms, gp, gl = _export_terms(op)
+    assert len(gp) == 3 and gl[1]
+    words = [sorted(w) for _, w in terms[gp[1]:gp[2]]]
+    assert words[:2] in ([[(0, 6), (1, 5), (2, 1)], [(0, 6), (1, 5), (6, 0)]],
+                         [[(0, 6), (1, 5), (6, 0)], [(0, 6), (1, 5), (2, 1)]])
+    assert words[2:5] == [[(0, 6), (1, 5), (2, 2), (4, 0)], [(0, 6), (1, 5), (3, 2)], [(0, 6), (1, 5), (5, 2)]]
+    assert words[5:] == [[(0, 5), (1, 6)], [(0, 5), (1, 6), (5, 2)]]
+    A = ode.qubit_hamiltonian(8, list(tl.terms())).toarray()
+    B = ode.qubit_hamiltonian(8, terms).toarray()
+    np.testing.assert_allclose(B, A, atol=1e-12)
