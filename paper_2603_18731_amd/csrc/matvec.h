@@ -28,12 +28,12 @@ __device__ __forceinline__ int64_t tile_index(unsigned b, unsigned G, bool remap
 }
 
 // Loads the lane's row: position `row0 + lane` of the canonical order, or of the slot order
-// with `by_slot` (clamped to a valid row for lanes past the end).
+// with `by_slot` (clamped to a valid row for lanes past the end, or past `row_end` when given).
 template <int Wp>
 __device__ __forceinline__ int64_t load_row(const SubView &s, int64_t row0, uint64_t (&key)[Wp], uint64_t &hrow,
-                                            uint32_t &prow, bool &valid, bool by_slot = false) {
+                                            uint32_t &prow, bool &valid, bool by_slot = false, int64_t row_end = -1) {
     const int64_t i = row0 + threadIdx.x;
-    valid = i < s.N;
+    valid = i < (row_end < 0 ? s.N : row_end);
     const int64_t p = valid ? i : s.N - 1;
     if (by_slot) {
 #pragma unroll
@@ -99,11 +99,11 @@ __device__ __forceinline__ void matvec_block(const SubView &s, const HamView &h,
                                              const ET *__restrict__ dim, const ET *__restrict__ x, int64_t ldx,
                                              ET *__restrict__ y, int64_t ldy, int nvec, int64_t row0,
                                              ChunkLds<Wp> &lds, bool by_slot = false, bool lockstep = false,
-                                             bool filter_first = false, bool split = false) {
+                                             bool filter_first = false, bool split = false, int64_t row_end = -1) {
     uint64_t key[Wp], hrow;
     uint32_t prow;
     bool valid;
-    const int64_t r = load_row<Wp>(s, row0, key, hrow, prow, valid, by_slot);
+    const int64_t r = load_row<Wp>(s, row0, key, hrow, prow, valid, by_slot, row_end);
     double acc_re[NV], acc_im[NV];
     bool have = !split;  // acc holds d_r x[r] (+ the elements so far)
 #pragma unroll

@@ -67,12 +67,14 @@ ORDERS = {"parts": {}, "weight": {"order_by_parts": False}, "mask": {"order_by_m
 
 
 @pytest.mark.parametrize("na,nb,order", [(37, 29, "parts"), (70, 70, "parts"), (70, 70, "weight"), (70, 70, "mask"),
-                                         (128, 3, "parts"), (1, 200, "parts"), (300, 1, "weight")])
+                                         (128, 3, "parts"), (1, 200, "parts"), (300, 1, "weight"),
+                                         (600, 7, "parts"), (513, 3, "weight")])
 def test_product_matvec_exact(na, nb, order):
     """Dyadic coefficients and vectors: every schedule, with the map and through the table,
     under each group order, equals the oracle bit for bit (one vector, three interleaved
     vectors, and FP32 elements and vectors with FP64 accumulation, whose result is the exact
-    value rounded once)."""
+    value rounded once).  With 512 or more alpha strings the map kernel's tiles follow the
+    product's blocks of rows (600 = 2 x 256 + 88, 513 = 2 x 256 + 1)."""
     ops, keys = c3_parts(na, nb) if na > 1 and nb > 1 else (None, None)
     if ops is None:
         w = wl.c3_molecular(na, nb)
