@@ -55,6 +55,20 @@ __device__ __forceinline__ double wsum(double v) {
     return v;
 }
 
+// Row tiles of a request on a product subspace whose low-part count pna spans two or more tiles
+// (and not in slot order): tile k of high part b takes rows b pna + 256 k .. (b + 1) pna, so its
+// rows share their high part, as in qsd_matvec.  pm_tiles = how many (0: plain 256-row tiles).
+__host__ __device__ inline int64_t pm_tiles(int64_t N, uint32_t pna, uint32_t sched) {
+    if (pna < 2u * kBlock || (sched & QSD_SCHED_SLOT_ORDER)) return 0;
+    return N / pna * ((pna + kBlock - 1) / kBlock);
+}
+__device__ __forceinline__ void pm_tile(uint32_t pna, uint32_t sched, int idx, int64_t &row0, int64_t &row_end) {
+    if (pna < 2u * kBlock || (sched & QSD_SCHED_SLOT_ORDER)) return;
+    const int64_t tpb = (pna + kBlock - 1) / kBlock, b = idx / tpb;
+    row0 = b * (int64_t)pna + (idx - b * tpb) * kBlock;
+    row_end = (b + 1) * (int64_t)pna;
+}
+
 // PF = 2: the tiles of matrix-free requests on product subspaces (product map); else PF = 1.
 template <int Wp, class ET, int PF = 1>
 __global__ __launch_bounds__(kBlock) void kb_matvec(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles) {
@@ -98,9 +112,11 @@ __global__ __launch_bounds__(kBlock) void kb_matvec(const ReqDev *__restrict__ r
         return;
     }
     // the operator's schedule, with the diagonal term formed in the row kernel (no separate pass)
-    matvec_block<Wp, 1, ET, false, PF>(R.s, R.h, dre, nullptr, x, 1, y, 1, 1, (int64_t)t.idx * kBlock, lds,
+    int64_t row0 = (int64_t)t.idx * kBlock, row_end = -1;
+    if constexpr (PF == 2) pm_tile(R.s.pna, R.sched, t.idx, row0, row_end);
+    matvec_block<Wp, 1, ET, false, PF>(R.s, R.h, dre, nullptr, x, 1, y, 1, 1, row0, lds,
                                        (R.sched & QSD_SCHED_SLOT_ORDER) != 0, (R.sched & QSD_SCHED_LOCKSTEP) != 0,
-                                       (R.sched & QSD_SCHED_FILTER_FIRST) != 0);
+                                       (R.sched & QSD_SCHED_FILTER_FIRST) != 0, false, row_end);
 }
 
 // x32 = x (to_f32) or w = w32 (back), over 2048-row tiles
@@ -389,6 +405,11 @@ struct qsd_batch {
     int n_mv = 0, n_bl = 0;
     int n_mv_pm = 0;  // the first n_mv_pm row tiles belong to requests that take the product map
     size_t cap_mv = 0, cap_bl = 0;
+    // the product-map SpMV's tiles (pm_tile: within the product's blocks of rows where a block
+    // spans two or more tiles, else the 256-row tiles)
+    Tile *d_pmt = nullptr;
+    int n_pmt = 0;
+    size_t cap_pmt = 0;
     double *d_out = nullptr;  // [max_slots][4]
     int64_t *d_spike = nullptr;
     bool dirty = true;
@@ -437,7 +458,7 @@ int sync_tables(qsd_batch *b, hipStream_t st) {
     if (!b->dirty) return QSD_OK;
     AllocScope scope(&b->alloc, st);
     std::vector<ReqDev> host(b->max_slots);
-    std::vector<Tile> mv, mvo, bl;
+    std::vector<Tile> mv, mvo, bl, pmt;
     for (int i = 0; i < b->max_slots; ++i) {
         const auto &S = b->slots[i];
         if (!S.used) {
@@ -450,6 +471,10 @@ int sync_tables(qsd_batch *b, hipStream_t st) {
         // kernel), then the others; no kernel depends on the order of the tiles
         const bool pm = b->Wp == 1 && !S.d.cptr && S.d.s.prank && !(S.d.sched & QSD_SCHED_HASH_LOOKUP);
         for (int64_t t = 0; t < (S.d.N + kBlock - 1) / kBlock; ++t) (pm ? mv : mvo).push_back({i, (int)t});
+        if (pm) {
+            const int64_t n = pm_tiles(S.d.N, S.d.s.pna, S.d.sched);
+            for (int64_t t = 0; t < (n ? n : (S.d.N + kBlock - 1) / kBlock); ++t) pmt.push_back({i, (int)t});
+        }
         for (int t = 0; t < S.d.nbt; ++t) bl.push_back({i, t});
     }
     const int n_pm = (int)mv.size();
@@ -464,13 +489,21 @@ int sync_tables(qsd_batch *b, hipStream_t st) {
         b->cap_bl = bl.size() * 2;
         QSD_TRY(dev_alloc(&b->d_bl, b->cap_bl));
     }
+    if (pmt.size() > b->cap_pmt) {
+        dev_free(b->d_pmt);
+        b->cap_pmt = pmt.size() * 2;
+        QSD_TRY(dev_alloc(&b->d_pmt, b->cap_pmt));
+    }
     QSD_CHECK_HIP(hipMemcpyAsync(b->d_reqs, host.data(), host.size() * sizeof(ReqDev), hipMemcpyHostToDevice, st));
     if (!mv.empty()) QSD_CHECK_HIP(hipMemcpyAsync(b->d_mv, mv.data(), mv.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
     if (!bl.empty()) QSD_CHECK_HIP(hipMemcpyAsync(b->d_bl, bl.data(), bl.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
+    if (!pmt.empty())
+        QSD_CHECK_HIP(hipMemcpyAsync(b->d_pmt, pmt.data(), pmt.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
     // the host vectors are staged by the runtime before the calls return (pageable copies)
     QSD_CHECK_HIP(hipStreamSynchronize(st));
     b->n_mv = (int)mv.size();
     b->n_mv_pm = n_pm;
+    b->n_pmt = (int)pmt.size();
     b->n_bl = (int)bl.size();
     b->dirty = false;
     return QSD_OK;
@@ -482,9 +515,9 @@ void launch_bmv(qsd_batch *b, hipStream_t st) {
     const int np = Wp == 1 ? b->n_mv_pm : 0, no = b->n_mv - np;
     if (np > 0) {
         if (b->f32)
-            kb_matvec<1, float, 2><<<np, kBlock, 0, st>>>(b->d_reqs, b->d_mv);
+            kb_matvec<1, float, 2><<<b->n_pmt, kBlock, 0, st>>>(b->d_reqs, b->d_pmt);
         else
-            kb_matvec<1, double, 2><<<np, kBlock, 0, st>>>(b->d_reqs, b->d_mv);
+            kb_matvec<1, double, 2><<<b->n_pmt, kBlock, 0, st>>>(b->d_reqs, b->d_pmt);
     }
     if (no > 0) {
         if (b->f32)
@@ -757,6 +790,7 @@ extern "C" int qsd_batch_destroy(qsd_batch *b) {
     dev_free(b->d_reqs);
     dev_free(b->d_mv);
     dev_free(b->d_bl);
+    dev_free(b->d_pmt);
     dev_free(b->d_out);
     dev_free(b->d_spike);
     delete b;

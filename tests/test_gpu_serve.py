@@ -43,11 +43,14 @@ def _ham(keys, tl):
 def hams():
     c1 = wl.c1_tfim12()
     ops3, keys3 = c3_parts(40, 40)
+    opsw, keysw = c3_parts(600, 4)
     return {
         "tfim12": _ham(c1.keys, c1.ops),
         "xxz20k": _ham(c2_keys(20_000), wl.xxz_grid_6x6()),
         "fermi1600": _ham(keys3, ops3),
         "xxz3k": _ham(c2_keys(3_000), wl.xxz_grid_6x6()),
+        # 600 alpha strings: the product-map tiles follow the product's blocks of rows
+        "fermi2400": _ham(keysw, opsw),
     }
 
 
@@ -55,7 +58,9 @@ def hams():
 def oracle_energies():
     out = {"tfim12": -2.0 / math.sin(math.pi / 24)}
     ops3, keys3 = c3_parts(40, 40)
-    for name, keys, tl in (("xxz20k", c2_keys(20_000), wl.xxz_grid_6x6()), ("fermi1600", keys3, ops3)):
+    opsw, keysw = c3_parts(600, 4)
+    for name, keys, tl in (("xxz20k", c2_keys(20_000), wl.xxz_grid_6x6()), ("fermi1600", keys3, ops3),
+                           ("fermi2400", keysw, opsw)):
         A = orw.csr_c(osub.canonical_keys(keys), tl).real.tocsr()
         e, _, _ = olz.lanczos_ground(lambda v, A=A: A @ v, A.shape[0], tol=1e-13, max_iter=800)
         out[name] = e
@@ -155,7 +160,7 @@ def test_matvec_batched_complex():
 
 def test_batch_energies(hams, oracle_energies):
     b = qsd.LanczosBatch(8, max_iter=300)
-    slots = {name: b.add(hams[name], tol=1e-10) for name in ("tfim12", "xxz20k", "fermi1600")}
+    slots = {name: b.add(hams[name], tol=1e-10) for name in ("tfim12", "xxz20k", "fermi1600", "fermi2400")}
     say("batch energies", slots)
     st, e, it, rr = _run_to_end(b)
     for name, s in slots.items():
@@ -167,11 +172,12 @@ def test_batch_energies(hams, oracle_energies):
         assert abs(e[s] - e_single) / abs(e_single) < 1e-10
 
 
-@pytest.mark.parametrize("spmv_dtype", ["f64", "f32"])
-def test_alone_vs_mix_bitwise(hams, spmv_dtype):
+@pytest.mark.parametrize("spmv_dtype,name", [("f64", "fermi1600"), ("f32", "fermi1600"), ("f64", "fermi2400")])
+def test_alone_vs_mix_bitwise(hams, spmv_dtype, name):
     """Request A takes 30 iterations alone, and 30 in a batch where B runs from the start and
-    C joins after 10 iterations and B leaves after 20: A's results are bitwise the same."""
-    A = hams["fermi1600"]
+    C joins after 10 iterations and B leaves after 20: A's results are bitwise the same (also
+    for a product subspace whose tiles follow its blocks of rows)."""
+    A = hams[name]
     alone = qsd.LanczosBatch(4, max_iter=200, spmv_dtype=spmv_dtype)
     sa = alone.add(A, v0="random", seed=11)
     alone.step(30)
