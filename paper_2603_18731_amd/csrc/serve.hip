@@ -373,9 +373,12 @@ __global__ __launch_bounds__(kBlock) void kbm_matvec(const MvReq *__restrict__ r
     __shared__ ChunkLds<Wp> lds;
     const Tile t = tiles[blockIdx.x];
     const MvReq &R = reqs[t.slot];
+    int64_t row0 = (int64_t)t.idx * kBlock, row_end = -1;
+    if constexpr (PF == 2) pm_tile(R.s.pna, R.sched, t.idx, row0, row_end);
     matvec_block<Wp, NV, ET, CPLX, PF>(R.s, R.h, (const ET *)R.dre, (const ET *)R.dim, (const ET *)R.x, R.ld, (ET *)R.y,
-                                   R.ld, R.nv, (int64_t)t.idx * kBlock, lds, (R.sched & QSD_SCHED_SLOT_ORDER) != 0,
-                                   (R.sched & QSD_SCHED_LOCKSTEP) != 0, (R.sched & QSD_SCHED_FILTER_FIRST) != 0);
+                                   R.ld, R.nv, row0, lds, (R.sched & QSD_SCHED_SLOT_ORDER) != 0,
+                                   (R.sched & QSD_SCHED_LOCKSTEP) != 0, (R.sched & QSD_SCHED_FILTER_FIRST) != 0, false,
+                                   row_end);
 }
 
 }  // namespace
@@ -879,7 +882,9 @@ int plan_batched(int32_t n, const qsd_ham *const *hams, const void *const *xs, v
                 L.nv_max = std::max(L.nv_max, R.nv);
                 const int slot = (int)P.reqs.size();
                 P.reqs.push_back(R);
-                for (int64_t t = 0; t < (h->N + kBlock - 1) / kBlock; ++t) P.tiles.push_back({slot, (int)t});
+                // product-map requests: tiles within the product's blocks of rows (see pm_tile)
+                const int64_t nb = L.pm ? pm_tiles(h->N, h->s->pna, h->schedule) : 0;
+                for (int64_t t = 0; t < (nb ? nb : (h->N + kBlock - 1) / kBlock); ++t) P.tiles.push_back({slot, (int)t});
             }
             L.nt = P.tiles.size() - L.t0;
             if (L.nt > 0) P.launches.push_back(L);

@@ -84,8 +84,8 @@ def test_matvec_batched_bitwise(hams, dtype):
     rng = np.random.default_rng(7)
     hh, ops_hex_keys = heavy_hex_small(4_000)
     H4 = _ham(ops_hex_keys, hh)  # four key words: a second launch
-    hs = [hams["tfim12"], hams["xxz20k"], H4, hams["fermi1600"], hams["xxz3k"]]
-    nvecs = [1, 3, 8, 16, 2]
+    hs = [hams["tfim12"], hams["xxz20k"], H4, hams["fermi1600"], hams["xxz3k"], hams["fermi2400"]]
+    nvecs = [1, 3, 8, 16, 2, 4]
     xs = []
     for h, nv in zip(hs, nvecs):
         x = rng.standard_normal((h.N, nv)) if nv > 1 else rng.standard_normal(h.N)

@@ -34,6 +34,7 @@ def _ham(keys, tl):
 def hams():
     c1 = wl.c1_tfim12()
     ops3, keys3 = c3_parts(40, 40)
+    opsw, keysw = c3_parts(600, 4)
     hh, hex_keys = heavy_hex_small(4_000)
     return {
         "tfim12": _ham(c1.keys, c1.ops),
@@ -41,6 +42,7 @@ def hams():
         "hex4k": _ham(hex_keys, hh),  # four key words: a launch of its own
         "fermi1600": _ham(keys3, ops3),
         "xxz3k": _ham(c2_keys(3_000), wl.xxz_grid_6x6()),
+        "fermi2400": _ham(keysw, opsw),  # product tiles within its blocks of rows
     }
 
 
@@ -56,7 +58,7 @@ def _vectors(rng, hs, nvecs, dtype):
 def test_noalloc_equals_batched_on_consecutive_calls(hams, dtype):
     rng = np.random.default_rng(21)
     calls = [
-        (["tfim12", "xxz20k", "hex4k", "fermi1600", "xxz3k"], [1, 3, 8, 16, 2]),
+        (["tfim12", "xxz20k", "hex4k", "fermi1600", "xxz3k", "fermi2400"], [1, 3, 8, 16, 2, 1]),
         (["xxz3k", "tfim12"], [2, 1]),  # smaller: fewer requests, tiles and launches
     ]
     for names, nvecs in calls:
