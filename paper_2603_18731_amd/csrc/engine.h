@@ -45,7 +45,7 @@ constexpr int kLockBatch = 4;   // groups in flight per wave in lockstep mode
 constexpr int kOccBatch = 8;    // occupancy-bit loads in flight per lane (filter-first mode)
 constexpr int kSlotBatch = 4;   // slot loads in flight per lane (filter-first mode)
 constexpr int kSlotBatchPM = 2; // hits per batch in filter-first mode with the product map
-constexpr int kOccBatchPM = 2;  // filter tests per batch in filter-first mode with the product map
+constexpr int kOccBatchPM = 1;  // filter tests per batch in filter-first mode with the product map
 
 // One- and two-word keys copy the part filters into LDS; wider keys read them from memory.
 template <int Wp>
